@@ -1,0 +1,240 @@
+"""Plain FP64 CPU oracle of the NNCA H2 matrix-vector product.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only callers.  The GPU library and
+its Python binding never import this package.
+
+The arithmetic lives in ``nnca_oracle.c`` (plain C, FP64, compiled with
+``-ffp-contract=off``); this module only builds it with gcc and marshals numpy
+arrays through ctypes.  Each function of the C file cites the section of the
+paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nnca_oracle.c")
+_LIB = os.path.join(_HERE, "libnnca_oracle.so")
+
+KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "poly2": 99}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64, i32, f64 = C.c_int64, C.c_int, C.c_double
+        L.orc_log.restype = f64; L.orc_log.argtypes = [f64]
+        L.orc_exp.restype = f64; L.orc_exp.argtypes = [f64]
+        L.orc_kernel_eval.restype = f64
+        L.orc_kernel_eval.argtypes = [i32, f64, P, P, i32]
+        L.orc_direct.restype = None
+        L.orc_direct.argtypes = [P, i64, i32, i32, f64, P, i64, P, i64, P]
+        L.orc_tree_build.restype = P
+        L.orc_tree_build.argtypes = [P, i64, i32, i32, i64, i64]
+        L.orc_tree_free.argtypes = [P]
+        L.orc_tree_kappa.restype = i32; L.orc_tree_kappa.argtypes = [P]
+        L.orc_tree_ncell.restype = i64; L.orc_tree_ncell.argtypes = [P, i32]
+        L.orc_tree_domain.argtypes = [P, P, P]
+        L.orc_tree_order.argtypes = [P, P]
+        L.orc_tree_cells.argtypes = [P, i32, P, P, P, P, P]
+        L.orc_tree_lists.restype = i64; L.orc_tree_lists.argtypes = [P, i32, i32, P, P]
+        L.orc_aca_block.restype = i64
+        L.orc_aca_block.argtypes = [P, i64, P, i64, i32, i32, f64, f64, P, P, P, P, P]
+        L.orc_h2_new.restype = P; L.orc_h2_new.argtypes = [P, i32, f64, f64, i32]
+        L.orc_h2_lmin.restype = i32; L.orc_h2_lmin.argtypes = [P]
+        L.orc_h2_build.restype = i32; L.orc_h2_build.argtypes = [P, i32, P, i64]
+        L.orc_h2_free.argtypes = [P]
+        L.orc_h2_cell.restype = i32; L.orc_h2_cell.argtypes = [P, i32, i64, P, P, P, P, P]
+        L.orc_h2_matvec.argtypes = [P, P, P, i64, i32]
+        L.orc_h2_interactions.argtypes = [P, P]
+        L.orc_num_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def log(x: float) -> float:
+    return lib().orc_log(float(x))
+
+
+def exp(x: float) -> float:
+    return lib().orc_exp(float(x))
+
+
+def kernel_eval(kind: str, a, b, h: float = 1.0) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    return lib().orc_kernel_eval(KINDS[kind], float(h), _p(a), _p(b), a.shape[0])
+
+
+def direct(points, x, kind: str, h: float = 1.0, rows=None) -> np.ndarray:
+    """Dense sum y_i = sum_j K(p_i, p_j) x_j (compensated, FP64).
+
+    ``points`` is (n, d); ``x`` is (n,) or (n, r).  ``rows`` restricts the
+    output to the listed target indices."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, d = pts.shape
+    x = np.asarray(x, dtype=np.float64)
+    vec = x.ndim == 1
+    X = np.ascontiguousarray(x.reshape(n, -1).T)  # column-major columns
+    nrhs = X.shape[0]
+    if rows is None:
+        r = None
+        nr = n
+    else:
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        nr = r.shape[0]
+    Y = np.zeros((nrhs, nr))
+    lib().orc_direct(_p(pts), n, d, KINDS[kind], float(h), _p(X), nrhs, _p(r), nr, _p(Y))
+    return Y[0] if vec else Y.T.copy()
+
+
+def aca_block(prow, pcol, kind: str, tol: float, h: float = 1.0):
+    """ACA of the block K(prow, pcol); returns (rowpos, colpos, U, V, C)."""
+    pr = np.ascontiguousarray(prow, dtype=np.float64)
+    pc = np.ascontiguousarray(pcol, dtype=np.float64)
+    m, d = pr.shape
+    n = pc.shape[0]
+    kcap = min(m, n)
+    rp = np.zeros(max(kcap, 1), np.int64)
+    cp = np.zeros(max(kcap, 1), np.int64)
+    U = np.zeros((max(kcap, 1), m))
+    V = np.zeros((max(kcap, 1), n))
+    Cm = np.zeros(max(m * kcap, 1))
+    k = lib().orc_aca_block(_p(pr), m, _p(pc), n, d, KINDS[kind], float(h), float(tol),
+                            _p(rp), _p(cp), _p(U), _p(V), _p(Cm))
+    return rp[:k].copy(), cp[:k].copy(), U[:k].T.copy(), V[:k].copy(), Cm[: m * k].reshape(m, k).copy()
+
+
+class Tree:
+    """Uniform 2^d tree with neighbour and interaction lists (Sec. 2.1-2.2)."""
+
+    def __init__(self, points, leaf_size: int, eta2=None):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        self.n, self.d = pts.shape
+        if eta2 is None:
+            eta2 = (self.d, 1)
+        num, den = eta2
+        self._h = lib().orc_tree_build(_p(pts), self.n, self.d, int(leaf_size), int(num), int(den))
+        if not self._h:
+            raise ValueError("oracle tree build rejected its arguments")
+        self.kappa = lib().orc_tree_kappa(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_tree_free(self._h)
+            self._h = None
+
+    def domain(self):
+        lo = np.zeros(3)
+        L = np.zeros(1)
+        lib().orc_tree_domain(self._h, _p(lo), _p(L))
+        return lo[: self.d], float(L[0])
+
+    def order(self):
+        o = np.zeros(self.n, np.int64)
+        lib().orc_tree_order(self._h, _p(o))
+        return o
+
+    def ncell(self, l: int) -> int:
+        return int(lib().orc_tree_ncell(self._h, l))
+
+    def cells(self, l: int):
+        nc = self.ncell(l)
+        key = np.zeros(nc, np.uint64)
+        coord = np.zeros((nc, self.d), np.int64)
+        first = np.zeros(nc, np.int64)
+        count = np.zeros(nc, np.int64)
+        parent = np.zeros(nc, np.int64)
+        lib().orc_tree_cells(self._h, l, _p(key), _p(coord), _p(first), _p(count), _p(parent))
+        return dict(key=key, coord=coord, first=first, count=count, parent=parent)
+
+    def lists(self, l: int, which: str):
+        w = 1 if which == "il" else 0
+        tot = lib().orc_tree_lists(self._h, l, w, None, None)
+        ptr = np.zeros(self.ncell(l) + 1, np.int64)
+        idx = np.zeros(max(tot, 1), np.int64)
+        lib().orc_tree_lists(self._h, l, w, _p(ptr), _p(idx))
+        return ptr, idx[:tot]
+
+
+class H2:
+    """NNCA pivots, transfer operators and the H2 matvec (Sec. 2.3-4)."""
+
+    def __init__(self, tree: Tree, kind: str, tol: float, h: float = 1.0, policy: int = 1,
+                 build: bool = True):
+        self.tree = tree
+        self.kind = kind
+        self._h = lib().orc_h2_new(tree._h, KINDS[kind], float(h), float(tol), int(policy))
+        self.lmin = lib().orc_h2_lmin(self._h)
+        if build:
+            self.build()
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_h2_free(self._h)
+            self._h = None
+
+    def build(self, level: int | None = None, cells=None):
+        if level is None:
+            lib().orc_h2_build(self._h, 0, None, -1)
+        else:
+            c = np.ascontiguousarray(cells, dtype=np.int64)
+            lib().orc_h2_build(self._h, int(level), _p(c), c.shape[0])
+
+    def cell(self, l: int, b: int):
+        mnk = np.zeros(4, np.int64)
+        if lib().orc_h2_cell(self._h, l, b, _p(mnk), None, None, None, None) != 0:
+            raise KeyError((l, b))
+        m, n, k, pt = (int(v) for v in mnk)
+        piv = np.zeros(max(k, 1), np.int64)
+        col = np.zeros(max(k, 1), np.int64)
+        tt = np.zeros(max(m, 1), np.int64)
+        Cm = np.zeros(max(m * k, 1))
+        lib().orc_h2_cell(self._h, l, b, None, _p(piv), _p(col), _p(tt), _p(Cm))
+        return dict(m=m, n=n, k=k, passthrough=bool(pt), piv=piv[:k].copy(),
+                    colpts=None if pt else col[:k].copy(), tt=tt[:m].copy(),
+                    C=Cm[: m * k].reshape(m, k).copy())
+
+    def matvec(self, x, adjoint: bool = False) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        n = self.tree.n
+        vec = x.ndim == 1
+        X = np.ascontiguousarray(x.reshape(n, -1).T)
+        Y = np.zeros_like(X)
+        lib().orc_h2_matvec(self._h, _p(X), _p(Y), X.shape[0], int(adjoint))
+        return Y[0] if vec else Y.T.copy()
+
+    def interactions(self):
+        out = np.zeros(2, np.int64)
+        lib().orc_h2_interactions(self._h, _p(out))
+        return int(out[0]), int(out[1])
