@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Throughput of the NNCA H2 matvec on one MI355X.
+
+Workload: 3D 1/|x-y| (zero on the diagonal), N = 2^20 points uniform in
+[-1,1]^3, leaf <= 64, ACA tolerance 1e-6, one right-hand side x ~ N(0,1)
+(seeded, synthetic).  A step is one mixed-precision matvec y = A~ x through
+the whole apply path (gather/split, P2M/M2M, M2L, L2L/L2P, near field and
+FP64 combine) with the H2 representation resident in HBM; the FP64 GPU build
+(tree, ACA pivots, transfer operators) is timed separately.
+
+Prints one JSON line.  The per-launch durations of the dominant kernel (M2L)
+come from HIP events the library records on its launch stream during the
+timed steps.  The CPU baseline is the plain FP64 oracle timed on a smaller
+sample of the same distribution and scaled by interaction count.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H2 matvecs/s at N=1M 3D 1/r, mixed vs FP64 at rel.err≤1e-6; % roofline"
+# Roofline of the dominant kernel (M2L, FP32 1/r): an interaction is
+# 3 subtractions + 1 multiply + 2 FMA (squared distance) + 1 v_rsq_f32
+# (quarter rate: 4 issue slots) + 1 FMA = 11 VALU issue slots per lane.
+# Non-packed FP32 VALU issue: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
+VALU_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
+SLOTS_PER_INTERACTION = 11.0
+PEAK_INTERACTIONS = VALU_LANE_SLOTS / SLOTS_PER_INTERACTION
+
+
+def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3):
+    """Oracle (plain FP64 C, OpenMP over cells) on a sample of the workload."""
+    import oracle
+    from paper_2203_14832_amd.workloads import workload
+    p, x = workload("c2", n=sample_n)
+    T = oracle.Tree(p, 64)
+    H = oracle.H2(T, "inv_r", 1e-6)
+    H.matvec(x[:, 0])
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        H.matvec(x[:, 0])
+    dt = (time.perf_counter() - t0) / reps
+    far, near = H.interactions()
+    rate = (far + near) / dt
+    return {
+        "value": rate / n_full_inter, "unit": "matvecs/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": f"oracle FP64 matvec on N={sample_n} points of the same distribution (leaf 64, tol 1e-6), "
+                  f"{reps} timed matvecs, {far + near} interactions each, scaled by interaction count to "
+                  f"the N=2^20 problem ({n_full_inter} interactions)",
+        "sample_seconds_per_matvec": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import workload
+
+    dev = torch.device("cuda:0")
+    p, x = workload("c2", n=args.n)
+    n = p.shape[0]
+    t0 = time.perf_counter()
+    H = nnca.H2Matrix(p, "inv_r", 1e-6, 64, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = H.info()
+    inter = info["m2l_interactions"] + info["p2p_interactions"]
+    print(f"[bench] built N={n} kappa={info['kappa']} in {build_s:.2f}s, "
+          f"M2L {info['m2l_interactions']:.3e} + P2P {info['p2p_interactions']:.3e} interactions",
+          file=sys.stderr, flush=True)
+
+    X = torch.tensor(x[:, 0], device=dev).reshape(1, n).contiguous()
+    Ym = torch.empty_like(X)
+    Y64 = torch.empty_like(X)
+
+    def run(prec, Y, k):
+        for _ in range(k):
+            H.matvec_raw(X, Y, 1, prec)
+
+    # FP64 matvec (reference arithmetic on the same pivots)
+    run("fp64", Y64, 2)
+    torch.cuda.synchronize()
+    k64 = max(3, args.steps // 4)
+    t0 = time.perf_counter()
+    run("fp64", Y64, k64)
+    torch.cuda.synchronize()
+    fp64_ms = (time.perf_counter() - t0) / k64 * 1e3
+
+    # timed mixed-precision steps, with per-launch events on the library stream
+    run("mixed", Ym, args.warmup)
+    torch.cuda.synchronize()
+    H.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run("mixed", Ym, args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    passes, levels, ms = H.profile_read()
+    H.profile(False)
+    ms_step = dt / args.steps * 1e3
+    value = args.steps / dt
+
+    # the same steps without event recording, for reference
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run("mixed", Ym, args.steps)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) / args.steps * 1e3
+
+    m2l_ms = ms[passes == 2]
+    m2l_per_step = m2l_ms.sum() / args.steps
+    launches_per_step = m2l_ms.size / args.steps
+    m2l_rate = info["m2l_interactions"] / (m2l_per_step * 1e-3)
+    breakdown = {name: float(ms[passes == i].sum() / args.steps)
+                 for i, name in enumerate(["gather", "up", "m2l", "down", "p2p"])}
+
+    err_mixed = float(torch.linalg.norm(Ym - Y64) / torch.linalg.norm(Y64))
+    out = {
+        "metric": METRIC, "value": value, "unit": "matvecs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"3D 1/r, N={n} uniform in [-1,1]^3, leaf 64, tol 1e-6, 1 RHS N(0,1), "
+                               f"mixed FP32 apply with FP64 pivots/operators and FP64 near-field refinement",
+                   "n": n, "kappa": info["kappa"], "leaf_size": 64, "tol": 1e-6, "nrhs": 1},
+        "roofline": {"bound": "alu", "achieved": m2l_rate / 1e9, "peak": PEAK_INTERACTIONS / 1e9,
+                     "unit": "G interactions/s", "frac": m2l_rate / PEAK_INTERACTIONS, "traffic": None,
+                     "kernel": "k_m2l<float, 1/r>", "launches_per_step": launches_per_step,
+                     "avg_launch_ms": float(m2l_ms.mean()) if m2l_ms.size else None,
+                     "interactions_per_step": info["m2l_interactions"]},
+        "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
+        "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,
+        "interactions_per_step": inter, "ms_per_step_without_events": ms_plain,
+    }
+    if not args.no_direct:
+        yd = nnca.direct(p, X.reshape(n), "inv_r", device=dev)
+        torch.cuda.synchronize()
+        out["err_fp64_vs_direct"] = float(torch.linalg.norm(Y64.reshape(n) - yd) / torch.linalg.norm(yd))
+        out["err_mixed_vs_direct"] = float(torch.linalg.norm(Ym.reshape(n) - yd) / torch.linalg.norm(yd))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inter)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

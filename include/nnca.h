@@ -1,0 +1,172 @@
+/*
+ * nnca.h -- C ABI of the MI355X (gfx950) library for the NNCA-based H2
+ * matrix-vector product of Gujjula & Ambikasaran, "A new Nested Cross
+ * Approximation".
+ *
+ * The operator is A_ij = K(p_i, p_j) over one point set P = Q in 2D or 3D
+ * (Sec. 1; the symmetric case of Sec. 5).  nnca_build runs the single
+ * bottom-up traversal of Sec. 2.3.2 on the GPU (tree of Sec. 2.1, lists of
+ * Sec. 2.2 / Table 1, one partially pivoted ACA per cell, Sec. 2.2.1, with the
+ * transfer operators taken from the ACA by-products, Remark in Sec. 2.3.2).
+ * nnca_matvec applies the H2 representation of Sec. 3 with the passes of
+ * Sec. 4 (upward, transverse, downward, near field).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns nnca_status.  Nothing aborts or throws across
+ *     the ABI; on error nnca_last_error() holds a message (thread-local) and
+ *     output arguments are left untouched.
+ *   - Device pointers are HIP device memory on the current device.  Host
+ *     pointers are ordinary process memory.  The library never takes
+ *     ownership of caller memory.
+ *   - Vectors are column-major N x nrhs in the caller's original point order,
+ *     with leading dimension ld >= N.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  nnca_build and
+ *     the export/query functions are blocking; nnca_matvec,
+ *     nnca_matvec_adjoint and nnca_direct are asynchronous on `stream`.
+ *   - A handle may be used from one thread at a time.
+ */
+#ifndef NNCA_H
+#define NNCA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnca_h2 *nnca_handle;
+
+typedef enum {
+    NNCA_OK = 0,
+    NNCA_ERR_INVALID_ARG = 1,   /* a bad size, pointer, tolerance or point    */
+    NNCA_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed         */
+    NNCA_ERR_HIP = 3,           /* a HIP runtime call or a kernel launch failed */
+    NNCA_ERR_NOT_SUPPORTED = 4, /* valid but unsupported combination          */
+    NNCA_ERR_NUMERICAL = 5,     /* a zero pivot in a transfer-operator solve  */
+    NNCA_ERR_INTERNAL = 6
+} nnca_status;
+
+/* Kernel functions K(x, y) = K(r), r = |x - y| (Sec. 5, Exp. 1-6).
+ * log r and 1/r are zero at r = 0; the Gaussian exp(-r^2/h^2) is 1 there. */
+typedef enum {
+    NNCA_K_LOG_R = 1,   /* log r, 2D only                                 */
+    NNCA_K_INV_R = 2,   /* 1/r                                            */
+    NNCA_K_GAUSS = 3    /* exp(-r^2 / h^2), h = length_scale > 0          */
+} nnca_kernel_kind;
+
+/* Arithmetic of a matvec.
+ *   NNCA_PREC_FP64:  every pass in FP64.
+ *   NNCA_PREC_MIXED: every pass in FP32 with FP32 accumulation on cell-local
+ *     coordinates; the input is split x = x_hi + x_lo (x_hi = fl32(x),
+ *     x_lo = fl32(x - x_hi)), the near field is applied to both parts and
+ *     the three partial results are combined in FP64.  Pivots and transfer
+ *     operators always come from the FP64 build.                           */
+typedef enum { NNCA_PREC_FP64 = 0, NNCA_PREC_MIXED = 1 } nnca_precision;
+
+typedef struct {
+    uint32_t struct_size;    /* sizeof(nnca_build_options)                    */
+    int32_t eta2_num;        /* admissibility eta^2 = eta2_num / eta2_den;     */
+    int32_t eta2_den;        /*   0/0 selects eta^2 = dim (adjacent cells)    */
+    int32_t exhausted_policy;/* 1 (default): a cell whose far-field candidate
+                                set has fewer columns than rows keeps all its
+                                rows (identity operator); 0: plain ACA        */
+    int64_t workspace_bytes; /* cap on the ACA panel workspace; 0 = automatic */
+} nnca_build_options;
+
+/* Build the H2 representation (Sec. 3 steps 1; steps 2-3 are evaluated on
+ * the fly by nnca_matvec).
+ *   points: dim x n coordinates, structure of arrays: coordinate q of point i
+ *           at points[q * ld + i]; host memory if points_on_device == 0, else
+ *           device memory.  Copied; the caller may free it on return.
+ *   n >= 1, dim in {2, 3}, ld >= n, leaf_size >= 1 (the nu of Sec. 2.1),
+ *   tol >= 0 (epsilon_NCA of Sec. 2.3.2, the same at every level).
+ *   opts may be NULL (defaults).  On success *out receives a new handle.
+ * Errors: INVALID_ARG for bad sizes, NULL pointers, tol < 0 or NaN,
+ * non-finite coordinates, length_scale <= 0 with the Gaussian;
+ * NOT_SUPPORTED for the log kernel outside 2D; OUT_OF_MEMORY; HIP.          */
+nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
+                       int32_t points_on_device, int32_t kernel_kind, double length_scale,
+                       double tol, int32_t leaf_size, const nnca_build_options *opts,
+                       void *stream, nnca_handle *out);
+
+/* Y = A~ X (Sec. 4) for nrhs columns.  X, Y: device FP64, original point
+ * order, column-major with leading dimensions ldx, ldy >= n; X and Y must not
+ * overlap.  precision is an nnca_precision.  Asynchronous on `stream`.     */
+nnca_status nnca_matvec(nnca_handle h, const double *X, double *Y, int64_t nrhs,
+                        int64_t ldx, int64_t ldy, int32_t precision, void *stream);
+
+/* Y = A~^T X: the same passes transposed (P2M <-> L2P, M2M <-> L2L, every
+ * M2L and near-field block transposed).  Arguments as nnca_matvec.        */
+nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64_t nrhs,
+                                int64_t ldx, int64_t ldy, int32_t precision, void *stream);
+
+/* Dense FP64 direct sum Y = A X with A_ij = K(p_i, p_j) (the plain
+ * definition; used for error reports).  points: device, dim x n SoA with
+ * stride ld; X, Y: device FP64 column-major.  Asynchronous on `stream`.    */
+nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld,
+                        int32_t kernel_kind, double length_scale, const double *X, double *Y,
+                        int64_t nrhs, int64_t ldx, int64_t ldy, void *stream);
+
+#define NNCA_MAX_LEVELS 64
+typedef struct {
+    int64_t n;
+    int32_t dim, kappa, lmin, leaf_size;
+    int32_t kernel_kind;
+    double length_scale, tol;
+    double lo[3], side;                   /* the root cell: lo + [0, side]^dim */
+    int64_t ncell[NNCA_MAX_LEVELS];       /* non-empty cells per level         */
+    int64_t npiv[NNCA_MAX_LEVELS];        /* sum of ranks per level            */
+    int64_t nlist[NNCA_MAX_LEVELS][2];    /* total entries of N and IL lists   */
+    int32_t max_rank[NNCA_MAX_LEVELS];
+    int64_t transfer_entries;             /* stored non-identity entries of all C */
+    int64_t m2l_interactions;             /* sum over IL pairs of k_B k_B'      */
+    int64_t p2p_interactions;             /* sum over near pairs |t^B| |t^B'|   */
+    double build_seconds;
+} nnca_info;
+
+/* Structure and statistics of a handle (blocking). */
+nnca_status nnca_query(nnca_handle h, nnca_info *info);
+
+/* Parity exports (blocking; all output buffers are host memory sized by the
+ * caller from nnca_query).
+ *   order[n]: original index of each tree-order position.
+ *   cells of level l: key (Morton prefix), first/count (tree-order range).
+ *   lists of level l (which = 0: N(B), 1: IL(B)): ptr[ncell+1], idx[total].
+ *   pivots of level l: ptr[ncell+1], rows[npiv] (t^{B,i}, original indices,
+ *     ACA selection order), cols[npiv] (s^{B,i}, original indices; -1 for
+ *     cells kept whole).
+ *   operator of cell b at level l: m x k row-major dense C_B into C
+ *     (capacity `cap` doubles), *m and *k receive its shape.               */
+nnca_status nnca_export_order(nnca_handle h, int64_t *order);
+nnca_status nnca_export_cells(nnca_handle h, int32_t level, uint64_t *key, int64_t *first,
+                              int64_t *count);
+nnca_status nnca_export_lists(nnca_handle h, int32_t level, int32_t which, int64_t *ptr,
+                              int64_t *idx);
+nnca_status nnca_export_pivots(nnca_handle h, int32_t level, int64_t *ptr, int64_t *rows,
+                               int64_t *cols);
+nnca_status nnca_export_operator(nnca_handle h, int32_t level, int64_t cell, double *C,
+                                 int64_t cap, int64_t *m, int64_t *k);
+
+/* Evaluate the method's FP64 kernel on the device for `count` pairs
+ * (a[i], b[i]); a, b: host, dim x count SoA; out: host, count values.
+ * Used to check that the device evaluates K bit for bit as specified.     */
+nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int32_t dim,
+                                   const double *a, const double *b, int64_t count, double *out);
+
+/* Per-launch timing of the matvec passes with HIP events recorded on the
+ * matvec stream.  nnca_profile_enable(h, 1) starts recording (and clears
+ * earlier records), 0 stops.  nnca_profile_read (blocking) copies up to
+ * `cap` records -- pass (0 gather/split, 1 P2M/M2M, 2 M2L, 3 L2L/L2P,
+ * 4 near field + combine), tree level (-1 for none) and milliseconds -- into
+ * host arrays, stores the number of records in *count and clears them.     */
+nnca_status nnca_profile_enable(nnca_handle h, int32_t enable);
+nnca_status nnca_profile_read(nnca_handle h, int64_t *count, int32_t *pass, int32_t *level, double *ms,
+                              int64_t cap);
+
+nnca_status nnca_destroy(nnca_handle h);
+const char *nnca_status_string(nnca_status s);
+const char *nnca_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

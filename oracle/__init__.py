@@ -14,6 +14,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+import sys
 
 import numpy as np
 
@@ -144,15 +145,18 @@ class Tree:
         if eta2 is None:
             eta2 = (self.d, 1)
         num, den = eta2
+        self._free = lib().orc_tree_free
         self._h = lib().orc_tree_build(_p(pts), self.n, self.d, int(leaf_size), int(num), int(den))
         if not self._h:
             raise ValueError("oracle tree build rejected its arguments")
         self.kappa = lib().orc_tree_kappa(self._h)
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().orc_tree_free(self._h)
-            self._h = None
+        # at interpreter exit the process frees everything; the order in which
+        # objects die there is arbitrary, so nothing is released explicitly
+        if getattr(self, "_h", None) and not sys.is_finalizing():
+            self._free(self._h)
+        self._h = None
 
     def domain(self):
         lo = np.zeros(3)
@@ -194,15 +198,16 @@ class H2:
                  build: bool = True):
         self.tree = tree
         self.kind = kind
+        self._free = lib().orc_h2_free
         self._h = lib().orc_h2_new(tree._h, KINDS[kind], float(h), float(tol), int(policy))
         self.lmin = lib().orc_h2_lmin(self._h)
         if build:
             self.build()
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().orc_h2_free(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and not sys.is_finalizing():
+            self._free(self._h)
+        self._h = None
 
     def build(self, level: int | None = None, cells=None):
         if level is None:

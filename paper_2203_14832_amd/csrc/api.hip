@@ -1,0 +1,400 @@
+// C ABI of the library (declared in include/nnca.h): argument checks, error
+// translation, handle lifetime, parity exports.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "nnca_internal.h"
+
+namespace nnca {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void fail(nnca_status s, const std::string &msg) { throw Error{s, msg}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? NNCA_ERR_OUT_OF_MEMORY : NNCA_ERR_HIP,
+             std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace nnca
+
+using namespace nnca;
+
+template <typename F>
+static nnca_status guarded(F &&f)
+{
+    try {
+        f();
+        return NNCA_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return NNCA_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        set_error("unexpected exception");
+        return NNCA_ERR_INTERNAL;
+    }
+}
+
+static void clear_profile(nnca_h2 *H)
+{
+    for (auto &r : H->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    H->prof.clear();
+}
+
+static void free_handle(nnca_h2 *H)
+{
+    if (!H) return;
+    clear_profile(H);
+    for (auto &L : H->lev) {
+        void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
+                      L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
+                      L.rem_pos, L.crem_off, L.crem64, L.crem32, L.pc64, L.pc32, L.ilpre, L.ilsum, L.w64,
+                      L.u64, L.w32, L.u32};
+        for (void *p : ps) dfree(p);
+    }
+    void *ps[] = {H->pts64, H->pts32, H->order, H->keys, H->nbpre, H->nbsum, H->xs64, H->far64, H->xhi, H->xlo,
+                  H->far32};
+    for (void *p : ps) dfree(p);
+    delete H;
+}
+
+static void check_kernel(int32_t kind, int32_t dim, double hparam)
+{
+    if (kind != NNCA_K_LOG_R && kind != NNCA_K_INV_R && kind != NNCA_K_GAUSS)
+        fail(NNCA_ERR_INVALID_ARG, "unknown kernel kind");
+    if (kind == NNCA_K_LOG_R && dim != 2) fail(NNCA_ERR_NOT_SUPPORTED, "log kernel is provided in 2D only");
+    if (kind == NNCA_K_GAUSS && !(hparam > 0.0 && std::isfinite(hparam)))
+        fail(NNCA_ERR_INVALID_ARG, "Gaussian length scale must be positive and finite");
+}
+
+static const Level &level_of(nnca_handle h, int32_t level)
+{
+    if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+    if (level < 0 || level > h->kappa) fail(NNCA_ERR_INVALID_ARG, "level out of range");
+    return h->lev[level];
+}
+
+template <typename S, typename D>
+static void d2h_convert(const S *dev, int64_t cnt, D *host)
+{
+    std::vector<S> tmp(cnt > 0 ? cnt : 1);
+    if (cnt > 0) HIPCHECK(hipMemcpy(tmp.data(), dev, sizeof(S) * cnt, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < cnt; i++) host[i] = (D)tmp[i];
+}
+
+extern "C" {
+
+nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t points_on_device,
+                       int32_t kernel_kind, double length_scale, double tol, int32_t leaf_size,
+                       const nnca_build_options *opts, void *stream, nnca_handle *out)
+{
+    return guarded([&] {
+        if (!out) fail(NNCA_ERR_INVALID_ARG, "out is NULL");
+        if (!points) fail(NNCA_ERR_INVALID_ARG, "points is NULL");
+        if (n < 1 || n > (int64_t)INT32_MAX / 2) fail(NNCA_ERR_INVALID_ARG, "n out of range");
+        if (dim != 2 && dim != 3) fail(NNCA_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (ld < n) fail(NNCA_ERR_INVALID_ARG, "ld < n");
+        if (leaf_size < 1) fail(NNCA_ERR_INVALID_ARG, "leaf_size < 1");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(NNCA_ERR_INVALID_ARG, "tol must be finite and >= 0");
+        check_kernel(kernel_kind, dim, length_scale);
+        nnca_build_options o{};
+        o.struct_size = sizeof(o);
+        o.exhausted_policy = 1;
+        if (opts) {
+            if (opts->struct_size < sizeof(nnca_build_options)) fail(NNCA_ERR_INVALID_ARG, "bad struct_size");
+            o = *opts;
+        }
+        if ((o.eta2_num == 0) != (o.eta2_den == 0) || o.eta2_num < 0 || o.eta2_den < 0)
+            fail(NNCA_ERR_INVALID_ARG, "eta2 must be a positive fraction or 0/0");
+        if (o.exhausted_policy != 0 && o.exhausted_policy != 1) fail(NNCA_ERR_INVALID_ARG, "bad exhausted_policy");
+
+        auto t0 = std::chrono::steady_clock::now();
+        nnca_h2 *H = new nnca_h2();
+        H->n = n;
+        H->dim = dim;
+        H->kind = kernel_kind;
+        H->hparam = kernel_kind == NNCA_K_GAUSS ? length_scale : 1.0;
+        H->tol = tol;
+        H->leaf = leaf_size;
+        H->eta_num = o.eta2_num ? o.eta2_num : dim;
+        H->eta_den = o.eta2_num ? o.eta2_den : 1;
+        H->policy = o.exhausted_policy;
+        H->ws_budget = o.workspace_bytes;
+        H->stream = (hipStream_t)stream;
+        try {
+            double *pin = nullptr;
+            int64_t pld = ld;
+            if (points_on_device) {
+                pin = const_cast<double *>(points);
+            } else {
+                pin = dalloc<double>((size_t)dim * n);
+                HIPCHECK(hipMemcpy2DAsync(pin, sizeof(double) * n, points, sizeof(double) * ld, sizeof(double) * n,
+                                          dim, hipMemcpyHostToDevice, H->stream));
+                pld = n;
+            }
+            try {
+                build_tree(H, pin, pld);
+            } catch (...) {
+                if (!points_on_device) dfree(pin);
+                throw;
+            }
+            if (!points_on_device) {
+                HIPCHECK(hipStreamSynchronize(H->stream));
+                dfree(pin);
+            }
+            build_pivots(H);
+            prepare_apply(H);
+            HIPCHECK(hipStreamSynchronize(H->stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(H->stream);
+            free_handle(H);
+            throw;
+        }
+        H->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = H;
+    });
+}
+
+static nnca_status matvec_common(nnca_handle h, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                 int32_t precision, void *stream)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        if (!X || !Y) fail(NNCA_ERR_INVALID_ARG, "X or Y is NULL");
+        if (nrhs < 1) fail(NNCA_ERR_INVALID_ARG, "nrhs < 1");
+        if (ldx < h->n || ldy < h->n) fail(NNCA_ERR_INVALID_ARG, "leading dimension < n");
+        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+        const char *xb = (const char *)X, *xe = (const char *)(X + (nrhs - 1) * ldx + h->n);
+        const char *yb = (const char *)Y, *ye = (const char *)(Y + (nrhs - 1) * ldy + h->n);
+        if (xb < ye && yb < xe) fail(NNCA_ERR_INVALID_ARG, "X and Y overlap");
+        run_matvec(h, X, Y, nrhs, ldx, ldy, precision, (hipStream_t)stream);
+    });
+}
+
+nnca_status nnca_matvec(nnca_handle h, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                        int32_t precision, void *stream)
+{
+    return matvec_common(h, X, Y, nrhs, ldx, ldy, precision, stream);
+}
+
+// In the symmetric case of Sec. 5 (P = Q, K(x,y) = K(y,x), V_B = U_B,
+// T_{B B_c} = C_{B_c B}^T) the transposed passes coincide with the forward
+// ones: P2M^T = L2P, M2M^T = L2L, and every block S_{B,B'}^T = S_{B',B} with
+// B' in IL(B) <=> B in IL(B'), near blocks likewise.  The adjoint therefore
+// runs the same kernels.
+nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                int32_t precision, void *stream)
+{
+    return matvec_common(h, X, Y, nrhs, ldx, ldy, precision, stream);
+}
+
+nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t kernel_kind,
+                        double length_scale, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                        void *stream)
+{
+    return guarded([&] {
+        if (!points || !X || !Y) fail(NNCA_ERR_INVALID_ARG, "NULL pointer");
+        if (n < 1 || (dim != 2 && dim != 3) || ld < n || nrhs < 1 || ldx < n || ldy < n)
+            fail(NNCA_ERR_INVALID_ARG, "bad size");
+        check_kernel(kernel_kind, dim, length_scale);
+        run_direct(points, n, dim, ld, kernel_kind, kernel_kind == NNCA_K_GAUSS ? length_scale : 1.0, X, Y, nrhs,
+                   ldx, ldy, (hipStream_t)stream);
+    });
+}
+
+nnca_status nnca_query(nnca_handle h, nnca_info *info)
+{
+    return guarded([&] {
+        if (!h || !info) fail(NNCA_ERR_INVALID_ARG, "NULL argument");
+        std::memset(info, 0, sizeof(*info));
+        info->n = h->n;
+        info->dim = h->dim;
+        info->kappa = h->kappa;
+        info->lmin = h->lmin;
+        info->leaf_size = h->leaf;
+        info->kernel_kind = h->kind;
+        info->length_scale = h->hparam;
+        info->tol = h->tol;
+        for (int q = 0; q < 3; q++) info->lo[q] = h->lo[q];
+        info->side = h->L;
+        for (int l = 0; l <= h->kappa && l < NNCA_MAX_LEVELS; l++) {
+            const Level &L = h->lev[l];
+            info->ncell[l] = L.ncell;
+            info->npiv[l] = L.has_piv ? L.npiv : 0;
+            info->nlist[l][0] = L.nnb;
+            info->nlist[l][1] = L.nil;
+            info->max_rank[l] = L.has_piv ? L.max_k : 0;
+        }
+        info->transfer_entries = h->transfer_entries;
+        info->m2l_interactions = h->m2l_inter;
+        info->p2p_interactions = h->p2p_inter;
+        info->build_seconds = h->build_seconds;
+    });
+}
+
+nnca_status nnca_export_order(nnca_handle h, int64_t *order)
+{
+    return guarded([&] {
+        if (!h || !order) fail(NNCA_ERR_INVALID_ARG, "NULL argument");
+        d2h_convert(h->order, h->n, order);
+    });
+}
+
+nnca_status nnca_export_cells(nnca_handle h, int32_t level, uint64_t *key, int64_t *first, int64_t *count)
+{
+    return guarded([&] {
+        const Level &L = level_of(h, level);
+        if (key) HIPCHECK(hipMemcpy(key, L.key, sizeof(uint64_t) * L.ncell, hipMemcpyDeviceToHost));
+        if (first) d2h_convert(L.first, L.ncell, first);
+        if (count) d2h_convert(L.count, L.ncell, count);
+    });
+}
+
+nnca_status nnca_export_lists(nnca_handle h, int32_t level, int32_t which, int64_t *ptr, int64_t *idx)
+{
+    return guarded([&] {
+        const Level &L = level_of(h, level);
+        if (which != 0 && which != 1) fail(NNCA_ERR_INVALID_ARG, "which must be 0 or 1");
+        if (!ptr || !idx) fail(NNCA_ERR_INVALID_ARG, "NULL argument");
+        d2h_convert(which ? L.il_ptr : L.nb_ptr, L.ncell + 1, ptr);
+        d2h_convert(which ? L.il : L.nb, which ? L.nil : L.nnb, idx);
+    });
+}
+
+nnca_status nnca_export_pivots(nnca_handle h, int32_t level, int64_t *ptr, int64_t *rows, int64_t *cols)
+{
+    return guarded([&] {
+        const Level &L = level_of(h, level);
+        if (!L.has_piv) fail(NNCA_ERR_INVALID_ARG, "level carries no pivots");
+        std::vector<int32_t> order(h->n);
+        HIPCHECK(hipMemcpy(order.data(), h->order, sizeof(int32_t) * h->n, hipMemcpyDeviceToHost));
+        if (ptr) d2h_convert(L.piv_ptr, L.ncell + 1, ptr);
+        std::vector<int32_t> tmp(L.npiv > 0 ? L.npiv : 1);
+        if (rows) {
+            if (L.npiv) HIPCHECK(hipMemcpy(tmp.data(), L.piv_id, sizeof(int32_t) * L.npiv, hipMemcpyDeviceToHost));
+            for (int64_t q = 0; q < L.npiv; q++) rows[q] = order[tmp[q]];
+        }
+        if (cols) {
+            if (L.npiv) HIPCHECK(hipMemcpy(tmp.data(), L.jid, sizeof(int32_t) * L.npiv, hipMemcpyDeviceToHost));
+            for (int64_t q = 0; q < L.npiv; q++) cols[q] = tmp[q] < 0 ? -1 : order[tmp[q]];
+        }
+    });
+}
+
+nnca_status nnca_export_operator(nnca_handle h, int32_t level, int64_t cell, double *C, int64_t cap, int64_t *m,
+                                 int64_t *k)
+{
+    return guarded([&] {
+        const Level &L = level_of(h, level);
+        if (!L.has_piv) fail(NNCA_ERR_INVALID_ARG, "level carries no pivots");
+        if (cell < 0 || cell >= L.ncell) fail(NNCA_ERR_INVALID_ARG, "cell out of range");
+        int64_t mm = L.h_m[cell], kk = L.h_k[cell];
+        if (m) *m = mm;
+        if (k) *k = kk;
+        if (!C) return;
+        if (cap < mm * kk) fail(NNCA_ERR_INVALID_ARG, "C too small");
+        int32_t pp[2], rp[2];
+        int64_t co[2];
+        HIPCHECK(hipMemcpy(pp, L.piv_ptr + cell, sizeof(pp), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(rp, L.rem_ptr + cell, sizeof(rp), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(co, L.crem_off + cell, sizeof(co), hipMemcpyDeviceToHost));
+        std::vector<int32_t> ip(kk > 0 ? kk : 1), rpos(rp[1] - rp[0] > 0 ? rp[1] - rp[0] : 1);
+        std::vector<double> cr(co[1] - co[0] > 0 ? co[1] - co[0] : 1);
+        if (kk) HIPCHECK(hipMemcpy(ip.data(), L.ipos + pp[0], sizeof(int32_t) * kk, hipMemcpyDeviceToHost));
+        if (rp[1] > rp[0])
+            HIPCHECK(hipMemcpy(rpos.data(), L.rem_pos + rp[0], sizeof(int32_t) * (rp[1] - rp[0]), hipMemcpyDeviceToHost));
+        if (co[1] > co[0])
+            HIPCHECK(hipMemcpy(cr.data(), L.crem64 + co[0], sizeof(double) * (co[1] - co[0]), hipMemcpyDeviceToHost));
+        std::memset(C, 0, sizeof(double) * mm * kk);
+        for (int64_t q = 0; q < kk; q++) C[(int64_t)ip[q] * kk + q] = 1.0;
+        for (int64_t r = 0; r < rp[1] - rp[0]; r++)
+            for (int64_t q = 0; q < kk; q++) C[(int64_t)rpos[r] * kk + q] = cr[r * kk + q];
+    });
+}
+
+nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int32_t dim, const double *a,
+                                   const double *b, int64_t count, double *out)
+{
+    return guarded([&] {
+        if (!a || !b || !out || count < 1 || (dim != 2 && dim != 3)) fail(NNCA_ERR_INVALID_ARG, "bad argument");
+        check_kernel(kernel_kind, dim, length_scale);
+        debug_kernel_eval(kernel_kind, kernel_kind == NNCA_K_GAUSS ? length_scale : 1.0, dim, a, b, count, out,
+                          nullptr);
+    });
+}
+
+nnca_status nnca_profile_enable(nnca_handle h, int32_t enable)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        HIPCHECK(hipStreamSynchronize(h->stream));
+        clear_profile(h);
+        h->profiling = enable != 0;
+    });
+}
+
+nnca_status nnca_profile_read(nnca_handle h, int64_t *count, int32_t *pass, int32_t *level, double *ms, int64_t cap)
+{
+    return guarded([&] {
+        if (!h || !count) fail(NNCA_ERR_INVALID_ARG, "NULL argument");
+        int64_t nrec = (int64_t)h->prof.size();
+        for (int64_t q = 0; q < nrec && q < cap; q++) {
+            auto &r = h->prof[q];
+            HIPCHECK(hipEventSynchronize(r.b));
+            float t = 0.f;
+            HIPCHECK(hipEventElapsedTime(&t, r.a, r.b));
+            if (pass) pass[q] = r.pass;
+            if (level) level[q] = r.level;
+            if (ms) ms[q] = t;
+        }
+        *count = nrec;
+        clear_profile(h);
+    });
+}
+
+nnca_status nnca_destroy(nnca_handle h)
+{
+    return guarded([&] {
+        if (h) {
+            (void)hipStreamSynchronize(h->stream);
+            free_handle(h);
+        }
+    });
+}
+
+const char *nnca_status_string(nnca_status s)
+{
+    switch (s) {
+    case NNCA_OK: return "ok";
+    case NNCA_ERR_INVALID_ARG: return "invalid argument";
+    case NNCA_ERR_OUT_OF_MEMORY: return "out of memory";
+    case NNCA_ERR_HIP: return "HIP error";
+    case NNCA_ERR_NOT_SUPPORTED: return "not supported";
+    case NNCA_ERR_NUMERICAL: return "numerical failure";
+    case NNCA_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *nnca_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal declarations of the gfx950 NNCA library: the handle, the per-level
+// device layout and the launchers that each translation unit provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nnca.h"
+
+namespace nnca {
+
+// Thrown inside the library and turned into an nnca_status at the ABI.
+struct Error {
+    nnca_status status;
+    std::string msg;
+};
+
+void set_error(const std::string &msg);
+[[noreturn]] void fail(nnca_status s, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HIPCHECK(x) ::nnca::hip_check((x), #x)
+
+// Device allocation owned by the library (freed with the handle).
+template <typename T>
+T *dalloc(size_t count)
+{
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(NNCA_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return static_cast<T *>(p);
+}
+void dfree(void *p);
+
+// One level of the uniform 2^d tree and, from lmin to kappa, its pivots,
+// transfer operators and apply buffers.  All pointers are device memory.
+// Cells are the non-empty cells of the level in ascending Morton order;
+// points are addressed by their position in tree order ("sorted ids").
+struct Level {
+    int64_t ncell = 0;
+    double h = 0.0;                  // cell side
+    uint64_t *key = nullptr;         // Morton prefix of each cell
+    int32_t *coord = nullptr;        // integer coordinates, SoA: coord[q * ncell + c]
+    int32_t *first = nullptr;        // tree-order range of the cell's points
+    int32_t *count = nullptr;
+    int32_t *parent = nullptr;       // cell index one level up (-1 at the root)
+    int32_t *child_first = nullptr;  // children: [child_first, child_first + child_count)
+    int32_t *child_count = nullptr;
+    int32_t *nb_ptr = nullptr, *nb = nullptr;  // N(B), CSR, ascending
+    int32_t *il_ptr = nullptr, *il = nullptr;  // IL(B), CSR, ascending
+    int64_t nnb = 0, nil = 0;
+
+    // pivots: levels lmin..kappa
+    bool has_piv = false;
+    int64_t npiv = 0;                // sum of ranks
+    int32_t max_k = 0;
+    int32_t *m = nullptr;            // |t~^{B,i}|
+    int32_t *tt_off = nullptr;       // t~ as a range: leaf -> tree order, else -> piv_id of level+1
+    int32_t *k = nullptr;            // rank k_B = |t^{B,i}|
+    int32_t *piv_ptr = nullptr;      // ncell + 1
+    int32_t *piv_id = nullptr;       // t^{B,i}: sorted ids, ACA selection order
+    int32_t *ipos = nullptr;         // position of each pivot inside t~
+    int32_t *jid = nullptr;          // s^{B,i}: sorted ids (-1 for a cell kept whole)
+    int32_t *rem_ptr = nullptr;      // ncell + 1: rows of t~ that are not pivots
+    int32_t *rem_pos = nullptr;      //   their positions inside t~, ascending
+    int64_t *crem_off = nullptr;     // ncell + 1: offsets of each cell's block in crem
+    int64_t ncrem = 0;
+    double *crem64 = nullptr;        // non-identity rows of C_B, (m - k) x k row-major
+    float *crem32 = nullptr;
+    double *pc64 = nullptr;          // pivot coordinates, SoA 3 x npiv (global)
+    float *pc32 = nullptr;           // pivot coordinates relative to the cell centre
+    int32_t *ilpre = nullptr;        // per IL entry: sources before it in the cell's list
+    int32_t *ilsum = nullptr;        // per cell: M2L sources
+    std::vector<int32_t> h_k, h_m;   // host copies
+    int32_t max_ilsum = 0;
+
+    // apply state (one right-hand side at a time)
+    double *w64 = nullptr, *u64 = nullptr;
+    float *w32 = nullptr, *u32 = nullptr;
+};
+
+struct ChunkInfo;
+
+}  // namespace nnca
+
+struct nnca_h2 {
+    int64_t n = 0;
+    int32_t dim = 3, kind = NNCA_K_INV_R, leaf = 64;
+    double hparam = 1.0, tol = 0.0;
+    int64_t eta_num = 3, eta_den = 1;
+    int32_t policy = 1;
+    int64_t ws_budget = 0;
+    int32_t kmax = 20, kappa = 0, lmin = 1;
+    double lo[3] = {0, 0, 0}, L = 0.0;
+    hipStream_t stream = nullptr;
+    double build_seconds = 0.0;
+
+    double *pts64 = nullptr;      // 3 x n, tree order
+    float *pts32 = nullptr;       // 3 x n, relative to the leaf-cell centre
+    int32_t *order = nullptr;     // tree position -> original index
+    uint64_t *keys = nullptr;     // finest Morton key per tree position
+    std::vector<nnca::Level> lev;
+
+    int32_t *nbpre = nullptr;     // leaf level: per N entry, sources before it
+    int32_t *nbsum = nullptr;     // leaf level: near-field sources per cell
+    int32_t max_leaf = 0;
+
+    // matvec workspace
+    double *xs64 = nullptr, *far64 = nullptr;
+    float *xhi = nullptr, *xlo = nullptr, *far32 = nullptr;
+    int64_t m2l_inter = 0, p2p_inter = 0, transfer_entries = 0;
+
+    // per-launch HIP-event timing of the matvec passes (off by default)
+    struct ProfRec {
+        int32_t pass, level;
+        hipEvent_t a, b;
+    };
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+};
+
+namespace nnca {
+
+// tree.hip
+void build_tree(nnca_h2 *H, const double *pts_dev, int64_t ld);
+// aca.hip
+void build_pivots(nnca_h2 *H);
+void debug_kernel_eval(int kind, double hparam, int dim, const double *a, const double *b,
+                       int64_t count, double *out, hipStream_t s);
+// apply.hip
+void prepare_apply(nnca_h2 *H);
+void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                int precision, hipStream_t s);
+enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4 };
+void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
+                const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);
+
+inline int grid_for(int64_t work, int block)
+{
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 1048576) g = 1048576;
+    return (int)g;
+}
+
+}  // namespace nnca

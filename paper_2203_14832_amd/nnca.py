@@ -1,0 +1,260 @@
+"""Thin ctypes binding of the C ABI in ``include/nnca.h``.
+
+Argument marshalling only: every step of the build and of the matvec runs in
+the HIP library.  Importing this module does not touch the GPU; the library is
+loaded on first use and a missing library is an error (there is no CPU path).
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import sys
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnnca.so")
+
+KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3}
+PRECISION = {"fp64": 0, "mixed": 1}
+MAX_LEVELS = 64
+
+
+class NncaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"nnca status {status}: {msg}")
+        self.status = status
+
+
+class BuildOptions(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("eta2_num", C.c_int32), ("eta2_den", C.c_int32),
+                ("exhausted_policy", C.c_int32), ("workspace_bytes", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("kappa", C.c_int32), ("lmin", C.c_int32),
+                ("leaf_size", C.c_int32), ("kernel_kind", C.c_int32), ("length_scale", C.c_double),
+                ("tol", C.c_double), ("lo", C.c_double * 3), ("side", C.c_double),
+                ("ncell", C.c_int64 * MAX_LEVELS), ("npiv", C.c_int64 * MAX_LEVELS),
+                ("nlist", (C.c_int64 * 2) * MAX_LEVELS), ("max_rank", C.c_int32 * MAX_LEVELS),
+                ("transfer_entries", C.c_int64), ("m2l_interactions", C.c_int64),
+                ("p2p_interactions", C.c_int64), ("build_seconds", C.c_double)]
+
+
+_lib = None
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release device memory while the HIP runtime is still up
+    for m in list(_live):
+        m.close()
+
+
+def lib():
+    """Load libnnca.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "nnca_build": [P, i64, i32, i64, i32, i32, f64, f64, i32, P, P, P],
+            "nnca_matvec": [P, P, P, i64, i64, i64, i32, P],
+            "nnca_matvec_adjoint": [P, P, P, i64, i64, i64, i32, P],
+            "nnca_direct": [P, i64, i32, i64, i32, f64, P, P, i64, i64, i64, P],
+            "nnca_query": [P, P],
+            "nnca_export_order": [P, P],
+            "nnca_export_cells": [P, i32, P, P, P],
+            "nnca_export_lists": [P, i32, i32, P, P],
+            "nnca_export_pivots": [P, i32, P, P, P],
+            "nnca_export_operator": [P, i32, i64, P, i64, P, P],
+            "nnca_debug_kernel_eval": [i32, f64, i32, P, P, i64, P],
+            "nnca_destroy": [P],
+            "nnca_profile_enable": [P, i32],
+            "nnca_profile_read": [P, P, P, P, P, i64],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.nnca_last_error.restype = C.c_char_p
+        L.nnca_status_string.restype = C.c_char_p
+        L.nnca_status_string.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise NncaError(status, lib().nnca_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _as_columns(torch, X, n, device):
+    """(n,) or (n, r) -> column-major FP64 device buffer (r, n) and r."""
+    X = torch.as_tensor(X, dtype=torch.float64, device=device)
+    if X.dim() == 1:
+        return X.contiguous().reshape(1, n), 1, True
+    return X.t().contiguous(), X.shape[1], False
+
+
+class H2Matrix:
+    """H2 representation built by NNCA on the GPU (``nnca_build``)."""
+
+    def __init__(self, points, kernel: str = "inv_r", tol: float = 1e-6, leaf_size: int = 64,
+                 length_scale: float = 1.0, eta2=None, policy: int = 1, workspace_bytes: int = 0,
+                 device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        pts = torch.as_tensor(points, dtype=torch.float64)
+        n, d = pts.shape
+        self.n, self.dim, self.kernel = n, d, kernel
+        soa = pts.t().contiguous().to(self.device)
+        opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes))
+        if eta2 is not None:
+            opts.eta2_num, opts.eta2_den = int(eta2[0]), int(eta2[1])
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_build(C.c_void_p(soa.data_ptr()), n, d, n, 1, KINDS[kernel], float(length_scale),
+                                    float(tol), int(leaf_size), C.byref(opts), _stream(torch), C.byref(h)))
+        self._h = h
+        self._soa = soa
+        self._destroy = lib().nnca_destroy
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
+
+    def _apply(self, X, precision: str, adjoint: bool, out=None):
+        torch = self.torch
+        Xc, r, vec = _as_columns(torch, X, self.n, self.device)
+        Y = torch.empty((r, self.n), dtype=torch.float64, device=self.device) if out is None else out
+        fn = lib().nnca_matvec_adjoint if adjoint else lib().nnca_matvec
+        with torch.cuda.device(self.device):
+            _check(fn(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), r, self.n, self.n,
+                      PRECISION[precision], _stream(torch)))
+        return Y.reshape(self.n) if vec else Y.t()
+
+    def matvec(self, X, precision: str = "fp64"):
+        """Y = A~ X (FP64 device tensor, (n,) or (n, r))."""
+        return self._apply(X, precision, False)
+
+    def rmatvec(self, X, precision: str = "fp64"):
+        """Y = A~^T X."""
+        return self._apply(X, precision, True)
+
+    def matvec_raw(self, Xc, Y, nrhs: int, precision: str = "fp64"):
+        """Column-major device buffers (nrhs, n) in, (nrhs, n) out; no copies."""
+        _check(lib().nnca_matvec(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs, self.n,
+                                 self.n, PRECISION[precision], _stream(self.torch)))
+
+    def profile(self, enable: bool = True):
+        """Start (and clear) or stop per-launch event timing of matvec passes."""
+        _check(lib().nnca_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, cap: int = 1 << 16):
+        """Records (pass, level, ms) since profile(True); clears them."""
+        cnt = C.c_int64()
+        ps = np.zeros(cap, np.int32)
+        lv = np.zeros(cap, np.int32)
+        ms = np.zeros(cap)
+        _check(lib().nnca_profile_read(self._h, C.byref(cnt), _np_ptr(ps), _np_ptr(lv), _np_ptr(ms), cap))
+        k = min(cnt.value, cap)
+        return ps[:k].copy(), lv[:k].copy(), ms[:k].copy()
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().nnca_query(self._h, C.byref(inf)))
+        L = inf.kappa + 1
+        return dict(n=inf.n, dim=inf.dim, kappa=inf.kappa, lmin=inf.lmin, leaf_size=inf.leaf_size,
+                    tol=inf.tol, lo=list(inf.lo)[: inf.dim], side=inf.side,
+                    ncell=[inf.ncell[l] for l in range(L)], npiv=[inf.npiv[l] for l in range(L)],
+                    nlist=[(inf.nlist[l][0], inf.nlist[l][1]) for l in range(L)],
+                    max_rank=[inf.max_rank[l] for l in range(L)], transfer_entries=inf.transfer_entries,
+                    m2l_interactions=inf.m2l_interactions, p2p_interactions=inf.p2p_interactions,
+                    build_seconds=inf.build_seconds)
+
+    # parity exports -----------------------------------------------------
+    def order(self):
+        o = np.zeros(self.n, np.int64)
+        _check(lib().nnca_export_order(self._h, _np_ptr(o)))
+        return o
+
+    def cells(self, level: int):
+        nc = self.info()["ncell"][level]
+        key = np.zeros(nc, np.uint64)
+        first = np.zeros(nc, np.int64)
+        count = np.zeros(nc, np.int64)
+        _check(lib().nnca_export_cells(self._h, level, _np_ptr(key), _np_ptr(first), _np_ptr(count)))
+        return dict(key=key, first=first, count=count)
+
+    def lists(self, level: int, which: str):
+        inf = self.info()
+        w = 1 if which == "il" else 0
+        tot = inf["nlist"][level][w]
+        ptr = np.zeros(inf["ncell"][level] + 1, np.int64)
+        idx = np.zeros(max(tot, 1), np.int64)
+        _check(lib().nnca_export_lists(self._h, level, w, _np_ptr(ptr), _np_ptr(idx)))
+        return ptr, idx[:tot]
+
+    def pivots(self, level: int):
+        inf = self.info()
+        npv = inf["npiv"][level]
+        ptr = np.zeros(inf["ncell"][level] + 1, np.int64)
+        rows = np.zeros(max(npv, 1), np.int64)
+        cols = np.zeros(max(npv, 1), np.int64)
+        _check(lib().nnca_export_pivots(self._h, level, _np_ptr(ptr), _np_ptr(rows), _np_ptr(cols)))
+        return ptr, rows[:npv], cols[:npv]
+
+    def operator(self, level: int, cell: int):
+        m = C.c_int64()
+        k = C.c_int64()
+        _check(lib().nnca_export_operator(self._h, level, cell, None, 0, C.byref(m), C.byref(k)))
+        Cm = np.zeros(max(m.value * k.value, 1))
+        _check(lib().nnca_export_operator(self._h, level, cell, _np_ptr(Cm), Cm.size, C.byref(m), C.byref(k)))
+        return Cm[: m.value * k.value].reshape(m.value, k.value)
+
+
+def direct(points, X, kernel: str = "inv_r", length_scale: float = 1.0, device="cuda:0"):
+    """Dense FP64 direct sum on the GPU (``nnca_direct``)."""
+    import torch
+    dev = torch.device(device)
+    pts = torch.as_tensor(points, dtype=torch.float64)
+    n, d = pts.shape
+    soa = pts.t().contiguous().to(dev)
+    Xc, r, vec = _as_columns(torch, X, n, dev)
+    Y = torch.empty((r, n), dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib().nnca_direct(C.c_void_p(soa.data_ptr()), n, d, n, KINDS[kernel], float(length_scale),
+                                 C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), r, n, n, _stream(torch)))
+    return Y.reshape(n) if vec else Y.t()
+
+
+def debug_kernel_eval(kernel: str, a, b, length_scale: float = 1.0):
+    """Evaluate the method's FP64 kernel on the device for pairs (a[i], b[i])."""
+    a = np.ascontiguousarray(np.asarray(a, np.float64).T)
+    b = np.ascontiguousarray(np.asarray(b, np.float64).T)
+    d, cnt = a.shape
+    out = np.zeros(cnt)
+    _check(lib().nnca_debug_kernel_eval(KINDS[kernel], float(length_scale), d, _np_ptr(a), _np_ptr(b), cnt,
+                                        _np_ptr(out)))
+    return out

@@ -1,0 +1,60 @@
+"""The C-ABI library loads, exports every entry point of include/nnca.h and
+rejects bad arguments with the documented status before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "nnca.h")).read()
+    return sorted(set(re.findall(r"\b(nnca_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2203_14832_amd import nnca
+    return nnca.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert "nnca_build" in syms and "nnca_matvec" in syms and "nnca_matvec_adjoint" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert lib.nnca_status_string(s)
+
+
+def _build(lib, pts, n, dim, ld, kind=2, h=1.0, tol=1e-6, leaf=64, out=True):
+    handle = C.c_void_p()
+    return lib.nnca_build(pts, n, dim, ld, 0, kind, h, tol, leaf, None, None,
+                          C.byref(handle) if out else None), handle
+
+
+def test_invalid_arguments(lib):
+    p = np.zeros((3, 10))
+    P = p.ctypes.data_as(C.c_void_p)
+    assert _build(lib, None, 10, 3, 10)[0] == 1
+    assert _build(lib, P, 10, 3, 10, out=False)[0] == 1
+    assert _build(lib, P, 0, 3, 10)[0] == 1
+    assert _build(lib, P, 10, 4, 10)[0] == 1
+    assert _build(lib, P, 10, 3, 5)[0] == 1
+    assert _build(lib, P, 10, 3, 10, leaf=0)[0] == 1
+    assert _build(lib, P, 10, 3, 10, tol=-1.0)[0] == 1
+    assert _build(lib, P, 10, 3, 10, tol=float("nan"))[0] == 1
+    assert _build(lib, P, 10, 3, 10, kind=7)[0] == 1
+    assert _build(lib, P, 10, 3, 10, kind=3, h=0.0)[0] == 1
+    assert _build(lib, P, 10, 3, 10, kind=1)[0] == 4   # log only in 2D
+    assert b"dim" in lib.nnca_last_error() or lib.nnca_last_error()
+    assert lib.nnca_matvec(None, None, None, 1, 1, 1, 0, None) == 1
+    assert lib.nnca_query(None, None) == 1
+    assert lib.nnca_destroy(None) == 0
+    assert lib.nnca_direct(None, 10, 3, 10, 2, 1.0, None, None, 1, 10, 10, None) == 1
