@@ -27,11 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H2 matvecs/s at N=1M 3D 1/r, mixed vs FP64 at rel.err≤1e-6; % roofline"
-# Roofline of the dominant kernel (M2L, FP32 1/r): an interaction is
-# 3 subtractions + 1 multiply + 2 FMA (squared distance) + 1 v_rsq_f32
-# (quarter rate: 4 issue slots) + 1 FMA = 11 VALU issue slots per lane.
-# Non-packed FP32 VALU issue: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
-VALU_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
+# Roofline of the dominant kernel, the FP32 transverse pass (M2L) of the two
+# finest levels.  Its bound is plain VALU arithmetic.  Peak FP32 vector rate
+# of the chip: 157.3 TFLOP/s = 256 CU x 128 lanes/clock x 2.4 GHz x 2 (FMA),
+# i.e. 7.864e13 lane-instructions/s.  One interaction needs 3 subtractions,
+# 1 multiply and 2 FMA for r^2, one v_rsq_f32 and 1 FMA: 7 full-rate
+# instructions plus one transcendental at quarter rate (4 issue slots), 11
+# slots in all.
+VALU_LANE_SLOTS = 256 * 128 * 2.4e9
 SLOTS_PER_INTERACTION = 11.0
 PEAK_INTERACTIONS = VALU_LANE_SLOTS / SLOTS_PER_INTERACTION
 
@@ -128,10 +131,15 @@ def main():
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t0) / args.steps * 1e3
 
-    m2l_ms = ms[passes == 2]
+    # FP32 M2L launches: the two finest levels (coarser levels run refined FP64)
+    kap = info["kappa"]
+    fine = (passes == 2) & (levels >= kap - 1)
+    m2l_ms = ms[fine]
     m2l_per_step = m2l_ms.sum() / args.steps
     launches_per_step = m2l_ms.size / args.steps
-    m2l_rate = info["m2l_interactions"] / (m2l_per_step * 1e-3)
+    fine_inter = sum(info["m2l_level"][l] for l in range(max(kap - 1, 0), kap + 1))
+    m2l_rate = fine_inter / (m2l_per_step * 1e-3)
+    coarse_ms = float(ms[(passes == 2) & (levels < kap - 1)].sum() / args.steps)
     breakdown = {name: float(ms[passes == i].sum() / args.steps)
                  for i, name in enumerate(["gather", "up", "m2l", "down", "p2p"])}
 
@@ -145,9 +153,12 @@ def main():
                    "n": n, "kappa": info["kappa"], "leaf_size": 64, "tol": 1e-6, "nrhs": 1},
         "roofline": {"bound": "alu", "achieved": m2l_rate / 1e9, "peak": PEAK_INTERACTIONS / 1e9,
                      "unit": "G interactions/s", "frac": m2l_rate / PEAK_INTERACTIONS, "traffic": None,
-                     "kernel": "k_m2l<float, 1/r>", "launches_per_step": launches_per_step,
+                     "kernel": "k_m2l<1/r, FP32, 1024> (levels kappa-1, kappa)",
+                     "launches_per_step": launches_per_step,
                      "avg_launch_ms": float(m2l_ms.mean()) if m2l_ms.size else None,
-                     "interactions_per_step": info["m2l_interactions"]},
+                     "interactions_per_launch": fine_inter / max(launches_per_step, 1),
+                     "peak_derivation": "7.864e13 FP32 lane-instr/s / 11 slots per interaction"},
+        "m2l_coarse_fp64_ms_per_step": coarse_ms, "m2l_level_interactions": info["m2l_level"],
         "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,
         "interactions_per_step": inter, "ms_per_step_without_events": ms_plain,

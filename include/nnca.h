@@ -70,6 +70,10 @@ typedef struct {
                                 set has fewer columns than rows keeps all its
                                 rows (identity operator); 0: plain ACA        */
     int64_t workspace_bytes; /* cap on the ACA panel workspace; 0 = automatic */
+    int32_t rank_reserve;    /* panel rows reserved per non-leaf cell before a
+                                cell that needs more is re-run with min(m, n);
+                                0 = 256.  Affects memory and speed only.      */
+    int32_t reserved;
 } nnca_build_options;
 
 /* Build the H2 representation (Sec. 3 steps 1; steps 2-3 are evaluated on
@@ -117,6 +121,7 @@ typedef struct {
     int64_t npiv[NNCA_MAX_LEVELS];        /* sum of ranks per level            */
     int64_t nlist[NNCA_MAX_LEVELS][2];    /* total entries of N and IL lists   */
     int32_t max_rank[NNCA_MAX_LEVELS];
+    int64_t m2l_level[NNCA_MAX_LEVELS];   /* M2L interactions per level        */
     int64_t transfer_entries;             /* stored non-identity entries of all C */
     int64_t m2l_interactions;             /* sum over IL pairs of k_B k_B'      */
     int64_t p2p_interactions;             /* sum over near pairs |t^B| |t^B'|   */

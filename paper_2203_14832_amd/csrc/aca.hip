@@ -32,6 +32,7 @@ namespace {
 constexpr int NT = 256;      // threads per cell
 constexpr int DOTB = 8;      // cross products reduced per pass
 constexpr int COEF = 2048;   // coefficients staged in LDS
+constexpr int RW = 4;        // residual columns per thread and pass
 
 // log x from IEEE operations: x = m 2^e, m in (sqrt(1/2), sqrt(2)],
 // log m = 2 atanh(s) with s = (m-1)/(m+1) and the series of atanh(s)/s in s^2
@@ -158,7 +159,7 @@ struct AcaCell {
     int64_t cap_off;  // pivot slots (kcap, or m for a cell kept whole)
     int32_t m, n, kcap, whole;
     int32_t tt_off;
-    int32_t pad;
+    int32_t kfull;    // min(m, n): the largest rank the cell can reach
 };
 
 namespace {
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
     __shared__ double su2[NT], sv2[NT];
     __shared__ double du[DOTB][NT], dv[DOTB][NT];
     __shared__ double coef[COEF];
-    __shared__ int32_t s_row, s_k, s_stop, s_jk;
+    __shared__ int32_t s_row, s_k, s_stop, s_jk, s_over;
 
     const int32_t m = C.m, n = C.n, kcap = C.kcap;
     if (kcap == 0) {
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
     const double *sx = sc + C.s_off, *sy = sc + ntot + C.s_off, *sz = sc + 2 * ntot + C.s_off;
     for (int32_t r = t; r < m; r += NT) rf[r] = 0;
     for (int32_t j = t; j < n; j += NT) cf[j] = 0;
-    if (t == 0) { s_row = 0; s_k = 0; s_stop = 0; }
+    if (t == 0) { s_row = 0; s_k = 0; s_stop = 0; s_over = 0; }
     double nrm2 = 0.0;   // meaningful in thread 0
     __syncthreads();
     int32_t k = 0;
@@ -263,20 +264,41 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
         const double ax = P[pid], ay = P[np + pid], az = d == 3 ? P[2 * np + pid] : 0.0;
         for (int32_t l = t; l < k && l < COEF; l += NT) coef[l] = Uc[(int64_t)l * m + i];
         __syncthreads();
-        // 1-2: row residual and its argmax over unused columns
+        // 1-2: row residual and its argmax over unused columns.  Each thread
+        // runs RW columns side by side (independent chains, every column
+        // still accumulated in ascending l) and scans them in ascending j.
         double best = 0.0;
         int32_t bj = INT32_MAX;
         double *Rk = Vc + (int64_t)k * n;
-        for (int32_t j = t; j < n; j += NT) {
-            double r = kval(kind, hh, d, ax, ay, az, sx[j], sy[j], sz[j]);
-            for (int32_t l = 0; l < k; l++) {
-                double ul = l < COEF ? coef[l] : Uc[(int64_t)l * m + i];
-                r = r - ul * Vc[(int64_t)l * n + j];
+        for (int32_t j0 = t; j0 < n; j0 += RW * NT) {
+            double r[RW];
+#pragma unroll
+            for (int c = 0; c < RW; c++) {
+                int32_t j = j0 + c * NT;
+                r[c] = j < n ? kval(kind, hh, d, ax, ay, az, sx[j], sy[j], sz[j]) : 0.0;
             }
-            Rk[j] = r;
-            if (!cf[j]) {
-                double a = fabs(r);
-                if (a > best) { best = a; bj = j; }
+            const int nv = (n - j0 + NT - 1) / NT < RW ? (n - j0 + NT - 1) / NT : RW;
+            if (nv == RW) {
+                for (int32_t l = 0; l < k; l++) {
+                    double ul = l < COEF ? coef[l] : Uc[(int64_t)l * m + i];
+                    const double *Vl = Vc + (int64_t)l * n + j0;
+#pragma unroll
+                    for (int c = 0; c < RW; c++) r[c] = r[c] - ul * Vl[c * NT];
+                }
+            } else {
+                for (int32_t l = 0; l < k; l++) {
+                    double ul = l < COEF ? coef[l] : Uc[(int64_t)l * m + i];
+                    const double *Vl = Vc + (int64_t)l * n + j0;
+                    for (int c = 0; c < nv; c++) r[c] = r[c] - ul * Vl[c * NT];
+                }
+            }
+            for (int c = 0; c < nv; c++) {
+                int32_t j = j0 + c * NT;
+                Rk[j] = r[c];
+                if (!cf[j]) {
+                    double a = fabs(r[c]);
+                    if (a > best) { best = a; bj = j; }
+                }
             }
         }
         sv[t] = best;
@@ -388,7 +410,10 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
             rf[i] = 1;
             cf[jk] = 1;
             int32_t kn = k + 1;
-            int stop = (sqrt(ukk) * sqrt(vkk) <= tol * sqrt(nrm2)) || kn >= kcap || next == INT32_MAX;
+            bool conv = sqrt(ukk) * sqrt(vkk) <= tol * sqrt(nrm2);
+            int stop = conv || kn >= kcap || next == INT32_MAX;
+            // the panel was sized below min(m, n): the cell is run again with room for it
+            if (!conv && next != INT32_MAX && kn >= kcap && kcap < C.kfull) s_over = 1;
             s_k = kn;
             s_stop = stop;
             s_row = next;
@@ -397,7 +422,7 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
         k = s_k;
         if (s_stop) break;
     }
-    if (t == 0) k_out[cell] = k;
+    if (t == 0) k_out[cell] = s_over ? -1 : k;
 }
 
 // Transfer operator C_B = U L^{-1}, L = U(I, :) (Remark in Sec. 2.3.2).  The
@@ -531,14 +556,18 @@ static void build_level(nnca_h2 *H, int l)
         a.n = (int32_t)hn[c];
         a.tt_off = htt[c];
         a.whole = (a.n == 0 || (H->policy == 1 && a.n < a.m)) ? 1 : 0;
-        a.kcap = a.whole ? a.m : std::min(a.m, a.n);
+        a.kfull = std::min(a.m, a.n);
+        a.kcap = a.whole ? a.m : (leaf ? a.kfull : std::min(a.kfull, H->rank_reserve));
         cap_off[c] = sum_cap;
         a.cap_off = sum_cap;
-        sum_cap += a.kcap;
-        bytes[c] = a.whole ? 64
-                           : (int64_t)a.n * (4 + 24) + ((int64_t)a.m * a.kcap + (int64_t)a.kcap * a.n) * 8 +
-                                 (int64_t)a.m * 5 + a.n + 256;
+        sum_cap += a.whole ? a.m : a.kfull;
     }
+    auto cell_bytes = [&](const AcaCell &a) -> int64_t {
+        return a.whole ? 64
+                       : (int64_t)a.n * (4 + 24) + ((int64_t)a.m * a.kcap + (int64_t)a.kcap * a.n) * 8 +
+                             (int64_t)a.m * 5 + a.n + 256;
+    };
+    for (int64_t c = 0; c < nc; c++) bytes[c] = cell_bytes(hc[c]);
     cap_off[nc] = sum_cap;
     int32_t *ipos_cap = dalloc<int32_t>(sum_cap);
     int32_t *jid_cap = dalloc<int32_t>(sum_cap);
@@ -595,6 +624,18 @@ static void build_level(nnca_h2 *H, int l)
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(hk.data() + c0, L.k + c0, sizeof(int32_t) * cn, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
+        // cells whose rank outgrew the reserved panel: widen them and redo the chunk
+        bool again = false;
+        for (int64_t c = c0; c < c1; c++)
+            if (hk[c] < 0) {
+                hc[c].kcap = hc[c].kfull;
+                bytes[c] = cell_bytes(hc[c]);
+                again = true;
+            }
+        if (again) {
+            dfree(sid); dfree(sc); dfree(U); dfree(V); dfree(fl); dfree(rowmap);
+            continue;
+        }
         // remainder rows of this chunk
         std::vector<int64_t> rb(cn), cb(cn);
         int64_t rt = 0, ct = 0;

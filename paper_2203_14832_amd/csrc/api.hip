@@ -67,12 +67,11 @@ static void free_handle(nnca_h2 *H)
     for (auto &L : H->lev) {
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
-                      L.rem_pos, L.crem_off, L.crem64, L.crem32, L.pc64, L.pc32, L.ilpre, L.ilsum, L.w64,
-                      L.u64, L.w32, L.u32};
+                      L.rem_pos, L.crem_off, L.crem64, L.crem_t, L.piv_cell, L.rem_cell, L.pc64, L.pc32,
+                      L.ilpre, L.ilsum, L.w64, L.u64};
         for (void *p : ps) dfree(p);
     }
-    void *ps[] = {H->pts64, H->pts32, H->order, H->keys, H->nbpre, H->nbsum, H->xs64, H->far64, H->xhi, H->xlo,
-                  H->far32};
+    void *ps[] = {H->pts64, H->order, H->keys, H->nbpre, H->nbsum, H->xs64, H->far64, H->xhi, H->xlo, H->m2l_part};
     for (void *p : ps) dfree(p);
     delete H;
 }
@@ -139,6 +138,8 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
         H->eta_den = o.eta2_num ? o.eta2_den : 1;
         H->policy = o.exhausted_policy;
         H->ws_budget = o.workspace_bytes;
+        if (o.rank_reserve < 0) fail(NNCA_ERR_INVALID_ARG, "rank_reserve < 0");
+        H->rank_reserve = o.rank_reserve > 0 ? o.rank_reserve : 256;
         H->stream = (hipStream_t)stream;
         try {
             double *pin = nullptr;
@@ -243,6 +244,7 @@ nnca_status nnca_query(nnca_handle h, nnca_info *info)
             info->nlist[l][0] = L.nnb;
             info->nlist[l][1] = L.nil;
             info->max_rank[l] = L.has_piv ? L.max_k : 0;
+            info->m2l_level[l] = L.has_piv ? L.m2l_inter : 0;
         }
         info->transfer_entries = h->transfer_entries;
         info->m2l_interactions = h->m2l_inter;

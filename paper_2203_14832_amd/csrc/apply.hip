@@ -70,244 +70,411 @@ __global__ void k_gather64(int64_t n, const int32_t *order, const double *x, dou
     if (p < n) xs[p] = x[order[p]];
 }
 
-__global__ void k_gather_split(int64_t n, const int32_t *order, const double *x, float *hi, float *lo)
+__global__ void k_gather_split(int64_t n, const int32_t *order, const double *x, double *xs, float *hi, float *lo)
 {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     double v = x[order[p]];
+    xs[p] = v;
     float h = (float)v;
     hi[p] = h;
     lo[p] = (float)(v - (double)h);
 }
 
 // ---------------------------------------------------------------------------
-// upward pass: w^{B,o} = C_B^T x~ with x~ = x^B at a leaf (P2M), else the
-// children's w^{B_c,o} stacked (M2M).  One wavefront per cell.
+// Transfer passes, in FP64 in both precisions: the nested interpolation
+// operators C_B of a tolerance-driven ACA have entries of size 10-100, which
+// would amplify FP32 rounding of the nested vectors.  One thread per output
+// entry over the whole level (pivot entries first, then the other rows).
 
-template <typename T>
-__global__ void k_up(int64_t nc, const int32_t *m, const int32_t *k, const int32_t *tt_off,
-                     const int32_t *piv_ptr, const int32_t *ipos, const int32_t *rem_ptr,
-                     const int32_t *rem_pos, const int64_t *crem_off, const T *crem, const T *xin, T *w)
+// upward pass: w^{B,o} = C_B^T x~ with x~ = x^B at a leaf (P2M), else the
+// children's w^{B_c,o} stacked (M2M).  C_B's pivot rows are the identity.
+__global__ void k_up(int64_t npiv, const int32_t *piv_cell, const int32_t *piv_ptr, const int32_t *tt_off,
+                     const int32_t *ipos, const int32_t *rem_ptr, const int32_t *rem_pos, const int64_t *crem_off,
+                     const double *crem, const double *xin, double *w)
 {
-    int64_t c = blockIdx.x;
-    int lane = threadIdx.x;
-    int32_t kk = k[c], to = tt_off[c], po = piv_ptr[c], ro = rem_ptr[c];
-    int32_t nr = rem_ptr[c + 1] - ro;
-    const T *C = crem + crem_off[c];
-    for (int32_t q = lane; q < kk; q += 64) {
-        double acc = (double)xin[to + ipos[po + q]];
-        for (int32_t r = 0; r < nr; r++)
-            acc += (double)(C[(int64_t)r * kk + q] * xin[to + rem_pos[ro + r]]);
-        w[po + q] = (T)acc;
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= npiv) return;
+    int32_t c = piv_cell[g];
+    int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, q = (int32_t)g - po;
+    int32_t to = tt_off[c], ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    const double *C = crem + crem_off[c] + q;
+    double acc = xin[to + ipos[g]];
+    for (int32_t r = 0; r < nr; r++) acc += C[(int64_t)r * kk] * xin[to + rem_pos[ro + r]];
+    w[g] = acc;
+}
+
+// the same for levels whose cells have non-pivot rows: one workgroup per cell,
+// the inputs of those rows staged in LDS, rows split among thread groups
+constexpr int UP_TILE = 1024;
+__global__ __launch_bounds__(256) void k_up_cell(const int32_t *piv_ptr, const int32_t *tt_off, const int32_t *ipos,
+                                                 const int32_t *rem_ptr, const int32_t *rem_pos,
+                                                 const int64_t *crem_off, const double *crem, const double *xin,
+                                                 double *w)
+{
+    __shared__ double xr[UP_TILE];
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
+    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    const double *C = crem + crem_off[c];
+    for (int32_t tb = 0; tb < kk; tb += 256) {
+        const int32_t cnt = kk - tb < 256 ? kk - tb : 256;
+        const int32_t G = 256 / cnt, ti = t % cnt, g = t / cnt;
+        double acc = 0.0;
+        for (int32_t r0 = 0; r0 < nr; r0 += UP_TILE) {
+            const int32_t rn = nr - r0 < UP_TILE ? nr - r0 : UP_TILE;
+            __syncthreads();
+            for (int32_t i = t; i < rn; i += 256) xr[i] = xin[to + rem_pos[ro + r0 + i]];
+            __syncthreads();
+            if (g < G) {
+                // four independent partial sums keep four row loads in flight
+                double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int32_t r = g;
+                const double *Cq = C + tb + ti;
+                for (; r + 3 * G < rn; r += 4 * G) {
+                    acc += Cq[(int64_t)(r0 + r) * kk] * xr[r];
+                    a1 += Cq[(int64_t)(r0 + r + G) * kk] * xr[r + G];
+                    a2 += Cq[(int64_t)(r0 + r + 2 * G) * kk] * xr[r + 2 * G];
+                    a3 += Cq[(int64_t)(r0 + r + 3 * G) * kk] * xr[r + 3 * G];
+                }
+                for (; r < rn; r += G) acc += Cq[(int64_t)(r0 + r) * kk] * xr[r];
+                acc += (a1 + a2) + a3;
+            }
+        }
+        red[t] = acc;
+        __syncthreads();
+        if (t < cnt) {
+            double sum = xin[to + ipos[po + tb + t]];
+            for (int32_t gg = 0; gg < G; gg++) sum += red[gg * cnt + t];
+            w[po + tb + t] = sum;
+        }
+        __syncthreads();
     }
 }
 
 // downward pass: the stacked C_B u^{B,i} added to the children's u (L2L) or
-// written as the far field of the leaf's points (L2P).
-template <typename T>
-__global__ void k_down(int64_t nc, const int32_t *k, const int32_t *tt_off, const int32_t *piv_ptr,
-                       const int32_t *ipos, const int32_t *rem_ptr, const int32_t *rem_pos,
-                       const int64_t *crem_off, const T *crem, const T *u, T *out, int accumulate)
+// written as the far field of the leaf's points (L2P).  crem_t holds every
+// cell's block transposed (k x (m-k)) so that neighbouring rows read
+// neighbouring addresses.
+__global__ void k_down(int64_t npiv, int64_t nrem, const int32_t *piv_cell, const int32_t *rem_cell,
+                       const int32_t *piv_ptr, const int32_t *tt_off, const int32_t *ipos, const int32_t *rem_ptr,
+                       const int32_t *rem_pos, const int64_t *crem_off, const double *crem_t, const double *u,
+                       double *out, int accumulate)
 {
-    int64_t c = blockIdx.x;
-    int lane = threadIdx.x;
-    int32_t kk = k[c], to = tt_off[c], po = piv_ptr[c], ro = rem_ptr[c];
-    int32_t nr = rem_ptr[c + 1] - ro;
-    const T *C = crem + crem_off[c];
-    for (int32_t q = lane; q < kk; q += 64) {
-        int32_t dst = to + ipos[po + q];
-        out[dst] = accumulate ? out[dst] + u[po + q] : u[po + q];
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g < npiv) {
+        int32_t c = piv_cell[g];
+        int32_t dst = tt_off[c] + ipos[g];
+        out[dst] = accumulate ? out[dst] + u[g] : u[g];
+        return;
     }
-    for (int32_t r = lane; r < nr; r += 64) {
-        const T *row = C + (int64_t)r * kk;
-        double acc = 0.0;
-        for (int32_t q = 0; q < kk; q++) acc += (double)(row[q] * u[po + q]);
-        int32_t dst = to + rem_pos[ro + r];
-        out[dst] = accumulate ? (T)((double)out[dst] + acc) : (T)acc;
+    g -= npiv;
+    if (g >= nrem) return;
+    int32_t c = rem_cell[g];
+    int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po;
+    int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro, r = (int32_t)g - ro;
+    const double *Ct = crem_t + crem_off[c] + r;
+    const double *ub = u + po;
+    double acc = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int32_t q = 0;
+    for (; q + 3 < kk; q += 4) {
+        acc += Ct[(int64_t)q * nr] * ub[q];
+        a1 += Ct[(int64_t)(q + 1) * nr] * ub[q + 1];
+        a2 += Ct[(int64_t)(q + 2) * nr] * ub[q + 2];
+        a3 += Ct[(int64_t)(q + 3) * nr] * ub[q + 3];
     }
+    for (; q < kk; q++) acc += Ct[(int64_t)q * nr] * ub[q];
+    acc += (a1 + a2) + a3;
+    int32_t dst = tt_off[c] + rem_pos[g];
+    out[dst] = accumulate ? out[dst] + acc : acc;
 }
 
 // ---------------------------------------------------------------------------
-// Interaction kernels.  One workgroup per target cell; its targets are split
-// into groups of `cnt` consecutive threads (G = 256 / cnt groups), each group
-// taking every G-th source of a 256-wide LDS tile.
+// Interaction kernels.  One workgroup per target cell.  Each thread carries R
+// targets (register blocking); the cell's targets are covered by `tpg`
+// threads and the workgroup holds G = 256 / tpg such groups, group g taking
+// every G-th source of each 256-wide LDS tile.  Partial sums are formed in
+// the working precision over CHUNK sources and folded into FP64.
 
-struct TargetSplit {
-    int32_t cnt, G, ti, g;
-    __device__ TargetSplit(int32_t total, int32_t base, int t)
+constexpr int RB = 4;   // targets per thread
+
+struct Split {
+    int32_t cnt, tpg, G, ti, g;
+    __device__ Split(int32_t total, int32_t base, int t)
     {
-        cnt = total - base < NT ? total - base : NT;
-        G = NT / cnt;
-        ti = t % cnt;
-        g = t / cnt;
+        cnt = total - base < NT * RB ? total - base : NT * RB;
+        tpg = (cnt + RB - 1) / RB;
+        G = NT / tpg;
+        ti = t % tpg;
+        g = t / tpg;
     }
 };
 
-// transverse pass at one level: u^{B,i} = sum_{B' in IL(B)} K(t^{B,i}, t^{B',i}) w^{B',o}
-template <typename T, int KIND>
-__global__ __launch_bounds__(NT) void k_m2l(int64_t nc, const int32_t *k, const int32_t *piv_ptr,
-                                            const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
-                                            const int32_t *ilsum, const T *pc, int64_t npiv,
-                                            const int32_t *coord, T h, int d, const T *w, T *u, T prm)
+// Arithmetic of one transverse-pass launch.
+//   M_F32:    FP32 offsets from the cell centres, FP32 kernel and products,
+//             FP32 partial sums of CHUNK terms folded into FP64.
+//   M_F64:    FP64 throughout, K = 1/sqrt(r^2) correctly rounded (the plain
+//             FP64 matvec).
+//   M_F64R:   FP64 coordinates, differences and r^2; 1/r from an FP32
+//             reciprocal-square-root seed and one FP64 Newton step (relative
+//             error ~1e-14); FP64 products.  Used by the mixed matvec on the
+//             coarse levels, whose rounding errors the nested interpolation
+//             operators of all finer levels amplify.
+enum { M_F32 = 0, M_F64 = 1, M_F64R = 2 };
+
+template <int KIND, int MODE>
+__device__ inline double kv_refined(double d2, double prm)
 {
-    using T4 = typename V4<T>::type;
-    __shared__ T4 src[NT];
-    __shared__ double part[NT];
+    if (KIND == NNCA_K_INV_R) {
+        double y = (double)__builtin_amdgcn_rsqf((float)d2);
+        return y * (1.5 - 0.5 * d2 * y * y);
+    }
+    return kv64<KIND>(d2, prm);
+}
+
+template <int MODE> struct M2LTypes;
+template <> struct M2LTypes<M_F32> { using C = float; using V = float4; };
+template <> struct M2LTypes<M_F64> { using C = double; using V = double4; };
+template <> struct M2LTypes<M_F64R> { using C = double; using V = double4; };
+
+// transverse pass at one level: u^{B,i} = sum_{B' in IL(B)} K(t^{B,i}, t^{B',i}) w^{B',o}.
+// Launched with nc * P workgroups: part p of a cell takes the p-th of P equal
+// slices of its source list; with P > 1 the partial vectors go to `part_out`
+// (P x npiv) and are added in a fixed order by k_sum_parts.
+template <int KIND, int MODE, int TILE>
+__global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
+                                            const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
+                                            const int32_t *ilsum,
+                                            const typename M2LTypes<MODE>::C *pc, int64_t npiv,
+                                            const int32_t *coord, float h, int d, const double *w, double *u,
+                                            double *part_out, double prm64)
+{
+    using T = typename M2LTypes<MODE>::C;
+    using T4 = typename M2LTypes<MODE>::V;
+    constexpr int SPT = TILE / NT;   // sources loaded per thread per tile
+    __shared__ T4 src[TILE];
+    __shared__ double part[NT * RB];
     const int t = threadIdx.x;
-    const int64_t c = blockIdx.x;
+    const int64_t c = blockIdx.x / P;
+    const int pp = blockIdx.x % P;
     const int32_t kk = k[c], po = piv_ptr[c], S = ilsum[c];
+    const int32_t sb = (int32_t)(((int64_t)S * pp) / P), se = (int32_t)(((int64_t)S * (pp + 1)) / P);
     const int32_t e0 = il_ptr[c], e1 = il_ptr[c + 1];
-    const bool local = sizeof(T) == 4;
+    const T prm = (T)prm64;
     int32_t cc[3] = {coord[c], coord[nc + c], d == 3 ? coord[2 * nc + c] : 0};
-    for (int32_t tb = 0; tb < kk; tb += NT) {
-        TargetSplit sp(kk, tb, t);
+    double *dst = P > 1 ? part_out + (int64_t)pp * npiv : u;
+    for (int32_t tb = 0; tb < kk; tb += NT * RB) {
+        Split sp(kk, tb, t);
         const bool act = sp.g < sp.G;
-        T tx = 0, ty = 0, tz = 0;
-        if (act) {
-            int32_t q = po + tb + sp.ti;
-            tx = pc[q];
-            ty = pc[npiv + q];
-            tz = d == 3 ? pc[2 * npiv + q] : T(0);
+        T tx[RB], ty[RB], tz[RB];
+        double acc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; r++) {
+            int32_t i = sp.ti + r * sp.tpg;
+            i = i < sp.cnt ? i : sp.cnt - 1;
+            int32_t q = po + tb + i;
+            tx[r] = pc[q];
+            ty[r] = pc[npiv + q];
+            tz[r] = d == 3 ? pc[2 * npiv + q] : T(0);
+            acc[r] = 0.0;
         }
-        double acc = 0;
+        // first list entry holding source sb
         int32_t e = e0;
-        for (int32_t s0 = 0; s0 < S; s0 += NT) {
-            int32_t s = s0 + t;
-            T4 v;
-            v.x = 0; v.y = 0; v.z = 0; v.w = 0;
-            if (s < S) {
-                while (e + 1 < e1 && ilpre[e + 1] <= s) e++;
-                int32_t b = il[e];
-                int32_t idx = piv_ptr[b] + (s - ilpre[e]);
-                v.x = pc[idx];
-                v.y = pc[npiv + idx];
-                v.z = d == 3 ? pc[2 * npiv + idx] : T(0);
-                v.w = w[idx];
-                if (local) {
-                    v.x += (T)(coord[b] - cc[0]) * h;
-                    v.y += (T)(coord[nc + b] - cc[1]) * h;
-                    if (d == 3) v.z += (T)(coord[2 * nc + b] - cc[2]) * h;
+        {
+            int32_t lo = e0, hi = e1 - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (ilpre[mid] <= sb) lo = mid; else hi = mid - 1;
+            }
+            e = lo;
+        }
+        for (int32_t s0 = sb; s0 < se; s0 += TILE) {
+            T4 v[SPT];
+#pragma unroll
+            for (int q = 0; q < SPT; q++) {
+                int32_t s = s0 + q * NT + t;
+                v[q].x = 0; v[q].y = 0; v[q].z = 0; v[q].w = 0;
+                if (s < se) {
+                    while (e + 1 < e1 && ilpre[e + 1] <= s) e++;
+                    int32_t b = il[e];
+                    int32_t idx = piv_ptr[b] + (s - ilpre[e]);
+                    v[q].x = pc[idx];
+                    v[q].y = pc[npiv + idx];
+                    v[q].z = d == 3 ? pc[2 * npiv + idx] : T(0);
+                    v[q].w = (T)w[idx];
+                    if (MODE == M_F32) {
+                        v[q].x += (T)(coord[b] - cc[0]) * h;
+                        v[q].y += (T)(coord[nc + b] - cc[1]) * h;
+                        if (d == 3) v[q].z += (T)(coord[2 * nc + b] - cc[2]) * h;
+                    }
                 }
             }
             __syncthreads();
-            src[t] = v;
+#pragma unroll
+            for (int q = 0; q < SPT; q++) src[q * NT + t] = v[q];
             __syncthreads();
-            int32_t ns = S - s0 < NT ? S - s0 : NT;
+            int32_t ns = se - s0 < TILE ? se - s0 : TILE;
             if (act) {
-                // short sums in T, folded into the FP64 accumulator every CHUNK terms
-                for (int32_t j = sp.g; j < ns;) {
-                    int32_t je = j + CHUNK * sp.G < ns ? j + CHUNK * sp.G : ns;
-                    T a = 0;
-#pragma unroll 4
-                    for (; j < je; j += sp.G) {
-                        T4 q = src[j];
-                        T dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
-                        T d2 = dx * dx + dy * dy + dz * dz;
-                        a += kv<KIND, T>(d2, prm) * q.w;
+                if (MODE == M_F32) {
+                    for (int32_t j = sp.g; j < ns;) {
+                        int32_t je = j + CHUNK * sp.G < ns ? j + CHUNK * sp.G : ns;
+                        T a[RB];
+#pragma unroll
+                        for (int r = 0; r < RB; r++) a[r] = T(0);
+                        for (; j < je; j += sp.G) {
+                            T4 q = src[j];
+#pragma unroll
+                            for (int r = 0; r < RB; r++) {
+                                T dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
+                                T d2 = dx * dx + dy * dy + dz * dz;
+                                a[r] += kv<KIND, T>(d2, prm) * q.w;
+                            }
+                        }
+#pragma unroll
+                        for (int r = 0; r < RB; r++) acc[r] += (double)a[r];
                     }
-                    acc += (double)a;
+                } else {
+                    for (int32_t j = sp.g; j < ns; j += sp.G) {
+                        T4 q = src[j];
+#pragma unroll
+                        for (int r = 0; r < RB; r++) {
+                            double dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
+                            double d2 = dx * dx + dy * dy + dz * dz;
+                            double kvv = MODE == M_F64 ? kv64<KIND>(d2, prm64) : kv_refined<KIND, MODE>(d2, prm64);
+                            acc[r] += kvv * q.w;
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
-        part[t] = acc;
+        if (act)
+#pragma unroll
+            for (int r = 0; r < RB; r++) part[(sp.g * sp.tpg + sp.ti) * RB + r] = acc[r];
         __syncthreads();
-        if (t < sp.cnt) {
-            double sum = part[t];
-            for (int gg = 1; gg < sp.G; gg++) sum += part[gg * sp.cnt + t];
-            u[po + tb + t] = (T)sum;
+        for (int32_t i = t; i < sp.cnt; i += NT) {
+            int32_t ti = i % sp.tpg, r = i / sp.tpg;
+            double sum = 0.0;
+            for (int gg = 0; gg < sp.G; gg++) sum += part[(gg * sp.tpg + ti) * RB + r];
+            dst[po + tb + i] = sum;
         }
         __syncthreads();
     }
 }
 
+// u = sum over p of the P partial vectors, in order p = 0, 1, ...
+__global__ void k_sum_parts(int64_t npiv, int P, const double *part, double *u)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= npiv) return;
+    double s = 0.0;
+    for (int p = 0; p < P; p++) s += part[(int64_t)p * npiv + i];
+    u[i] = s;
+}
+
 // near field of one leaf plus the combine: y = far + sum_{B' in N(B)} K x.
-// Mixed: weights x_hi and x_lo, results added in FP64.
+// Coordinates are FP64 in both precisions; the mixed path rounds the FP64
+// coordinate differences to FP32 and evaluates K and the products in FP32
+// on the split weights x_hi, x_lo (close pairs would otherwise lose their
+// relative accuracy to the rounding of the coordinates themselves).  The far
+// field and the partial results are added in FP64.
 template <typename T, int KIND>
 __global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, const int32_t *count,
                                             const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
-                                            const int32_t *nbsum, const T *pts, int64_t n, const int32_t *coord,
-                                            T h, int d, const T *xw, const T *xw2, const T *far,
+                                            const int32_t *nbsum, const double *pts, int64_t n, int d,
+                                            const T *xw, const T *xw2, const double *far,
                                             const int32_t *order, double *y, T prm)
 {
-    using T4 = typename V4<T>::type;
-    __shared__ T4 src[NT];
-    __shared__ T src2[NT];
-    __shared__ double part[NT], part2[NT];
+    struct Src {
+        double x, y, z;
+        T w, w2;
+    };
+    __shared__ Src src[NT];
+    __shared__ double part[NT * RB], part2[NT * RB];
     const int t = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int32_t kk = count[c], po = first[c], S = nbsum[c];
     const int32_t e0 = nb_ptr[c], e1 = nb_ptr[c + 1];
     const bool mixed = sizeof(T) == 4;
-    int32_t cc[3] = {coord[c], coord[nc + c], d == 3 ? coord[2 * nc + c] : 0};
-    for (int32_t tb = 0; tb < kk; tb += NT) {
-        TargetSplit sp(kk, tb, t);
+    for (int32_t tb = 0; tb < kk; tb += NT * RB) {
+        Split sp(kk, tb, t);
         const bool act = sp.g < sp.G;
-        T tx = 0, ty = 0, tz = 0;
-        if (act) {
-            int32_t q = po + tb + sp.ti;
-            tx = pts[q];
-            ty = pts[n + q];
-            tz = d == 3 ? pts[2 * n + q] : T(0);
+        double tx[RB], ty[RB], tz[RB];
+        double acc[RB], acc2[RB];
+#pragma unroll
+        for (int r = 0; r < RB; r++) {
+            int32_t i = sp.ti + r * sp.tpg;
+            i = i < sp.cnt ? i : sp.cnt - 1;
+            int32_t q = po + tb + i;
+            tx[r] = pts[q];
+            ty[r] = pts[n + q];
+            tz[r] = d == 3 ? pts[2 * n + q] : 0.0;
+            acc[r] = 0.0;
+            acc2[r] = 0.0;
         }
-        double acc = 0, acc2 = 0;
         int32_t e = e0;
         for (int32_t s0 = 0; s0 < S; s0 += NT) {
             int32_t s = s0 + t;
-            T4 v;
-            v.x = 0; v.y = 0; v.z = 0; v.w = 0;
-            T v2 = 0;
+            Src v;
+            v.x = 0; v.y = 0; v.z = 0; v.w = 0; v.w2 = 0;
             if (s < S) {
                 while (e + 1 < e1 && nbpre[e + 1] <= s) e++;
-                int32_t b = nb[e];
-                int32_t idx = first[b] + (s - nbpre[e]);
+                int32_t idx = first[nb[e]] + (s - nbpre[e]);
                 v.x = pts[idx];
                 v.y = pts[n + idx];
-                v.z = d == 3 ? pts[2 * n + idx] : T(0);
+                v.z = d == 3 ? pts[2 * n + idx] : 0.0;
                 v.w = xw[idx];
-                if (mixed) {
-                    v2 = xw2[idx];
-                    v.x += (T)(coord[b] - cc[0]) * h;
-                    v.y += (T)(coord[nc + b] - cc[1]) * h;
-                    if (d == 3) v.z += (T)(coord[2 * nc + b] - cc[2]) * h;
-                }
+                if (mixed) v.w2 = xw2[idx];
             }
             __syncthreads();
             src[t] = v;
-            src2[t] = v2;
             __syncthreads();
             int32_t ns = S - s0 < NT ? S - s0 : NT;
             if (act) {
                 for (int32_t j = sp.g; j < ns;) {
                     int32_t je = j + CHUNK * sp.G < ns ? j + CHUNK * sp.G : ns;
-                    T a = 0, a2 = 0;
-#pragma unroll 4
+                    T a[RB], a2[RB];
+#pragma unroll
+                    for (int r = 0; r < RB; r++) { a[r] = T(0); a2[r] = T(0); }
                     for (; j < je; j += sp.G) {
-                        T4 q = src[j];
-                        T dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
-                        T d2 = dx * dx + dy * dy + dz * dz;
-                        T kvv = kv_self<KIND, T>(d2, prm);
-                        a += kvv * q.w;
-                        if (mixed) a2 += kvv * src2[j];
+                        const Src q = src[j];
+#pragma unroll
+                        for (int r = 0; r < RB; r++) {
+                            T dx = (T)(tx[r] - q.x), dy = (T)(ty[r] - q.y), dz = (T)(tz[r] - q.z);
+                            T d2 = dx * dx + dy * dy + dz * dz;
+                            T kvv = kv_self<KIND, T>(d2, prm);
+                            a[r] += kvv * q.w;
+                            if (mixed) a2[r] += kvv * q.w2;
+                        }
                     }
-                    acc += (double)a;
-                    acc2 += (double)a2;
+#pragma unroll
+                    for (int r = 0; r < RB; r++) {
+                        acc[r] += (double)a[r];
+                        acc2[r] += (double)a2[r];
+                    }
                 }
             }
         }
         __syncthreads();
-        part[t] = acc;
-        part2[t] = acc2;
-        __syncthreads();
-        if (t < sp.cnt) {
-            double s1 = part[t], s2 = part2[t];
-            for (int gg = 1; gg < sp.G; gg++) {
-                s1 += part[gg * sp.cnt + t];
-                s2 += part2[gg * sp.cnt + t];
+        if (act)
+#pragma unroll
+            for (int r = 0; r < RB; r++) {
+                part[(sp.g * sp.tpg + sp.ti) * RB + r] = acc[r];
+                part2[(sp.g * sp.tpg + sp.ti) * RB + r] = acc2[r];
             }
-            int32_t p = po + tb + t;
-            double f = far ? (double)far[p] : 0.0;
-            y[order[p]] = mixed ? (f + s1) + s2 : f + s1;
+        __syncthreads();
+        for (int32_t i = t; i < sp.cnt; i += NT) {
+            int32_t ti = i % sp.tpg, r = i / sp.tpg;
+            double s1 = 0.0, s2 = 0.0;
+            for (int gg = 0; gg < sp.G; gg++) {
+                s1 += part[(gg * sp.tpg + ti) * RB + r];
+                s2 += part2[(gg * sp.tpg + ti) * RB + r];
+            }
+            int32_t p = po + tb + i;
+            double f = far ? far[p] : 0.0;
+            y[order[p]] = (f + s1) + s2;
         }
         __syncthreads();
     }
@@ -366,12 +533,6 @@ __global__ void k_list_prefix(int64_t nc, const int32_t *ptr, const int32_t *lst
     sum[c] = s;
 }
 
-__global__ void k_diff(int64_t nc, const int32_t *ptr, int32_t *out)
-{
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c < nc) out[c] = ptr[c + 1] - ptr[c];
-}
-
 // FP64 coordinates of the pivots and their FP32 offsets from the cell centre
 __global__ void k_pivot_coords(int64_t nc, const int32_t *piv_ptr, const int32_t *piv_id, const double *P,
                                int64_t n, int d, const int32_t *coord, double lo0, double lo1, double lo2,
@@ -390,45 +551,80 @@ __global__ void k_pivot_coords(int64_t nc, const int32_t *piv_ptr, const int32_t
     }
 }
 
-__global__ void k_point_local(int64_t nc, const int32_t *first, const int32_t *count, const double *P, int64_t n,
-                              int d, const int32_t *coord, double lo0, double lo1, double lo2, double h, float *out)
+// owner cell of every entry of a CSR range array
+__global__ void k_fill_owner(int64_t nc, const int32_t *ptr, int32_t *owner)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    for (int32_t e = ptr[c]; e < ptr[c + 1]; e++) owner[e] = (int32_t)c;
+}
+
+// per-cell (m-k) x k blocks -> k x (m-k)
+__global__ void k_transpose_blocks(int64_t nc, const int32_t *piv_ptr, const int32_t *rem_ptr,
+                                   const int64_t *crem_off, const double *a, double *at)
 {
     int64_t c = blockIdx.x;
-    double lo[3] = {lo0, lo1, lo2};
-    for (int32_t q = first[c] + threadIdx.x; q < first[c] + count[c]; q += blockDim.x)
-        for (int a = 0; a < 3; a++) {
-            double ctr = a < d ? lo[a] + ((double)coord[a * nc + c] + 0.5) * h : 0.0;
-            out[a * n + q] = a < d ? (float)(P[a * n + q] - ctr) : 0.0f;
+    int32_t kk = piv_ptr[c + 1] - piv_ptr[c], nr = rem_ptr[c + 1] - rem_ptr[c];
+    const double *src = a + crem_off[c];
+    double *dst = at + crem_off[c];
+    for (int32_t e = threadIdx.x; e < kk * nr; e += blockDim.x) {
+        int32_t r = e / kk, q = e % kk;
+        dst[(int64_t)q * nr + r] = src[e];
+    }
+}
+
+// Sources per LDS tile: long inner loops also for cells with few targets.
+constexpr int M2L_TILE = 4 * NT;
+
+// Split factor: enough workgroups to fill the chip on levels with few cells.
+static int m2l_parts(const nnca::Level &L)
+{
+    const int64_t want = 4096;
+    if (L.ncell >= want) return 1;
+    int64_t P = (want + L.ncell - 1) / L.ncell;
+    int64_t maxp = (L.max_ilsum + 1023) / 1024;   // keep at least ~1k sources per part
+    if (P > maxp) P = maxp;
+    if (P > 64) P = 64;
+    return P < 1 ? 1 : (int)P;
+}
+
+template <int MODE, typename C>
+static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C *pc, double prm, hipStream_t s)
+{
+    const int64_t nc = L.ncell;
+    const int P = m2l_parts(L);
+    double *part = nullptr;
+    if (P > 1) {
+        if (H->m2l_part_cap < (int64_t)P * L.npiv) {
+            dfree(H->m2l_part);
+            H->m2l_part = nullptr;
+            H->m2l_part = dalloc<double>((int64_t)P * L.npiv);
+            H->m2l_part_cap = (int64_t)P * L.npiv;
         }
-}
-
-__global__ void k_to_f32(int64_t n, const double *a, float *b)
-{
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
-}
-
-template <typename T>
-void launch_m2l(int kind, const nnca::Level &L, const T *pc, int d, const T *w, T *u, T prm, hipStream_t s)
-{
-    int64_t nc = L.ncell;
-    T h = (T)L.h;
-#define M2L_CASE(K) k_m2l<T, K><<<(int)nc, NT, 0, s>>>(nc, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, L.coord, h, d, w, u, prm)
-    if (kind == NNCA_K_INV_R) M2L_CASE(NNCA_K_INV_R);
-    else if (kind == NNCA_K_LOG_R) M2L_CASE(NNCA_K_LOG_R);
-    else M2L_CASE(NNCA_K_GAUSS);
+        part = H->m2l_part;
+    }
+    const int g = (int)(nc * P);
+#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, L.coord, (float)L.h, H->dim, L.w64, L.u64, part, prm
+#define M2L_CASE(K) k_m2l<K, MODE, M2L_TILE><<<g, NT, 0, s>>>(M2L_ARGS);
+    if (kind == NNCA_K_INV_R) { M2L_CASE(NNCA_K_INV_R) }
+    else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }
+    else { M2L_CASE(NNCA_K_GAUSS) }
 #undef M2L_CASE
+#undef M2L_ARGS
     HIPCHECK(hipGetLastError());
+    if (P > 1) {
+        k_sum_parts<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, P, part, L.u64);
+        HIPCHECK(hipGetLastError());
+    }
 }
 
 template <typename T>
-void launch_p2p(int kind, nnca_h2 *H, const T *pts, const T *xw, const T *xw2, const T *far, double *y, T prm,
+void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *far, double *y, T prm,
                 hipStream_t s)
 {
     const nnca::Level &L = H->lev[H->kappa];
     int64_t nc = L.ncell;
-    T h = (T)L.h;
-#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(nc, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, pts, H->n, L.coord, h, H->dim, xw, xw2, far, H->order, y, prm)
+#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(nc, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
     if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
     else P2P_CASE(NNCA_K_GAUSS);
@@ -459,51 +655,58 @@ struct Span {
     }
 };
 
+// One right-hand side.  xs64: x in tree order (FP64).  Mixed: x_hi, x_lo.
+// The transfer passes run in FP64 for both precisions; the M2L and near-field
+// kernels run in T.
 template <typename T>
-void one_column(nnca_h2 *H, const T *xin, const T *xin2, double *y, hipStream_t s)
+void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, double *y, hipStream_t s)
 {
     const bool f32 = sizeof(T) == 4;
     const int kap = H->kappa, lmin = H->lmin;
     const T prm = H->kind == NNCA_K_GAUSS ? (f32 ? (T)(1.4426950408889634 / (H->hparam * H->hparam))
                                                  : (T)(1.0 / (H->hparam * H->hparam)))
                                           : T(0);
-    T *far = nullptr;
+    double *far = nullptr;
     if (kap >= lmin) {
         // upward pass
         for (int l = kap; l >= lmin; l--) {
             nnca::Level &L = H->lev[l];
-            const T *src = (l == kap) ? xin : (f32 ? (const T *)H->lev[l + 1].w32 : (const T *)H->lev[l + 1].w64);
-            T *w = f32 ? (T *)L.w32 : (T *)L.w64;
-            const T *cr = f32 ? (const T *)L.crem32 : (const T *)L.crem64;
+            const double *src = (l == kap) ? xs64 : H->lev[l + 1].w64;
             Span sp(H, s, PASS_UP, l);
-            k_up<T><<<(int)L.ncell, 64, 0, s>>>(L.ncell, L.m, L.k, L.tt_off, L.piv_ptr, L.ipos, L.rem_ptr, L.rem_pos,
-                                                L.crem_off, cr, src, w);
+            if (L.nrem == 0)
+                k_up<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, L.piv_cell, L.piv_ptr, L.tt_off, L.ipos,
+                                                           L.rem_ptr, L.rem_pos, L.crem_off, L.crem64, src, L.w64);
+            else
+                k_up_cell<<<(int)L.ncell, 256, 0, s>>>(L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off,
+                                                       L.crem64, src, L.w64);
             HIPCHECK(hipGetLastError());
         }
-        // transverse pass
+        // transverse pass; the mixed matvec keeps the coarse levels
+        // (l <= kappa - 2) in refined FP64 arithmetic
+        const double prm64 = 1.0 / (H->hparam * H->hparam);
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
             Span sp(H, s, PASS_M2L, l);
-            if (f32) launch_m2l<T>(H->kind, L, (const T *)L.pc32, H->dim, (const T *)L.w32, (T *)L.u32, prm, s);
-            else launch_m2l<T>(H->kind, L, (const T *)L.pc64, H->dim, (const T *)L.w64, (T *)L.u64, prm, s);
+            if (!f32) launch_m2l_mode<M_F64>(H->kind, H, L, L.pc64, prm64, s);
+            else if (l <= kap - 2) launch_m2l_mode<M_F64R>(H->kind, H, L, L.pc64, prm64, s);
+            else launch_m2l_mode<M_F32>(H->kind, H, L, L.pc32, (double)prm, s);
         }
         // downward pass
-        far = f32 ? (T *)H->far32 : (T *)H->far64;
+        far = H->far64;
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
-            const T *cr = f32 ? (const T *)L.crem32 : (const T *)L.crem64;
-            const T *u = f32 ? (const T *)L.u32 : (const T *)L.u64;
-            T *out = (l == kap) ? far : (f32 ? (T *)H->lev[l + 1].u32 : (T *)H->lev[l + 1].u64);
+            double *out = (l == kap) ? far : H->lev[l + 1].u64;
             Span sp(H, s, PASS_DOWN, l);
-            k_down<T><<<(int)L.ncell, 64, 0, s>>>(L.ncell, L.k, L.tt_off, L.piv_ptr, L.ipos, L.rem_ptr, L.rem_pos,
-                                                  L.crem_off, cr, u, out, l == kap ? 0 : 1);
+            k_down<<<grid_for(L.npiv + L.nrem, 256), 256, 0, s>>>(L.npiv, L.nrem, L.piv_cell, L.rem_cell, L.piv_ptr,
+                                                                  L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off,
+                                                                  L.crem_t, L.u64, out, l == kap ? 0 : 1);
             HIPCHECK(hipGetLastError());
         }
     }
     // near field and combine
     Span sp(H, s, PASS_P2P, kap);
-    if (f32) launch_p2p<T>(H->kind, H, (const T *)H->pts32, xin, xin2, far, y, prm, s);
-    else launch_p2p<T>(H->kind, H, (const T *)H->pts64, xin, nullptr, far, y, prm, s);
+    if (f32) launch_p2p<T>(H->kind, H, xhi, xlo, far, y, prm, s);
+    else launch_p2p<T>(H->kind, H, (const T *)xs64, nullptr, far, y, prm, s);
 }
 
 }  // namespace
@@ -520,24 +723,31 @@ void prepare_apply(nnca_h2 *H)
         L.pc32 = dalloc<float>(3 * L.npiv);
         k_pivot_coords<<<(int)nc, 64, 0, s>>>(nc, L.piv_ptr, L.piv_id, H->pts64, H->n, d, L.coord, H->lo[0], H->lo[1],
                                               H->lo[2], L.h, L.npiv, L.pc64, L.pc32);
-        L.crem32 = dalloc<float>(L.ncrem);
-        if (L.ncrem) k_to_f32<<<grid_for(L.ncrem, 256), 256, 0, s>>>(L.ncrem, L.crem64, L.crem32);
+        int32_t nrem = 0;
+        HIPCHECK(hipMemcpy(&nrem, L.rem_ptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost));
+        L.nrem = nrem;
+        L.piv_cell = dalloc<int32_t>(L.npiv);
+        L.rem_cell = dalloc<int32_t>(L.nrem);
+        k_fill_owner<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.piv_ptr, L.piv_cell);
+        k_fill_owner<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.rem_ptr, L.rem_cell);
+        L.crem_t = dalloc<double>(L.ncrem);
+        if (L.ncrem) k_transpose_blocks<<<(int)nc, 256, 0, s>>>(nc, L.piv_ptr, L.rem_ptr, L.crem_off, L.crem64, L.crem_t);
         L.ilpre = dalloc<int32_t>(L.nil);
         L.ilsum = dalloc<int32_t>(nc);
         k_list_prefix<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.il_ptr, L.il, L.k, L.ilpre, L.ilsum);
         L.w64 = dalloc<double>(L.npiv);
         L.u64 = dalloc<double>(L.npiv);
-        L.w32 = dalloc<float>(L.npiv);
-        L.u32 = dalloc<float>(L.npiv);
         HIPCHECK(hipGetLastError());
         std::vector<int32_t> ils(nc);
         HIPCHECK(hipMemcpyAsync(ils.data(), L.ilsum, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         L.max_ilsum = 0;
+        L.m2l_inter = 0;
         for (int64_t c = 0; c < nc; c++) {
-            m2l += (int64_t)L.h_k[c] * ils[c];
+            L.m2l_inter += (int64_t)L.h_k[c] * ils[c];
             L.max_ilsum = std::max(L.max_ilsum, ils[c]);
         }
+        m2l += L.m2l_inter;
         trans += L.ncrem;
     }
     Level &F = H->lev[H->kappa];
@@ -546,9 +756,6 @@ void prepare_apply(nnca_h2 *H)
     H->nbpre = dalloc<int32_t>(F.nnb);
     H->nbsum = dalloc<int32_t>(nc);
     k_list_prefix<<<grid_for(nc, 256), 256, 0, s>>>(nc, F.nb_ptr, F.nb, cnt, H->nbpre, H->nbsum);
-    H->pts32 = dalloc<float>(3 * H->n);
-    k_point_local<<<(int)nc, 64, 0, s>>>(nc, F.first, F.count, H->pts64, H->n, d, F.coord, H->lo[0], H->lo[1],
-                                         H->lo[2], F.h, H->pts32);
     HIPCHECK(hipGetLastError());
     std::vector<int32_t> nbs(nc), hc(nc);
     HIPCHECK(hipMemcpyAsync(nbs.data(), H->nbsum, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
@@ -567,7 +774,6 @@ void prepare_apply(nnca_h2 *H)
     H->far64 = dalloc<double>(H->n);
     H->xhi = dalloc<float>(H->n);
     H->xlo = dalloc<float>(H->n);
-    H->far32 = dalloc<float>(H->n);
 }
 
 void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
@@ -580,17 +786,17 @@ void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ld
         if (precision == NNCA_PREC_MIXED) {
             {
                 Span sp(H, s, PASS_GATHER, -1);
-                k_gather_split<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xhi, H->xlo);
+                k_gather_split<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64, H->xhi, H->xlo);
                 HIPCHECK(hipGetLastError());
             }
-            one_column<float>(H, H->xhi, H->xlo, y, s);
+            one_column<float>(H, H->xs64, H->xhi, H->xlo, y, s);
         } else {
             {
                 Span sp(H, s, PASS_GATHER, -1);
                 k_gather64<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64);
                 HIPCHECK(hipGetLastError());
             }
-            one_column<double>(H, H->xs64, nullptr, y, s);
+            one_column<double>(H, H->xs64, nullptr, nullptr, y, s);
         }
     }
 }

@@ -70,17 +70,20 @@ struct Level {
     int64_t *crem_off = nullptr;     // ncell + 1: offsets of each cell's block in crem
     int64_t ncrem = 0;
     double *crem64 = nullptr;        // non-identity rows of C_B, (m - k) x k row-major
-    float *crem32 = nullptr;
+    double *crem_t = nullptr;        //   the same blocks transposed, k x (m - k)
+    int64_t nrem = 0;                // rows of t~ that are not pivots, over the level
+    int32_t *piv_cell = nullptr;     // owning cell of every pivot
+    int32_t *rem_cell = nullptr;     // owning cell of every non-pivot row
     double *pc64 = nullptr;          // pivot coordinates, SoA 3 x npiv (global)
     float *pc32 = nullptr;           // pivot coordinates relative to the cell centre
     int32_t *ilpre = nullptr;        // per IL entry: sources before it in the cell's list
     int32_t *ilsum = nullptr;        // per cell: M2L sources
     std::vector<int32_t> h_k, h_m;   // host copies
     int32_t max_ilsum = 0;
+    int64_t m2l_inter = 0;           // sum over IL pairs of k_B k_B' at this level
 
-    // apply state (one right-hand side at a time)
+    // apply state (one right-hand side at a time): multipole / local vectors
     double *w64 = nullptr, *u64 = nullptr;
-    float *w32 = nullptr, *u32 = nullptr;
 };
 
 struct ChunkInfo;
@@ -94,13 +97,13 @@ struct nnca_h2 {
     int64_t eta_num = 3, eta_den = 1;
     int32_t policy = 1;
     int64_t ws_budget = 0;
+    int32_t rank_reserve = 256;
     int32_t kmax = 20, kappa = 0, lmin = 1;
     double lo[3] = {0, 0, 0}, L = 0.0;
     hipStream_t stream = nullptr;
     double build_seconds = 0.0;
 
     double *pts64 = nullptr;      // 3 x n, tree order
-    float *pts32 = nullptr;       // 3 x n, relative to the leaf-cell centre
     int32_t *order = nullptr;     // tree position -> original index
     uint64_t *keys = nullptr;     // finest Morton key per tree position
     std::vector<nnca::Level> lev;
@@ -111,7 +114,9 @@ struct nnca_h2 {
 
     // matvec workspace
     double *xs64 = nullptr, *far64 = nullptr;
-    float *xhi = nullptr, *xlo = nullptr, *far32 = nullptr;
+    float *xhi = nullptr, *xlo = nullptr;
+    double *m2l_part = nullptr;   // partial M2L vectors of split launches
+    int64_t m2l_part_cap = 0;
     int64_t m2l_inter = 0, p2p_inter = 0, transfer_entries = 0;
 
     // per-launch HIP-event timing of the matvec passes (off by default)

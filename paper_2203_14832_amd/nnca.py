@@ -30,7 +30,8 @@ class NncaError(RuntimeError):
 
 class BuildOptions(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("eta2_num", C.c_int32), ("eta2_den", C.c_int32),
-                ("exhausted_policy", C.c_int32), ("workspace_bytes", C.c_int64)]
+                ("exhausted_policy", C.c_int32), ("workspace_bytes", C.c_int64), ("rank_reserve", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -39,6 +40,7 @@ class Info(C.Structure):
                 ("tol", C.c_double), ("lo", C.c_double * 3), ("side", C.c_double),
                 ("ncell", C.c_int64 * MAX_LEVELS), ("npiv", C.c_int64 * MAX_LEVELS),
                 ("nlist", (C.c_int64 * 2) * MAX_LEVELS), ("max_rank", C.c_int32 * MAX_LEVELS),
+                ("m2l_level", C.c_int64 * MAX_LEVELS),
                 ("transfer_entries", C.c_int64), ("m2l_interactions", C.c_int64),
                 ("p2p_interactions", C.c_int64), ("build_seconds", C.c_double)]
 
@@ -115,7 +117,7 @@ class H2Matrix:
 
     def __init__(self, points, kernel: str = "inv_r", tol: float = 1e-6, leaf_size: int = 64,
                  length_scale: float = 1.0, eta2=None, policy: int = 1, workspace_bytes: int = 0,
-                 device="cuda:0"):
+                 rank_reserve: int = 0, device="cuda:0"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -123,7 +125,7 @@ class H2Matrix:
         n, d = pts.shape
         self.n, self.dim, self.kernel = n, d, kernel
         soa = pts.t().contiguous().to(self.device)
-        opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes))
+        opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes), int(rank_reserve), 0)
         if eta2 is not None:
             opts.eta2_num, opts.eta2_den = int(eta2[0]), int(eta2[1])
         h = C.c_void_p()
@@ -189,7 +191,8 @@ class H2Matrix:
                     tol=inf.tol, lo=list(inf.lo)[: inf.dim], side=inf.side,
                     ncell=[inf.ncell[l] for l in range(L)], npiv=[inf.npiv[l] for l in range(L)],
                     nlist=[(inf.nlist[l][0], inf.nlist[l][1]) for l in range(L)],
-                    max_rank=[inf.max_rank[l] for l in range(L)], transfer_entries=inf.transfer_entries,
+                    max_rank=[inf.max_rank[l] for l in range(L)], m2l_level=[inf.m2l_level[l] for l in range(L)],
+                    transfer_entries=inf.transfer_entries,
                     m2l_interactions=inf.m2l_interactions, p2p_interactions=inf.p2p_interactions,
                     build_seconds=inf.build_seconds)
 
