@@ -678,6 +678,7 @@ static void build_level(nnca_h2 *H, int l)
         rpp[c + 1] = rpp[c] + nr;
         cpp[c + 1] = cpp[c] + (int64_t)nr * hk[c];
         kmx = std::max(kmx, hk[c]);
+        L.max_nrem = std::max(L.max_nrem, nr);
     }
     L.h_k = hk;
     L.max_k = kmx;

@@ -64,6 +64,7 @@ static void free_handle(nnca_h2 *H)
 {
     if (!H) return;
     clear_profile(H);
+    free_multi(H);
     for (auto &L : H->lev) {
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,

@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "nnca_internal.h"
+#include "kernel_values.h"
 
 namespace nnca {
 
@@ -30,36 +31,6 @@ constexpr int CHUNK = 16;   // terms summed in the working precision before an F
 template <typename T> struct V4;
 template <> struct V4<float> { using type = float4; };
 template <> struct V4<double> { using type = double4; };
-
-// kernel values of the apply passes
-template <int KIND>
-__device__ inline float kv32(float d2, float prm)
-{
-    if (KIND == NNCA_K_INV_R) return __builtin_amdgcn_rsqf(d2);
-    if (KIND == NNCA_K_LOG_R) return 0.5f * logf(d2);
-    return __builtin_amdgcn_exp2f(-d2 * prm);  // prm = log2(e) / h^2
-}
-template <int KIND>
-__device__ inline double kv64(double d2, double prm)
-{
-    if (KIND == NNCA_K_INV_R) return 1.0 / sqrt(d2);
-    if (KIND == NNCA_K_LOG_R) return 0.5 * log(d2);
-    return exp(-d2 * prm);  // prm = 1 / h^2
-}
-template <int KIND, typename T>
-__device__ inline T kv(T d2, T prm)
-{
-    if constexpr (sizeof(T) == 4) return kv32<KIND>(d2, prm);
-    else return kv64<KIND>(d2, prm);
-}
-// near field: 1/r and log r vanish at r = 0, the Gaussian is 1 there
-template <int KIND, typename T>
-__device__ inline T kv_self(T d2, T prm)
-{
-    T v = kv<KIND, T>(d2, prm);
-    if (KIND == NNCA_K_GAUSS) return v;
-    return d2 > T(0) ? v : T(0);
-}
 
 // ---------------------------------------------------------------------------
 // input gather (original -> tree order) and split
@@ -223,16 +194,6 @@ struct Split {
 //             coarse levels, whose rounding errors the nested interpolation
 //             operators of all finer levels amplify.
 enum { M_F32 = 0, M_F64 = 1, M_F64R = 2 };
-
-template <int KIND, int MODE>
-__device__ inline double kv_refined(double d2, double prm)
-{
-    if (KIND == NNCA_K_INV_R) {
-        double y = (double)__builtin_amdgcn_rsqf((float)d2);
-        return y * (1.5 - 0.5 * d2 * y * y);
-    }
-    return kv64<KIND>(d2, prm);
-}
 
 template <int MODE> struct M2LTypes;
 template <> struct M2LTypes<M_F32> { using C = float; using V = float4; };
@@ -779,6 +740,10 @@ void prepare_apply(nnca_h2 *H)
 void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
                 hipStream_t s)
 {
+    if (nrhs > 1) {
+        run_matvec_multi(H, X, Y, nrhs, ldx, ldy, precision, s);
+        return;
+    }
     const int64_t n = H->n;
     for (int64_t col = 0; col < nrhs; col++) {
         const double *x = X + col * ldx;

@@ -1,0 +1,628 @@
+// H2 matrix-vector product for many right-hand sides (Sec. 4 passes applied
+// to an N x R block).  Vectors are held in tree order with the R columns
+// innermost and padded to RP = 16 * NCB columns, so one source row of weights
+// is contiguous.
+//
+// Transverse pass, mixed precision, two finest levels: the kernel tile
+// K(t^{B,i}, sources) is generated in FP32 on the vector ALUs, one entry per
+// lane in the A-operand layout of v_mfma_f32_16x16x4f32, and multiplied by the
+// weight tile (4 sources x 16 columns) on the matrix cores, R/16 products per
+// generated tile; FP32 accumulators are folded into FP64 every 4 steps
+// (16 sources).
+// FP64 and the coarse levels of the mixed form use v_mfma_f64_16x16x4f64 on an
+// FP64 kernel tile; the near field uses the matrix cores as well.  Precision
+// scheme as for one column.
+#include <cstring>
+#include <algorithm>
+
+#include "nnca_internal.h"
+#include "kernel_values.h"
+
+namespace nnca {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int NT = 256;
+
+__global__ void k_gather_multi(int64_t n, int R, int RP, const int32_t *order, const double *X, int64_t ldx,
+                               double *xs, float *hi, float *lo)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * RP) return;
+    int64_t p = i / RP;
+    int c = (int)(i % RP);
+    double v = c < R ? X[(int64_t)c * ldx + order[p]] : 0.0;
+    xs[i] = v;
+    if (hi) {
+        float h = (float)v;
+        hi[i] = h;
+        lo[i] = (float)(v - (double)h);
+    }
+}
+
+// upward pass for RP columns: w = C_B^T x~, one workgroup per cell; the rows
+// of x~ that are not pivots are staged in LDS 32 at a time
+constexpr int XT = 32;
+__global__ __launch_bounds__(NT) void k_up_multi(int RP, const int32_t *piv_ptr, const int32_t *tt_off,
+                                                 const int32_t *ipos, const int32_t *rem_ptr, const int32_t *rem_pos,
+                                                 const int64_t *crem_off, const double *crem, const double *xin,
+                                                 double *w)
+{
+    __shared__ double xr[XT * 64];
+    const int64_t c = blockIdx.x;
+    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
+    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    const double *C = crem + crem_off[c];
+    for (int32_t e0 = blockIdx.y * NT; e0 < kk * RP; e0 += NT * gridDim.y) {
+        const int32_t e = e0 + threadIdx.x;
+        const bool act = e < kk * RP;
+        const int32_t q = act ? e / RP : 0, col = e % RP;
+        double acc = act ? xin[(int64_t)(to + ipos[po + q]) * RP + col] : 0.0;
+        double a1 = 0.0;
+        for (int32_t r0 = 0; r0 < nr; r0 += XT) {
+            const int32_t rn = nr - r0 < XT ? nr - r0 : XT;
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < rn * RP; i += NT)
+                xr[i] = xin[(int64_t)(to + rem_pos[ro + r0 + i / RP]) * RP + i % RP];
+            __syncthreads();
+            if (act) {
+                const double *Cq = C + (int64_t)r0 * kk + q;
+                int32_t r = 0;
+                for (; r + 1 < rn; r += 2) {
+                    acc += Cq[(int64_t)r * kk] * xr[r * RP + col];
+                    a1 += Cq[(int64_t)(r + 1) * kk] * xr[(r + 1) * RP + col];
+                }
+                if (r < rn) acc += Cq[(int64_t)r * kk] * xr[r * RP + col];
+            }
+        }
+        if (act) w[(int64_t)(po + q) * RP + col] = acc + a1;
+    }
+}
+
+// downward pass for RP columns: the stacked C_B u added to the children (L2L)
+// or written as the far field of the leaf's points (L2P); u staged in LDS
+__global__ __launch_bounds__(NT) void k_down_multi(int RP, const int32_t *piv_ptr, const int32_t *tt_off,
+                                                   const int32_t *ipos, const int32_t *rem_ptr,
+                                                   const int32_t *rem_pos, const int64_t *crem_off,
+                                                   const double *crem, const double *u, double *out, int accumulate)
+{
+    __shared__ double ur[XT * 64];
+    const int64_t c = blockIdx.x;
+    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
+    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    const double *C = crem + crem_off[c];
+    for (int32_t e = blockIdx.y * NT + threadIdx.x; e < kk * RP; e += NT * gridDim.y) {
+        int32_t q = e / RP, col = e % RP;
+        int64_t dst = (int64_t)(to + ipos[po + q]) * RP + col;
+        double v = u[(int64_t)(po + q) * RP + col];
+        out[dst] = accumulate ? out[dst] + v : v;
+    }
+    for (int32_t e0 = blockIdx.y * NT; e0 < nr * RP; e0 += NT * gridDim.y) {
+        const int32_t e = e0 + threadIdx.x;
+        const bool act = e < nr * RP;
+        const int32_t r = act ? e / RP : 0, col = e % RP;
+        const double *row = C + (int64_t)r * kk;
+        double acc = 0.0, a1 = 0.0;
+        for (int32_t q0 = 0; q0 < kk; q0 += XT) {
+            const int32_t qn = kk - q0 < XT ? kk - q0 : XT;
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < qn * RP; i += NT) ur[i] = u[(int64_t)(po + q0) * RP + i];
+            __syncthreads();
+            if (act) {
+                int32_t q = 0;
+                for (; q + 1 < qn; q += 2) {
+                    acc += row[q0 + q] * ur[q * RP + col];
+                    a1 += row[q0 + q + 1] * ur[(q + 1) * RP + col];
+                }
+                if (q < qn) acc += row[q0 + q] * ur[q * RP + col];
+            }
+        }
+        if (act) {
+            acc += a1;
+            int64_t dst = (int64_t)(to + rem_pos[ro + r]) * RP + col;
+            out[dst] = accumulate ? out[dst] + acc : acc;
+        }
+    }
+}
+
+// index of the interaction-list entry holding source s of the cell (the
+// largest e in [e0, e1) with pre[e] <= s)
+__device__ inline int32_t list_entry(const int32_t *pre, int32_t e0, int32_t e1, int32_t s)
+{
+    int32_t lo = e0, hi = e1 - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// M2L, FP32 on the matrix cores.  Four wavefronts; each takes one block of 16
+// targets (or, with fewer than four blocks, a phase of the 4-source steps).
+template <int KIND, int NCB>
+__global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
+                                                 const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
+                                                 const int32_t *ilsum, const float *pc, int64_t npiv,
+                                                 const int32_t *coord, float h, int d, const double *w, double *u,
+                                                 double *part_out, float prm)
+{
+    constexpr int RP = NCB * 16;
+    constexpr int TS = 128;
+    constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
+    __shared__ float4 sx[TS];
+    __shared__ int32_t sidx[TS];
+    __shared__ double swt_raw[TS * SW / 2 > NT * NCB * 4 ? TS * SW / 2 : NT * NCB * 4];
+    float *swt = reinterpret_cast<float *>(swt_raw);
+    double *red = swt_raw;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int64_t c = blockIdx.x / P;
+    const int pp = blockIdx.x % P;
+    const int32_t kk = k[c], po = piv_ptr[c], S = ilsum[c];
+    const int32_t sb = (int32_t)(((int64_t)S * pp) / P), se = (int32_t)(((int64_t)S * (pp + 1)) / P);
+    const int32_t e0 = il_ptr[c], e1 = il_ptr[c + 1];
+    const int32_t cc0 = coord[c], cc1 = coord[nc + c], cc2 = d == 3 ? coord[2 * nc + c] : 0;
+    double *dst = P > 1 ? part_out + (int64_t)pp * npiv * RP : u;
+    const int32_t ntb = (kk + 15) / 16;
+    for (int32_t tb0 = 0; tb0 < ntb; tb0 += 4) {
+        const int nb = ntb - tb0 < 4 ? ntb - tb0 : 4;
+        const int nph = 4 / nb;
+        const int myb = wave % nb, ph = wave / nb;
+        const bool wact = ph < nph;
+        const int32_t tb = tb0 + myb;
+        int32_t row = tb * 16 + (lane & 15);
+        int32_t rc = row < kk ? row : kk - 1;
+        const float tx = pc[po + rc], ty = pc[npiv + po + rc], tz = d == 3 ? pc[2 * npiv + po + rc] : 0.f;
+        floatx4 accf[NCB];
+        double accd[NCB][4];
+#pragma unroll
+        for (int b = 0; b < NCB; b++) {
+            accf[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < 4; i++) accd[b][i] = 0.0;
+        }
+        for (int32_t s0 = sb; s0 < se; s0 += TS) {
+            const int32_t ns = se - s0 < TS ? se - s0 : TS;
+            __syncthreads();
+            if (t < ns) {
+                int32_t s = s0 + t;
+                int32_t e = list_entry(ilpre, e0, e1, s);
+                int32_t b = il[e];
+                int32_t idx = piv_ptr[b] + (s - ilpre[e]);
+                sidx[t] = idx;
+                float4 v;
+                v.x = pc[idx] + (float)(coord[b] - cc0) * h;
+                v.y = pc[npiv + idx] + (float)(coord[nc + b] - cc1) * h;
+                v.z = d == 3 ? pc[2 * npiv + idx] + (float)(coord[2 * nc + b] - cc2) * h : 0.f;
+                v.w = 0.f;
+                sx[t] = v;
+            }
+            __syncthreads();
+            for (int32_t e = t; e < ns * RP; e += NT) swt[(e / RP) * SW + e % RP] = (float)w[(int64_t)sidx[e / RP] * RP + e % RP];
+            __syncthreads();
+            if (wact) {
+                int steps = 0;
+                for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
+                    int32_t src = s4 + (lane >> 4);
+                    float kvv = 0.f;
+                    int32_t srcc = src < ns ? src : ns - 1;
+                    if (src < ns) {
+                        float4 q = sx[src];
+                        float dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
+                        kvv = kv32<KIND>(dx * dx + dy * dy + dz * dz, prm);
+                    }
+#pragma unroll
+                    for (int b = 0; b < NCB; b++) {
+                        float bw = swt[srcc * SW + b * 16 + (lane & 15)];
+                        accf[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, bw, accf[b], 0, 0, 0);
+                    }
+                    if (++steps == 4) {
+                        steps = 0;
+#pragma unroll
+                        for (int b = 0; b < NCB; b++) {
+                            for (int i = 0; i < 4; i++) accd[b][i] += (double)accf[b][i];
+                            accf[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NCB; b++)
+            for (int i = 0; i < 4; i++) accd[b][i] += (double)accf[b][i];
+        // phases of the same block are added in order ph = 0, 1, ...
+        __syncthreads();
+        if (nph > 1 && wact)
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) red[(wave * 64 + lane) * NCB * 4 + b * 4 + i] = accd[b][i];
+        __syncthreads();
+        if (wact && ph == 0) {
+            for (int p2 = 1; p2 < nph; p2++) {
+                int w2 = p2 * nb + myb;
+                for (int b = 0; b < NCB; b++)
+                    for (int i = 0; i < 4; i++) accd[b][i] += red[(w2 * 64 + lane) * NCB * 4 + b * 4 + i];
+            }
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) {
+                    int32_t r = tb * 16 + 4 * (lane >> 4) + i;
+                    if (r < kk) dst[(int64_t)(po + r) * RP + b * 16 + (lane & 15)] = accd[b][i];
+                }
+        }
+        __syncthreads();
+    }
+}
+
+// M2L in FP64 on the matrix cores (v_mfma_f64_16x16x4f64): the plain FP64
+// kernel (MODE 1) or the refined one (MODE 2) generated once per (target,
+// source) pair.  Output layout of this instruction: lane l, element i holds
+// row 4 i + l / 16, column l % 16.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+template <int KIND, int MODE, int NCB>
+__global__ __launch_bounds__(NT) void k_m2l_mfma64(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
+                                                   const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
+                                                   const int32_t *ilsum, const double *pc, int64_t npiv, int d,
+                                                   const double *w, double *u, double *part_out, double prm)
+{
+    constexpr int RP = NCB * 16;
+    constexpr int TS = 64;
+    __shared__ double4 sx[TS];
+    __shared__ int32_t sidx[TS];
+    __shared__ double swt[TS * RP > NT * NCB * 4 ? TS * RP : NT * NCB * 4];
+    double *red = swt;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int64_t c = blockIdx.x / P;
+    const int pp = blockIdx.x % P;
+    const int32_t kk = k[c], po = piv_ptr[c], S = ilsum[c];
+    const int32_t sb = (int32_t)(((int64_t)S * pp) / P), se = (int32_t)(((int64_t)S * (pp + 1)) / P);
+    const int32_t e0 = il_ptr[c], e1 = il_ptr[c + 1];
+    double *dst = P > 1 ? part_out + (int64_t)pp * npiv * RP : u;
+    const int32_t ntb = (kk + 15) / 16;
+    for (int32_t tb0 = 0; tb0 < ntb; tb0 += 4) {
+        const int nb = ntb - tb0 < 4 ? ntb - tb0 : 4;
+        const int nph = 4 / nb;
+        const int myb = wave % nb, ph = wave / nb;
+        const bool wact = ph < nph;
+        const int32_t tb = tb0 + myb;
+        int32_t row = tb * 16 + (lane & 15);
+        int32_t rc = row < kk ? row : kk - 1;
+        const double tx = pc[po + rc], ty = pc[npiv + po + rc], tz = d == 3 ? pc[2 * npiv + po + rc] : 0.0;
+        doublex4 acc[NCB];
+#pragma unroll
+        for (int b = 0; b < NCB; b++) acc[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int32_t s0 = sb; s0 < se; s0 += TS) {
+            const int32_t ns = se - s0 < TS ? se - s0 : TS;
+            __syncthreads();
+            if (t < ns) {
+                int32_t s = s0 + t;
+                int32_t e = list_entry(ilpre, e0, e1, s);
+                int32_t idx = piv_ptr[il[e]] + (s - ilpre[e]);
+                sidx[t] = idx;
+                sx[t] = make_double4(pc[idx], pc[npiv + idx], d == 3 ? pc[2 * npiv + idx] : 0.0, 0.0);
+            }
+            __syncthreads();
+            for (int32_t e = t; e < ns * RP; e += NT) swt[e] = w[(int64_t)sidx[e / RP] * RP + e % RP];
+            __syncthreads();
+            if (wact)
+                for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
+                    int32_t src = s4 + (lane >> 4);
+                    double kvv = 0.0;
+                    int32_t srcc = src < ns ? src : ns - 1;
+                    if (src < ns) {
+                        double4 q = sx[src];
+                        double dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
+                        double d2 = dx * dx + dy * dy + dz * dz;
+                        kvv = MODE == 1 ? kv64<KIND>(d2, prm) : kv_refined<KIND>(d2, prm);
+                    }
+#pragma unroll
+                    for (int b = 0; b < NCB; b++)
+                        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kvv, swt[srcc * RP + b * 16 + (lane & 15)],
+                                                                     acc[b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+        if (nph > 1 && wact)
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) red[(wave * 64 + lane) * NCB * 4 + b * 4 + i] = acc[b][i];
+        __syncthreads();
+        if (wact && ph == 0) {
+            for (int p2 = 1; p2 < nph; p2++) {
+                int w2 = p2 * nb + myb;
+                for (int b = 0; b < NCB; b++)
+                    for (int i = 0; i < 4; i++) acc[b][i] += red[(w2 * 64 + lane) * NCB * 4 + b * 4 + i];
+            }
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) {
+                    int32_t r = tb * 16 + 4 * i + (lane >> 4);
+                    if (r < kk) dst[(int64_t)(po + r) * RP + b * 16 + (lane & 15)] = acc[b][i];
+                }
+        }
+        __syncthreads();
+    }
+}
+
+// Near field for RP columns on the matrix cores plus the combine into Y.
+// Coordinates FP64; the mixed form (T = float) rounds the differences to FP32,
+// generates K in FP32 and multiplies it by the x_hi and x_lo tiles with
+// v_mfma_f32_16x16x4f32 (partial sums folded into FP64 every 16 sources);
+// T = double uses v_mfma_f64_16x16x4f64.
+template <typename T, int KIND, int NCB>
+__global__ __launch_bounds__(NT) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
+                                                 const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
+                                                 const int32_t *nbsum, const double *pts, int64_t n, int d,
+                                                 const T *xw, const T *xw2, const double *far,
+                                                 const int32_t *order, double *Y, int64_t ldy, int R, T prm)
+{
+    constexpr int RP = NCB * 16;
+    constexpr int TS = 64;
+    constexpr bool mixed = sizeof(T) == 4;
+    constexpr int SW = (mixed && !(NCB & 1)) ? RP + 16 : RP;   // LDS row stride (bank spread)
+    __shared__ double4 sx[TS];
+    __shared__ int32_t sidx[TS];
+    __shared__ T swt[TS * SW];
+    __shared__ T swt2[mixed ? TS * SW : 1];
+    __shared__ double red[NT * NCB * 4];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int64_t c = blockIdx.x;
+    const int32_t kk = count[c], po = first[c], S = nbsum[c];
+    const int32_t e0 = nb_ptr[c], e1 = nb_ptr[c + 1];
+    const int32_t ntb = (kk + 15) / 16;
+    for (int32_t tb0 = 0; tb0 < ntb; tb0 += 4) {
+        const int nblk = ntb - tb0 < 4 ? ntb - tb0 : 4;
+        const int nph = 4 / nblk;
+        const int myb = wave % nblk, ph = wave / nblk;
+        const bool wact = ph < nph;
+        const int32_t tb = tb0 + myb;
+        int32_t row = tb * 16 + (lane & 15);
+        int32_t rc = row < kk ? row : kk - 1;
+        const double tx = pts[po + rc], ty = pts[n + po + rc], tz = d == 3 ? pts[2 * n + po + rc] : 0.0;
+        double accd[NCB][4];
+        floatx4 af[NCB], af2[NCB];
+        doublex4 ad[NCB];
+#pragma unroll
+        for (int b = 0; b < NCB; b++) {
+            for (int i = 0; i < 4; i++) accd[b][i] = 0.0;
+            af[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+            af2[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ad[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+        }
+        for (int32_t s0 = 0; s0 < S; s0 += TS) {
+            const int32_t ns = S - s0 < TS ? S - s0 : TS;
+            __syncthreads();
+            if (t < ns) {
+                int32_t s = s0 + t;
+                int32_t e = list_entry(nbpre, e0, e1, s);
+                int32_t idx = first[nb[e]] + (s - nbpre[e]);
+                sidx[t] = idx;
+                sx[t] = make_double4(pts[idx], pts[n + idx], d == 3 ? pts[2 * n + idx] : 0.0, 0.0);
+            }
+            __syncthreads();
+            for (int32_t e = t; e < ns * RP; e += NT) {
+                int64_t src = (int64_t)sidx[e / RP] * RP + e % RP;
+                swt[(e / RP) * SW + e % RP] = xw[src];
+                if (mixed) swt2[(e / RP) * SW + e % RP] = xw2[src];
+            }
+            __syncthreads();
+            if (wact) {
+                int steps = 0;
+                for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
+                    int32_t src = s4 + (lane >> 4);
+                    T kvv = T(0);
+                    int32_t srcc = src < ns ? src : ns - 1;
+                    if (src < ns) {
+                        double4 q = sx[src];
+                        T dx = (T)(tx - q.x), dy = (T)(ty - q.y), dz = (T)(tz - q.z);
+                        kvv = kv_self<KIND, T>(dx * dx + dy * dy + dz * dz, prm);
+                    }
+                    if constexpr (mixed) {
+#pragma unroll
+                        for (int b = 0; b < NCB; b++) {
+                            af[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt[srcc * SW + b * 16 + (lane & 15)],
+                                                                         af[b], 0, 0, 0);
+                            af2[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt2[srcc * SW + b * 16 + (lane & 15)],
+                                                                          af2[b], 0, 0, 0);
+                        }
+                        if (++steps == 4) {
+                            steps = 0;
+#pragma unroll
+                            for (int b = 0; b < NCB; b++) {
+                                for (int i = 0; i < 4; i++) accd[b][i] += (double)af[b][i] + (double)af2[b][i];
+                                af[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                                af2[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < NCB; b++)
+                            ad[b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kvv,
+                                                                         (double)swt[srcc * SW + b * 16 + (lane & 15)],
+                                                                         ad[b], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // result rows of this lane: FP32 layout row 4 (l/16) + i, FP64 layout row 4 i + l/16
+#pragma unroll
+        for (int b = 0; b < NCB; b++)
+            for (int i = 0; i < 4; i++)
+                accd[b][i] += mixed ? (double)af[b][i] + (double)af2[b][i] : (double)ad[b][i];
+        __syncthreads();
+        if (nph > 1 && wact)
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) red[(wave * 64 + lane) * NCB * 4 + b * 4 + i] = accd[b][i];
+        __syncthreads();
+        if (wact && ph == 0) {
+            for (int p2 = 1; p2 < nph; p2++) {
+                int w2 = p2 * nblk + myb;
+                for (int b = 0; b < NCB; b++)
+                    for (int i = 0; i < 4; i++) accd[b][i] += red[(w2 * 64 + lane) * NCB * 4 + b * 4 + i];
+            }
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) {
+                    int32_t r = tb * 16 + (mixed ? 4 * (lane >> 4) + i : 4 * i + (lane >> 4));
+                    int col = b * 16 + (lane & 15);
+                    if (r < kk && col < R) {
+                        int64_t p = po + r;
+                        double f = far ? far[p * RP + col] : 0.0;
+                        Y[(int64_t)col * ldy + order[p]] = f + accd[b][i];
+                    }
+                }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_sum_parts_multi(int64_t len, int P, const double *part, double *u)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int p = 0; p < P; p++) s += part[(int64_t)p * len + i];
+    u[i] = s;
+}
+
+int parts_for(const Level &L)
+{
+    const int64_t want = 4096;
+    if (L.ncell >= want) return 1;
+    int64_t P = (want + L.ncell - 1) / L.ncell;
+    int64_t maxp = (L.max_ilsum + 1023) / 1024;
+    if (P > maxp) P = maxp;
+    if (P > 64) P = 64;
+    return P < 1 ? 1 : (int)P;
+}
+
+template <int NCB>
+void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int64_t ldy, int precision,
+                 hipStream_t s)
+{
+    constexpr int RP = NCB * 16;
+    const int64_t n = H->n;
+    const int kap = H->kappa, lmin = H->lmin;
+    const bool mixed = precision == NNCA_PREC_MIXED;
+    const int kind = H->kind;
+    auto &W = H->multi;
+    // 256-element output chunks of the widest cell, at most 64
+    auto chunks = [](int32_t rows) {
+        int64_t ch = ((int64_t)rows * RP + NT - 1) / NT;
+        return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ch, 64));
+    };
+    k_gather_multi<<<grid_for(n * RP, 256), 256, 0, s>>>(n, R, RP, H->order, X, ldx, W.xs, mixed ? W.xhi : nullptr,
+                                                         mixed ? W.xlo : nullptr);
+    HIPCHECK(hipGetLastError());
+    const double prm64 = 1.0 / (H->hparam * H->hparam);
+    const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
+    double *far = nullptr;
+    if (kap >= lmin) {
+        for (int l = kap; l >= lmin; l--) {
+            Level &L = H->lev[l];
+            const double *src = l == kap ? W.xs : W.w[l + 1];
+            k_up_multi<<<dim3((unsigned)L.ncell, chunks(L.max_k)), NT, 0, s>>>(RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off,
+                                                  L.crem64, src, W.w[l]);
+            HIPCHECK(hipGetLastError());
+        }
+        for (int l = lmin; l <= kap; l++) {
+            Level &L = H->lev[l];
+            const int P = parts_for(L);
+            double *part = P > 1 ? W.part : nullptr;
+            const int g = (int)(L.ncell * P);
+            if (mixed && l >= kap - 1) {
+#define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, (float)L.h, H->dim, W.w[l], W.u[l], part, prm32)
+                if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
+                else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
+                else MF(NNCA_K_GAUSS);
+#undef MF
+            } else {
+#define VM(K, M) k_m2l_mfma64<K, M, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc64, L.npiv, H->dim, W.w[l], W.u[l], part, prm64)
+                if (!mixed) {
+                    if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 1);
+                    else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 1);
+                    else VM(NNCA_K_GAUSS, 1);
+                } else {
+                    if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 2);
+                    else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 2);
+                    else VM(NNCA_K_GAUSS, 2);
+                }
+#undef VM
+            }
+            HIPCHECK(hipGetLastError());
+            if (P > 1) {
+                k_sum_parts_multi<<<grid_for(L.npiv * RP, 256), 256, 0, s>>>(L.npiv * RP, P, part, W.u[l]);
+                HIPCHECK(hipGetLastError());
+            }
+        }
+        far = W.far;
+        for (int l = lmin; l <= kap; l++) {
+            Level &L = H->lev[l];
+            double *out = l == kap ? far : W.u[l + 1];
+            k_down_multi<<<dim3((unsigned)L.ncell, chunks(std::max(L.max_k, L.max_nrem))), NT, 0, s>>>(RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
+                                                    L.crem_off, L.crem64, W.u[l], out, l == kap ? 0 : 1);
+            HIPCHECK(hipGetLastError());
+        }
+    }
+    const Level &F = H->lev[kap];
+#define PP(T, K, A, B, PRM) k_p2p_mfma<T, K, NCB><<<(int)F.ncell, NT, 0, s>>>(F.ncell, F.first, F.count, F.nb_ptr, F.nb, H->nbpre, H->nbsum, H->pts64, n, H->dim, A, B, far, H->order, Y, ldy, R, PRM)
+    if (mixed) {
+        if (kind == NNCA_K_INV_R) PP(float, NNCA_K_INV_R, W.xhi, W.xlo, prm32);
+        else if (kind == NNCA_K_LOG_R) PP(float, NNCA_K_LOG_R, W.xhi, W.xlo, prm32);
+        else PP(float, NNCA_K_GAUSS, W.xhi, W.xlo, prm32);
+    } else {
+        if (kind == NNCA_K_INV_R) PP(double, NNCA_K_INV_R, W.xs, (const double *)nullptr, prm64);
+        else if (kind == NNCA_K_LOG_R) PP(double, NNCA_K_LOG_R, W.xs, (const double *)nullptr, prm64);
+        else PP(double, NNCA_K_GAUSS, W.xs, (const double *)nullptr, prm64);
+    }
+#undef PP
+    HIPCHECK(hipGetLastError());
+}
+
+void ensure_multi(nnca_h2 *H, int RP)
+{
+    auto &W = H->multi;
+    if (W.rp >= RP) return;
+    free_multi(H);
+    const int64_t n = H->n;
+    W.xs = dalloc<double>(n * RP);
+    W.far = dalloc<double>(n * RP);
+    W.xhi = dalloc<float>(n * RP);
+    W.xlo = dalloc<float>(n * RP);
+    W.w.assign(H->kappa + 2, nullptr);
+    W.u.assign(H->kappa + 2, nullptr);
+    int64_t part = 1;
+    for (int l = H->lmin; l <= H->kappa; l++) {
+        const Level &L = H->lev[l];
+        W.w[l] = dalloc<double>(L.npiv * RP);
+        W.u[l] = dalloc<double>(L.npiv * RP);
+        part = std::max(part, (int64_t)parts_for(L) * L.npiv * RP);
+    }
+    W.part = dalloc<double>(part);
+    W.rp = RP;
+}
+
+}  // namespace
+
+void free_multi(nnca_h2 *H)
+{
+    auto &W = H->multi;
+    dfree(W.xs); dfree(W.far); dfree(W.xhi); dfree(W.xlo); dfree(W.part);
+    for (auto p : W.w) dfree(p);
+    for (auto p : W.u) dfree(p);
+    W = nnca_h2::Multi();
+}
+
+void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                      int precision, hipStream_t s)
+{
+    for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
+        const int R = (int)std::min<int64_t>(64, nrhs - c0);
+        const int NCB = (R + 15) / 16;
+        ensure_multi(H, NCB * 16);
+        const double *Xb = X + c0 * ldx;
+        double *Yb = Y + c0 * ldy;
+        switch (NCB) {
+        case 1: multi_block<1>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
+        case 2: multi_block<2>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
+        case 3: multi_block<3>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
+        default: multi_block<4>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
+        }
+    }
+}
+
+}  // namespace nnca

@@ -1,0 +1,52 @@
+// Kernel values K(r) of the apply passes, shared by the single- and
+// multi-column kernels.  1/r and log r vanish at r = 0 in the near field; the
+// Gaussian is 1 there.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nnca.h"
+
+namespace nnca {
+template <int KIND>
+__device__ inline float kv32(float d2, float prm)
+{
+    if (KIND == NNCA_K_INV_R) return __builtin_amdgcn_rsqf(d2);
+    if (KIND == NNCA_K_LOG_R) return 0.5f * logf(d2);
+    return __builtin_amdgcn_exp2f(-d2 * prm);  // prm = log2(e) / h^2
+}
+template <int KIND>
+__device__ inline double kv64(double d2, double prm)
+{
+    if (KIND == NNCA_K_INV_R) return 1.0 / sqrt(d2);
+    if (KIND == NNCA_K_LOG_R) return 0.5 * log(d2);
+    return exp(-d2 * prm);  // prm = 1 / h^2
+}
+template <int KIND, typename T>
+__device__ inline T kv(T d2, T prm)
+{
+    if constexpr (sizeof(T) == 4) return kv32<KIND>(d2, prm);
+    else return kv64<KIND>(d2, prm);
+}
+// near field: 1/r and log r vanish at r = 0, the Gaussian is 1 there
+template <int KIND, typename T>
+__device__ inline T kv_self(T d2, T prm)
+{
+    T v = kv<KIND, T>(d2, prm);
+    if (KIND == NNCA_K_GAUSS) return v;
+    return d2 > T(0) ? v : T(0);
+}
+
+// 1/r from an FP32 reciprocal-square-root seed and one FP64 Newton step
+// (relative error ~1e-14); the other kernels in FP64.
+template <int KIND, int MODE = 0>
+__device__ inline double kv_refined(double d2, double prm)
+{
+    if (KIND == NNCA_K_INV_R) {
+        double y = (double)__builtin_amdgcn_rsqf((float)d2);
+        return y * (1.5 - 0.5 * d2 * y * y);
+    }
+    return kv64<KIND>(d2, prm);
+}
+
+
+}  // namespace nnca

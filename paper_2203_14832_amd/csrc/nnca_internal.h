@@ -58,6 +58,7 @@ struct Level {
     bool has_piv = false;
     int64_t npiv = 0;                // sum of ranks
     int32_t max_k = 0;
+    int32_t max_nrem = 0;            // most non-pivot rows of one cell
     int32_t *m = nullptr;            // |t~^{B,i}|
     int32_t *tt_off = nullptr;       // t~ as a range: leaf -> tree order, else -> piv_id of level+1
     int32_t *k = nullptr;            // rank k_B = |t^{B,i}|
@@ -117,6 +118,15 @@ struct nnca_h2 {
     float *xhi = nullptr, *xlo = nullptr;
     double *m2l_part = nullptr;   // partial M2L vectors of split launches
     int64_t m2l_part_cap = 0;
+
+    // workspace of the many-column matvec: rows in tree order, columns
+    // innermost, padded to rp columns
+    struct Multi {
+        int rp = 0;
+        double *xs = nullptr, *far = nullptr, *part = nullptr;
+        float *xhi = nullptr, *xlo = nullptr;
+        std::vector<double *> w, u;   // per level
+    } multi;
     int64_t m2l_inter = 0, p2p_inter = 0, transfer_entries = 0;
 
     // per-launch HIP-event timing of the matvec passes (off by default)
@@ -140,6 +150,9 @@ void debug_kernel_eval(int kind, double hparam, int dim, const double *a, const 
 void prepare_apply(nnca_h2 *H);
 void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                 int precision, hipStream_t s);
+void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                      int precision, hipStream_t s);
+void free_multi(nnca_h2 *H);
 enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4 };
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
                 const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);

@@ -119,10 +119,11 @@ def test_matvec_parity(built, name):
     n = p.shape[0]
     X = np.random.default_rng(12).standard_normal((n, 3))
     Xt = torch.tensor(X, device="cuda")
-    Y64 = G.matvec(Xt, "fp64").cpu().numpy()
+    # one column at a time (the single-column kernels)
+    Y64 = np.stack([G.matvec(Xt[:, c], "fp64").cpu().numpy() for c in range(3)], 1)
     Yo = O.matvec(X)
     assert rel(Y64, Yo) <= 1e-12
-    Ym = G.matvec(Xt, "mixed").cpu().numpy()
+    Ym = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
     print(name, "mixed vs fp64:", [rel(Ym[:, c], Y64[:, c]) for c in range(3)])
     for c in range(3):
         assert rel(Ym[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c, rel(Ym[:, c], Y64[:, c]))
@@ -198,3 +199,23 @@ def test_rank_cap_retry_and_chunking(orc):
                 np.testing.assert_array_equal(rows[ptr[b]:ptr[b + 1]], O.cell(l, b)["piv"])
     x = torch.tensor(rng.standard_normal(3000), device="cuda")
     np.testing.assert_array_equal(G1.matvec(x).cpu().numpy(), G2.matvec(x).cpu().numpy())
+
+
+@pytest.mark.parametrize("name,R", [("cube3d", 5), ("cube3d", 37), ("sphere", 64), ("mixture", 16), ("c1", 20),
+                                    ("literal_sqrt2", 33)])
+def test_many_rhs_parity(built, name, R):
+    # The block path (columns innermost, MFMA for the FP32 transverse pass)
+    # against the oracle and against one column at a time.
+    p, G, T, O, kind, h = built(name)
+    n = p.shape[0]
+    X = np.random.default_rng(17).standard_normal((n, R))
+    Xt = torch.tensor(X, device="cuda")
+    Y64 = G.matvec(Xt, "fp64").cpu().numpy()
+    Yo = O.matvec(X[:, :3])
+    assert rel(Y64[:, :3], Yo) <= 1e-12
+    one = np.stack([G.matvec(Xt[:, c], "fp64").cpu().numpy() for c in (0, R - 1)], 1)
+    assert rel(Y64[:, [0, R - 1]], one) <= 1e-13
+    Ym = G.matvec(Xt, "mixed").cpu().numpy()
+    errs = [rel(Ym[:, c], Y64[:, c]) for c in range(R)]
+    print(name, R, "block mixed vs fp64: max", max(errs))
+    assert max(errs) <= MIXED_TOL.get(name, 1e-6)
