@@ -71,6 +71,9 @@ def lib():
         L.orc_h2_matvec.argtypes = [P, P, P, i64, i32]
         L.orc_h2_interactions.argtypes = [P, P]
         L.orc_num_threads.restype = i32
+        L.orc_h2_frozen.restype = P; L.orc_h2_frozen.argtypes = [P, f64]
+        L.orc_h2_grad_h.restype = f64; L.orc_h2_grad_h.argtypes = [P, P, P, i32]
+        L.orc_dense_grad_h.restype = f64; L.orc_dense_grad_h.argtypes = [P, i64, i32, f64, P, P]
         _lib = L
     return _lib
 
@@ -195,10 +198,15 @@ class H2:
     """NNCA pivots, transfer operators and the H2 matvec (Sec. 2.3-4)."""
 
     def __init__(self, tree: Tree, kind: str, tol: float, h: float = 1.0, policy: int = 1,
-                 build: bool = True):
+                 build: bool = True, _handle=None):
         self.tree = tree
         self.kind = kind
+        self.h = float(h)
         self._free = lib().orc_h2_free
+        if _handle is not None:
+            self._h = _handle
+            self.lmin = lib().orc_h2_lmin(self._h)
+            return
         self._h = lib().orc_h2_new(tree._h, KINDS[kind], float(h), float(tol), int(policy))
         self.lmin = lib().orc_h2_lmin(self._h)
         if build:
@@ -243,3 +251,28 @@ class H2:
         out = np.zeros(2, np.int64)
         lib().orc_h2_interactions(self._h, _p(out))
         return int(out[0]), int(out[1])
+
+    def frozen(self, h: float) -> "H2":
+        """The same pivots with every operator re-evaluated at length scale h
+        (Gaussian only): C_B = K_h(t~, J) K_h(I, J)^{-1}, M2L and near field
+        at h."""
+        p = lib().orc_h2_frozen(self._h, float(h))
+        if not p:
+            raise ValueError("frozen re-evaluation failed (kernel or zero pivot)")
+        return H2(self.tree, self.kind, 0.0, h=h, _handle=p)
+
+    def grad_h(self, x, g, parts: int = 7) -> float:
+        """g^T (dA~/dh) x with the pivots frozen (forward-mode derivative of
+        every step of the matvec); x, g: (n,) in original order."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        return float(lib().orc_h2_grad_h(self._h, _p(x), _p(g), int(parts)))
+
+
+def dense_grad_h(points, x, g, h: float) -> float:
+    """The plain definition sum_ij g_i x_j dK/dh(r_ij) for the Gaussian."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, d = pts.shape
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    return float(lib().orc_dense_grad_h(_p(pts), n, d, float(h), _p(x), _p(g)))

@@ -1010,3 +1010,321 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* Derivative with respect to the Gaussian length scale, pivots frozen        */
+/* ------------------------------------------------------------------------- */
+/* For K(r) = exp(-r^2/h^2) every block of the H2 form depends on h.  With the
+ * index sets t^{B,i}, s^{B,i} held fixed, an ACA cell's operator is the plain
+ * definition  C_B(h) = K_h(t~, J) K_h(I, J)^{-1}  (I = t^{B,i} inside t~,
+ * J = s^{B,i}; Remark in Sec. 2.3.2), the M2L blocks are K_h(t^{B,i}, t^{B',i})
+ * and the near field is K_h itself (Sec. 4).  Pass-through cells keep the
+ * identity.  dK/dh = (2 r^2 / h^3) K.                                        */
+
+/* Gaussian elimination with partial pivoting (row interchanges, the largest
+ * |entry| of the column below the diagonal; ties to the first), solving
+ * A X = B for k x k row-major A and k x nrhs row-major B in place.
+ * Returns -1 on an exactly zero pivot.                                        */
+static int solve_gepp(int64_t k, double *A, double *B, int64_t nrhs)
+{
+    for (int64_t p = 0; p < k; p++) {
+        int64_t best = p;
+        for (int64_t r = p + 1; r < k; r++)
+            if (fabs(A[r * k + p]) > fabs(A[best * k + p])) best = r;
+        if (A[best * k + p] == 0.0) return -1;
+        if (best != p) {
+            for (int64_t c = 0; c < k; c++) {
+                double t = A[p * k + c]; A[p * k + c] = A[best * k + c]; A[best * k + c] = t;
+            }
+            for (int64_t c = 0; c < nrhs; c++) {
+                double t = B[p * nrhs + c]; B[p * nrhs + c] = B[best * nrhs + c]; B[best * nrhs + c] = t;
+            }
+        }
+        for (int64_t r = p + 1; r < k; r++) {
+            double f = A[r * k + p] / A[p * k + p];
+            for (int64_t c = p; c < k; c++) A[r * k + c] -= f * A[p * k + c];
+            for (int64_t c = 0; c < nrhs; c++) B[r * nrhs + c] -= f * B[p * nrhs + c];
+        }
+    }
+    for (int64_t p = k - 1; p >= 0; p--)
+        for (int64_t c = 0; c < nrhs; c++) {
+            double s = B[p * nrhs + c];
+            for (int64_t q = p + 1; q < k; q++) s -= A[p * k + q] * B[q * nrhs + c];
+            B[p * nrhs + c] = s / A[p * k + p];
+        }
+    return 0;
+}
+
+/* X (m x k, row-major) = R K(I, J)^{-1} for the ACA cell cb at length scale
+ * h, R m x k row-major.  Solved as K(I, J)^T X^T = R^T.                     */
+static int right_solve_kij(const orc_tree *T, const ocell *cb, double h, const double *R, double *X)
+{
+    int64_t m = cb->m, k = cb->k;
+    int d = T->d;
+    double *At = (double *)malloc(sizeof(double) * (k * k + 1));
+    double *Bt = (double *)malloc(sizeof(double) * (k * m + 1));
+    for (int64_t a = 0; a < k; a++)
+        for (int64_t b = 0; b < k; b++)   /* At[b][a] = K(I_a, J_b) */
+            At[b * k + a] = kern(ORC_K_GAUSS, h, T->pts + cb->piv[a] * d, T->pts + cb->colpts[b] * d, d);
+    for (int64_t r = 0; r < m; r++)
+        for (int64_t q = 0; q < k; q++) Bt[q * m + r] = R[r * k + q];
+    int rc = solve_gepp(k, At, Bt, m);
+    for (int64_t r = 0; r < m; r++)
+        for (int64_t q = 0; q < k; q++) X[r * k + q] = Bt[q * m + r];
+    free(At); free(Bt);
+    return rc;
+}
+
+static double dkern_dh(double h, const double *a, const double *b, int d)
+{
+    double d2 = dist2(a, b, d);
+    return (2.0 * d2 / (h * h * h)) * kern(ORC_K_GAUSS, h, a, b, d);
+}
+
+/* A copy of H whose operators are re-evaluated at length scale hnew with the
+ * pivots of H (Gaussian kernel only).  Shares H's tree.  NULL on a zero pivot. */
+orc_h2 *orc_h2_frozen(const orc_h2 *H, double hnew)
+{
+    const orc_tree *T = H->T;
+    if (H->kind != ORC_K_GAUSS) return NULL;
+    orc_h2 *F = orc_h2_new(H->T, H->kind, hnew, H->tol, H->policy);
+    int bad = 0;
+    for (int l = H->lmin; l <= T->kappa; l++) {
+        int64_t nc = T->lev[l].ncell;
+#pragma omp parallel for schedule(dynamic, 4) reduction(|| : bad)
+        for (int64_t b = 0; b < nc; b++) {
+            const ocell *s = &H->cell[l][b];
+            ocell *c = &F->cell[l][b];
+            if (!s->done) continue;
+            *c = *s;
+            int64_t m = s->m, k = s->k;
+            c->tt = (int64_t *)malloc(sizeof(int64_t) * (m + 1));
+            c->piv = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+            c->rowpos = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+            c->colpos = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+            c->colpts = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+            c->C = (double *)malloc(sizeof(double) * (m * k + 1));
+            memcpy(c->tt, s->tt, sizeof(int64_t) * m);
+            memcpy(c->piv, s->piv, sizeof(int64_t) * k);
+            memcpy(c->rowpos, s->rowpos, sizeof(int64_t) * k);
+            if (!s->passthrough) {
+                memcpy(c->colpos, s->colpos, sizeof(int64_t) * k);
+                memcpy(c->colpts, s->colpts, sizeof(int64_t) * k);
+            }
+            if (s->passthrough || k == 0) {
+                memcpy(c->C, s->C, sizeof(double) * m * k);
+                continue;
+            }
+            double *R = (double *)malloc(sizeof(double) * (m * k + 1));
+            for (int64_t r = 0; r < m; r++)
+                for (int64_t q = 0; q < k; q++)
+                    R[r * k + q] = kern(ORC_K_GAUSS, hnew, T->pts + s->tt[r] * T->d, T->pts + s->colpts[q] * T->d, T->d);
+            if (right_solve_kij(T, s, hnew, R, c->C)) bad = 1;
+            free(R);
+        }
+    }
+    if (bad) { orc_h2_free(F); return NULL; }
+    return F;
+}
+
+/* g^T (dA~/dh) x for one column (original point order), by forward-mode
+ * differentiation of each step of the matvec of Sec. 4 with the pivots
+ * frozen:
+ *   dC_B   = (dK(t~, J) - C_B dK(I, J)) K(I, J)^{-1}      (ACA cells; 0 else)
+ *   up:      w = C^T x~,            dw = dC^T x~ + C^T dx~
+ *   across:  u = sum K w',          du = sum (dK w' + K dw')
+ *   down:    u_c += C u,            du_c += dC u + C du
+ *   leaves:  y = C u + N x,         dy = dC u + C du + dN x
+ * and the result is g . dy.  `parts` selects terms for tests: bit 0 near
+ * field, bit 1 the M2L blocks, bit 2 the transfer operators (7 = all).
+ * Returns NaN for a kernel other than the Gaussian or on a zero pivot.       */
+double orc_h2_grad_h(const orc_h2 *H, const double *x, const double *g, int parts)
+{
+    const orc_tree *T = H->T;
+    if (H->kind != ORC_K_GAUSS) return NAN;
+    const int d = T->d, kap = T->kappa;
+    const int64_t n = T->n;
+    const double h = H->hparam;
+    const int pn = parts & 1, pm = (parts >> 1) & 1, pt = (parts >> 2) & 1;
+    double *xs = (double *)malloc(sizeof(double) * (n + 1));
+    double *dy = (double *)calloc(n + 1, sizeof(double));
+    for (int64_t p = 0; p < n; p++) xs[p] = x[T->order[p]];
+    double **w = (double **)calloc(kap + 1, sizeof(double *));
+    double **dw = (double **)calloc(kap + 1, sizeof(double *));
+    double **u = (double **)calloc(kap + 1, sizeof(double *));
+    double **du = (double **)calloc(kap + 1, sizeof(double *));
+    double ***dC = (double ***)calloc(kap + 1, sizeof(double **));
+    int64_t **off = (int64_t **)calloc(kap + 1, sizeof(int64_t *));
+    int bad = 0;
+    for (int l = H->lmin; l <= kap; l++) {
+        int64_t nc = T->lev[l].ncell;
+        off[l] = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+        off[l][0] = 0;
+        for (int64_t b = 0; b < nc; b++) off[l][b + 1] = off[l][b] + H->cell[l][b].k;
+        w[l] = (double *)calloc(off[l][nc] + 1, sizeof(double));
+        dw[l] = (double *)calloc(off[l][nc] + 1, sizeof(double));
+        u[l] = (double *)calloc(off[l][nc] + 1, sizeof(double));
+        du[l] = (double *)calloc(off[l][nc] + 1, sizeof(double));
+        dC[l] = (double **)calloc(nc, sizeof(double *));
+        /* dC_B, dense m x k (all zero for pass-through cells) */
+#pragma omp parallel for schedule(dynamic, 4) reduction(|| : bad)
+        for (int64_t b = 0; b < nc; b++) {
+            const ocell *cb = &H->cell[l][b];
+            int64_t m = cb->m, k = cb->k;
+            dC[l][b] = (double *)calloc(m * k + 1, sizeof(double));
+            if (cb->passthrough || k == 0 || !pt) continue;
+            double *R = (double *)malloc(sizeof(double) * (m * k + 1));
+            for (int64_t r = 0; r < m; r++)
+                for (int64_t q = 0; q < k; q++) {
+                    double s = dkern_dh(h, T->pts + cb->tt[r] * d, T->pts + cb->colpts[q] * d, d);
+                    for (int64_t a = 0; a < k; a++)
+                        s -= cb->C[r * k + a] * dkern_dh(h, T->pts + cb->piv[a] * d, T->pts + cb->colpts[q] * d, d);
+                    R[r * k + q] = s;
+                }
+            if (right_solve_kij(T, cb, h, R, dC[l][b])) bad = 1;
+            free(R);
+        }
+    }
+    /* upward pass with its tangent */
+    for (int l = kap; l >= H->lmin; l--) {
+        const olevel *lv = &T->lev[l];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t b = 0; b < lv->ncell; b++) {
+            const ocell *cb = &H->cell[l][b];
+            double *xt = (double *)calloc(cb->m + 1, sizeof(double));
+            double *dxt = (double *)calloc(cb->m + 1, sizeof(double));
+            if (l == kap) {
+                for (int64_t r = 0; r < cb->m; r++) xt[r] = xs[cb->tt[r]];
+            } else {
+                int64_t r = 0;
+                for (int64_t c = lv->child_first[b]; c < lv->child_first[b] + lv->child_count[b]; c++)
+                    for (int64_t q = off[l + 1][c]; q < off[l + 1][c + 1]; q++, r++) {
+                        xt[r] = w[l + 1][q];
+                        dxt[r] = dw[l + 1][q];
+                    }
+            }
+            for (int64_t q = 0; q < cb->k; q++) {
+                double s = 0.0, ds = 0.0;
+                for (int64_t r = 0; r < cb->m; r++) {
+                    s += cb->C[r * cb->k + q] * xt[r];
+                    ds += dC[l][b][r * cb->k + q] * xt[r] + cb->C[r * cb->k + q] * dxt[r];
+                }
+                w[l][off[l][b] + q] = s;
+                dw[l][off[l][b] + q] = ds;
+            }
+            free(xt); free(dxt);
+        }
+    }
+    /* transverse pass with its tangent */
+    for (int l = H->lmin; l <= kap; l++) {
+        const olevel *lv = &T->lev[l];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t b = 0; b < lv->ncell; b++) {
+            const ocell *cb = &H->cell[l][b];
+            for (int64_t e = lv->il_ptr[b]; e < lv->il_ptr[b + 1]; e++) {
+                int64_t bp = lv->il[e];
+                const ocell *cp = &H->cell[l][bp];
+                for (int64_t i = 0; i < cb->k; i++) {
+                    double s = 0.0, ds = 0.0;
+                    for (int64_t j = 0; j < cp->k; j++) {
+                        const double *a = T->pts + cb->piv[i] * d, *bb = T->pts + cp->piv[j] * d;
+                        double kij = kern(ORC_K_GAUSS, h, a, bb, d);
+                        double wj = w[l][off[l][bp] + j], dwj = dw[l][off[l][bp] + j];
+                        s += kij * wj;
+                        ds += (pm ? dkern_dh(h, a, bb, d) * wj : 0.0) + kij * dwj;
+                    }
+                    u[l][off[l][b] + i] += s;
+                    du[l][off[l][b] + i] += ds;
+                }
+            }
+        }
+    }
+    /* downward pass with its tangent */
+    for (int l = H->lmin; l < kap; l++) {
+        const olevel *lv = &T->lev[l];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t b = 0; b < lv->ncell; b++) {
+            const ocell *cb = &H->cell[l][b];
+            const double *ub = u[l] + off[l][b], *dub = du[l] + off[l][b];
+            int64_t r = 0;
+            for (int64_t c = lv->child_first[b]; c < lv->child_first[b] + lv->child_count[b]; c++)
+                for (int64_t q = off[l + 1][c]; q < off[l + 1][c + 1]; q++, r++) {
+                    double s = 0.0, ds = 0.0;
+                    for (int64_t j = 0; j < cb->k; j++) {
+                        s += cb->C[r * cb->k + j] * ub[j];
+                        ds += dC[l][b][r * cb->k + j] * ub[j] + cb->C[r * cb->k + j] * dub[j];
+                    }
+                    u[l + 1][q] += s;
+                    du[l + 1][q] += ds;
+                }
+        }
+    }
+    /* leaves: far field tangent plus the derivative of the near field */
+    const olevel *lf = &T->lev[kap];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < lf->ncell; b++) {
+        for (int64_t r = 0; r < lf->count[b]; r++) {
+            int64_t p = lf->first[b] + r;
+            double ds = 0.0;
+            if (kap >= H->lmin) {
+                const ocell *cb = &H->cell[kap][b];
+                const double *ub = u[kap] + off[kap][b], *dub = du[kap] + off[kap][b];
+                for (int64_t j = 0; j < cb->k; j++)
+                    ds += dC[kap][b][r * cb->k + j] * ub[j] + cb->C[r * cb->k + j] * dub[j];
+            }
+            if (pn)
+                for (int64_t e = lf->nb_ptr[b]; e < lf->nb_ptr[b + 1]; e++) {
+                    int64_t bp = lf->nb[e];
+                    for (int64_t q = lf->first[bp]; q < lf->first[bp] + lf->count[bp]; q++)
+                        ds += dkern_dh(h, T->pts + p * d, T->pts + q * d, d) * xs[q];
+                }
+            dy[p] = ds;
+        }
+    }
+    double sum = 0.0, comp = 0.0;
+    for (int64_t p = 0; p < n; p++) {
+        double t = g[T->order[p]] * dy[p];
+        double s2 = sum + t;
+        if (fabs(sum) >= fabs(t)) comp += (sum - s2) + t;
+        else comp += (t - s2) + sum;
+        sum = s2;
+    }
+    for (int l = H->lmin; l <= kap; l++) {
+        for (int64_t b = 0; b < T->lev[l].ncell; b++) free(dC[l][b]);
+        free(dC[l]); free(w[l]); free(dw[l]); free(u[l]); free(du[l]); free(off[l]);
+    }
+    free(dC); free(w); free(dw); free(u); free(du); free(off); free(xs); free(dy);
+    return bad ? NAN : sum + comp;
+}
+
+/* The plain definition of the derivative of the dense form:
+ *   g^T (dA/dh) x = sum_ij g_i x_j (2 r_ij^2 / h^3) exp(-r_ij^2 / h^2),
+ * C library exp, Neumaier-compensated sums.                                 */
+double orc_dense_grad_h(const double *pts, int64_t n, int d, double h, const double *x, const double *g)
+{
+    double *row = (double *)malloc(sizeof(double) * (n + 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double sum = 0.0, comp = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            double d2 = 0.0;
+            for (int q = 0; q < d; q++) d2 += (pts[i * d + q] - pts[j * d + q]) * (pts[i * d + q] - pts[j * d + q]);
+            double t = (2.0 * d2 / (h * h * h)) * exp(-d2 / (h * h)) * x[j];
+            double s2 = sum + t;
+            if (fabs(sum) >= fabs(t)) comp += (sum - s2) + t;
+            else comp += (t - s2) + sum;
+            sum = s2;
+        }
+        row[i] = g[i] * (sum + comp);
+    }
+    double sum = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double t = row[i];
+        double s2 = sum + t;
+        if (fabs(sum) >= fabs(t)) comp += (sum - s2) + t;
+        else comp += (t - s2) + sum;
+        sum = s2;
+    }
+    free(row);
+    return sum + comp;
+}
