@@ -103,6 +103,30 @@ nnca_status nnca_matvec(nnca_handle h, const double *X, double *Y, int64_t nrhs,
 nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64_t nrhs,
                                 int64_t ldx, int64_t ldy, int32_t precision, void *stream);
 
+/* Backward of Y = A~ X for a scalar loss L with G = dL/dY (device FP64,
+ * column-major, original point order, like X):
+ *   DX    = A~^T G  (the gradient with respect to X; Sec. 5's symmetric case
+ *           makes it the forward passes applied to G), if DX != NULL;
+ *   *dLdh = sum over the columns c of G_c^T (dA~/dh) X_c, the derivative of
+ *           L with respect to the Gaussian length scale h with every pivot
+ *           set t^{B,i}, s^{B,i} of the build held fixed, if dLdh != NULL.
+ *           With the pivots fixed the transfer operators are
+ *           C_B = K(t~, J) K(I, J)^{-1} (Remark in Sec. 2.3.2) and
+ *           dC_B = (dK(t~, J) - C_B dK(I, J)) K(I, J)^{-1}, dK/dh =
+ *           (2 r^2 / h^3) K; every block of Sec. 4 is differentiated.
+ * dLdh is a device pointer to one double.  precision (nnca_precision) sets
+ * the arithmetic of the passes; the transfer-operator terms and the FP64
+ * factors L U = K(I, J) are FP64 in both.  The first call with dLdh factors
+ * K(I, J) of every ACA cell (blocking, allocates sum k_B^2 doubles, kept
+ * with the handle); later calls are asynchronous on `stream`.
+ * Errors: INVALID_ARG (NULL G, neither output requested, X NULL with dLdh,
+ * leading dimensions < n, DX overlapping X, G or dLdh); NOT_SUPPORTED (dLdh
+ * with a kernel other than the Gaussian, or a rank above 1024);
+ * NUMERICAL (a zero pivot in K(I, J)); OUT_OF_MEMORY; HIP.                */
+nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G, int64_t nrhs, int64_t ldx,
+                                 int64_t ldg, int32_t precision, double *DX, int64_t lddx, double *dLdh,
+                                 void *stream);
+
 /* Dense FP64 direct sum Y = A X with A_ij = K(p_i, p_j) (the plain
  * definition; used for error reports).  points: device, dim x n SoA with
  * stride ld; X, Y: device FP64 column-major.  Asynchronous on `stream`.    */

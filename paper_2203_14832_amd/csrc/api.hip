@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "nnca_internal.h"
 
@@ -65,6 +66,7 @@ static void free_handle(nnca_h2 *H)
     if (!H) return;
     clear_profile(H);
     free_multi(H);
+    free_grad(H);
     for (auto &L : H->lev) {
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
@@ -207,6 +209,40 @@ nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64
                                 int32_t precision, void *stream)
 {
     return matvec_common(h, X, Y, nrhs, ldx, ldy, precision, stream);
+}
+
+nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G, int64_t nrhs, int64_t ldx,
+                                 int64_t ldg, int32_t precision, double *DX, int64_t lddx, double *dLdh,
+                                 void *stream)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        if (!G) fail(NNCA_ERR_INVALID_ARG, "G is NULL");
+        if (!DX && !dLdh) fail(NNCA_ERR_INVALID_ARG, "neither DX nor dLdh requested");
+        if (dLdh && !X) fail(NNCA_ERR_INVALID_ARG, "X is NULL");
+        if (nrhs < 1) fail(NNCA_ERR_INVALID_ARG, "nrhs < 1");
+        if (ldg < h->n || (X && ldx < h->n) || (DX && lddx < h->n))
+            fail(NNCA_ERR_INVALID_ARG, "leading dimension < n");
+        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+        if (dLdh && h->kind != NNCA_K_GAUSS)
+            fail(NNCA_ERR_NOT_SUPPORTED, "the length-scale derivative is defined for the Gaussian kernel only");
+        auto span = [&](const double *p, int64_t ld) {
+            return std::make_pair((const char *)p, (const char *)(p + (nrhs - 1) * ld + h->n));
+        };
+        if (DX) {
+            auto d = span(DX, lddx), g = span(G, ldg);
+            if (d.first < g.second && g.first < d.second) fail(NNCA_ERR_INVALID_ARG, "DX and G overlap");
+            if (X) {
+                auto x = span(X, ldx);
+                if (d.first < x.second && x.first < d.second) fail(NNCA_ERR_INVALID_ARG, "DX and X overlap");
+            }
+            if (dLdh) {
+                const char *q = (const char *)dLdh;
+                if (d.first < q + sizeof(double) && q < d.second) fail(NNCA_ERR_INVALID_ARG, "DX and dLdh overlap");
+            }
+        }
+        run_backward(h, X, G, nrhs, ldx, ldg, precision, DX, lddx, dLdh, (hipStream_t)stream);
+    });
 }
 
 nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t kernel_kind,

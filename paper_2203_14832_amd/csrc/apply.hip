@@ -569,6 +569,7 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
 #define M2L_CASE(K) k_m2l<K, MODE, M2L_TILE><<<g, NT, 0, s>>>(M2L_ARGS);
     if (kind == NNCA_K_INV_R) { M2L_CASE(NNCA_K_INV_R) }
     else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }
+    else if (kind == K_GAUSS_DH) { M2L_CASE(K_GAUSS_DH) }
     else { M2L_CASE(NNCA_K_GAUSS) }
 #undef M2L_CASE
 #undef M2L_ARGS
@@ -588,6 +589,7 @@ void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *f
 #define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(nc, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
     if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
+    else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
     else P2P_CASE(NNCA_K_GAUSS);
 #undef P2P_CASE
     HIPCHECK(hipGetLastError());
@@ -618,19 +620,25 @@ struct Span {
 
 // One right-hand side.  xs64: x in tree order (FP64).  Mixed: x_hi, x_lo.
 // The transfer passes run in FP64 for both precisions; the M2L and near-field
-// kernels run in T.
+// kernels run in T with the kernel `kind` (the handle's, or the length-scale
+// derivative of the Gaussian).  do_up = false reuses the multipole vectors
+// already in the levels; do_p2p = false stops after the downward pass (the
+// levels then hold every multipole vector and every local vector, the latter
+// with all contributions of the coarser levels added).
 template <typename T>
-void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, double *y, hipStream_t s)
+void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, double *y, hipStream_t s, int kind,
+                bool do_up, bool do_p2p)
 {
     const bool f32 = sizeof(T) == 4;
     const int kap = H->kappa, lmin = H->lmin;
-    const T prm = H->kind == NNCA_K_GAUSS ? (f32 ? (T)(1.4426950408889634 / (H->hparam * H->hparam))
-                                                 : (T)(1.0 / (H->hparam * H->hparam)))
-                                          : T(0);
+    const bool gauss = kind == NNCA_K_GAUSS || kind == K_GAUSS_DH;
+    const T prm = gauss ? (f32 ? (T)(1.4426950408889634 / (H->hparam * H->hparam))
+                               : (T)(1.0 / (H->hparam * H->hparam)))
+                        : T(0);
     double *far = nullptr;
     if (kap >= lmin) {
         // upward pass
-        for (int l = kap; l >= lmin; l--) {
+        for (int l = kap; l >= lmin && do_up; l--) {
             nnca::Level &L = H->lev[l];
             const double *src = (l == kap) ? xs64 : H->lev[l + 1].w64;
             Span sp(H, s, PASS_UP, l);
@@ -648,9 +656,9 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
             Span sp(H, s, PASS_M2L, l);
-            if (!f32) launch_m2l_mode<M_F64>(H->kind, H, L, L.pc64, prm64, s);
-            else if (l <= kap - 2) launch_m2l_mode<M_F64R>(H->kind, H, L, L.pc64, prm64, s);
-            else launch_m2l_mode<M_F32>(H->kind, H, L, L.pc32, (double)prm, s);
+            if (!f32) launch_m2l_mode<M_F64>(kind, H, L, L.pc64, prm64, s);
+            else if (l <= kap - 2) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s);
+            else launch_m2l_mode<M_F32>(kind, H, L, L.pc32, (double)prm, s);
         }
         // downward pass
         far = H->far64;
@@ -664,13 +672,31 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             HIPCHECK(hipGetLastError());
         }
     }
+    if (!do_p2p) return;
     // near field and combine
     Span sp(H, s, PASS_P2P, kap);
-    if (f32) launch_p2p<T>(H->kind, H, xhi, xlo, far, y, prm, s);
-    else launch_p2p<T>(H->kind, H, (const T *)xs64, nullptr, far, y, prm, s);
+    if (f32) launch_p2p<T>(kind, H, xhi, xlo, far, y, prm, s);
+    else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, far, y, prm, s);
 }
 
 }  // namespace
+
+void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s)
+{
+    const int64_t n = H->n;
+    Span sp(H, s, PASS_GATHER, -1);
+    if (precision == NNCA_PREC_MIXED)
+        k_gather_split<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64, H->xhi, H->xlo);
+    else
+        k_gather64<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64);
+    HIPCHECK(hipGetLastError());
+}
+
+void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, double *y, hipStream_t s)
+{
+    if (precision == NNCA_PREC_MIXED) one_column<float>(H, H->xs64, H->xhi, H->xlo, y, s, kind, do_up, do_p2p);
+    else one_column<double>(H, H->xs64, nullptr, nullptr, y, s, kind, do_up, do_p2p);
+}
 
 void prepare_apply(nnca_h2 *H)
 {
@@ -744,25 +770,9 @@ void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ld
         run_matvec_multi(H, X, Y, nrhs, ldx, ldy, precision, s);
         return;
     }
-    const int64_t n = H->n;
     for (int64_t col = 0; col < nrhs; col++) {
-        const double *x = X + col * ldx;
-        double *y = Y + col * ldy;
-        if (precision == NNCA_PREC_MIXED) {
-            {
-                Span sp(H, s, PASS_GATHER, -1);
-                k_gather_split<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64, H->xhi, H->xlo);
-                HIPCHECK(hipGetLastError());
-            }
-            one_column<float>(H, H->xs64, H->xhi, H->xlo, y, s);
-        } else {
-            {
-                Span sp(H, s, PASS_GATHER, -1);
-                k_gather64<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64);
-                HIPCHECK(hipGetLastError());
-            }
-            one_column<double>(H, H->xs64, nullptr, nullptr, y, s);
-        }
+        gather_input(H, X + col * ldx, precision, s);
+        column_passes(H, precision, H->kind, true, true, Y + col * ldy, s);
     }
 }
 

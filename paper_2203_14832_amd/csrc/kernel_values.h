@@ -7,11 +7,20 @@
 #include "nnca.h"
 
 namespace nnca {
+// Internal kind of the length-scale derivative of the Gaussian:
+// D(r) = (r^2/h^2) exp(-r^2/h^2), so that dK/dh = (2/h) D(r).  It runs
+// through the same interaction kernels as K; it is zero at r = 0.
+constexpr int K_GAUSS_DH = 103;
+
 template <int KIND>
 __device__ inline float kv32(float d2, float prm)
 {
     if (KIND == NNCA_K_INV_R) return __builtin_amdgcn_rsqf(d2);
     if (KIND == NNCA_K_LOG_R) return 0.5f * logf(d2);
+    if (KIND == K_GAUSS_DH) {
+        float t = d2 * prm;   // log2(e) r^2 / h^2
+        return (t * 0.693147180559945309f) * __builtin_amdgcn_exp2f(-t);
+    }
     return __builtin_amdgcn_exp2f(-d2 * prm);  // prm = log2(e) / h^2
 }
 template <int KIND>
@@ -19,6 +28,10 @@ __device__ inline double kv64(double d2, double prm)
 {
     if (KIND == NNCA_K_INV_R) return 1.0 / sqrt(d2);
     if (KIND == NNCA_K_LOG_R) return 0.5 * log(d2);
+    if (KIND == K_GAUSS_DH) {
+        double t = d2 * prm;  // r^2 / h^2
+        return t * exp(-t);
+    }
     return exp(-d2 * prm);  // prm = 1 / h^2
 }
 template <int KIND, typename T>

@@ -129,6 +129,20 @@ struct nnca_h2 {
     } multi;
     int64_t m2l_inter = 0, p2p_inter = 0, transfer_entries = 0;
 
+    // state of the length-scale derivative (set up on first use; pivots frozen)
+    struct Grad {
+        bool ready = false;
+        std::vector<int64_t *> lu_off;   // per level: ncell + 1 offsets into lu
+        std::vector<double *> lu;        // per level: L U = K(I, J) of every ACA cell, column-major
+        std::vector<double *> gw, gu;    // per level: multipole / local vectors of the cotangent
+        std::vector<int64_t> term_off;   // per level: first per-cell term; the dot parts follow
+        double *gs = nullptr;            // cotangent in tree order
+        double *yd = nullptr;            // derivative-kernel product, original order
+        double *terms = nullptr;
+        int64_t nterms = 0, lu_entries = 0;
+        int32_t *flag = nullptr;
+    } grad;
+
     // per-launch HIP-event timing of the matvec passes (off by default)
     struct ProfRec {
         int32_t pass, level;
@@ -153,6 +167,12 @@ void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ld
 void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                       int precision, hipStream_t s);
 void free_multi(nnca_h2 *H);
+void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s);
+void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, double *y, hipStream_t s);
+// grad.hip
+void run_backward(nnca_h2 *H, const double *X, const double *G, int64_t nrhs, int64_t ldx, int64_t ldg,
+                  int precision, double *DX, int64_t lddx, double *dldh, hipStream_t s);
+void free_grad(nnca_h2 *H);
 enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4 };
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
                 const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);

@@ -68,6 +68,7 @@ def lib():
             "nnca_build": [P, i64, i32, i64, i32, i32, f64, f64, i32, P, P, P],
             "nnca_matvec": [P, P, P, i64, i64, i64, i32, P],
             "nnca_matvec_adjoint": [P, P, P, i64, i64, i64, i32, P],
+            "nnca_matvec_backward": [P, P, P, i64, i64, i64, i32, P, i64, P, P],
             "nnca_direct": [P, i64, i32, i64, i32, f64, P, P, i64, i64, i64, P],
             "nnca_query": [P, P],
             "nnca_export_order": [P, P],
@@ -124,6 +125,7 @@ class H2Matrix:
         pts = torch.as_tensor(points, dtype=torch.float64)
         n, d = pts.shape
         self.n, self.dim, self.kernel = n, d, kernel
+        self.length_scale = float(length_scale)
         soa = pts.t().contiguous().to(self.device)
         opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes), int(rank_reserve), 0)
         if eta2 is not None:
@@ -142,8 +144,9 @@ class H2Matrix:
             self._destroy(self._h)
         self._h = None
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # module globals may already be gone at interpreter exit
+        if not _finalizing():
             self.close()
 
     def _apply(self, X, precision: str, adjoint: bool, out=None):
@@ -163,6 +166,39 @@ class H2Matrix:
     def rmatvec(self, X, precision: str = "fp64"):
         """Y = A~^T X."""
         return self._apply(X, precision, True)
+
+    def backward(self, X, G, precision: str = "fp64", need_x: bool = True, need_h: bool = True):
+        """Backward of Y = A~ X with G = dL/dY: (A~^T G or None, dL/dh or
+        None); dL/dh (Gaussian kernel, pivots frozen) is a 0-dim FP64 device
+        tensor."""
+        torch = self.torch
+        Xc, r, vec = _as_columns(torch, X, self.n, self.device)
+        Gc, rg, _ = _as_columns(torch, G, self.n, self.device)
+        if rg != r:
+            raise ValueError("X and G have different numbers of columns")
+        DX = torch.empty((r, self.n), dtype=torch.float64, device=self.device) if need_x else None
+        dh = torch.zeros((), dtype=torch.float64, device=self.device) if need_h else None
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_matvec_backward(
+                self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Gc.data_ptr()), r, self.n, self.n,
+                PRECISION[precision], None if DX is None else C.c_void_p(DX.data_ptr()), self.n,
+                None if dh is None else C.c_void_p(dh.data_ptr()), _stream(torch)))
+        if DX is not None:
+            DX = DX.reshape(self.n) if vec else DX.t()
+        return DX, dh
+
+    def apply(self, X, length_scale=None, precision: str = "fp64"):
+        """Differentiable Y = A~ X (torch.autograd): gradients flow to X and,
+        for the Gaussian kernel, to ``length_scale`` -- a tensor holding the
+        length scale the handle was built with (pivots frozen)."""
+        fn = _autograd_function(self.torch)
+        if length_scale is not None:
+            if self.kernel != "gauss":
+                raise ValueError("a length scale is differentiable for the Gaussian kernel only")
+            hv = float(length_scale.detach())
+            if abs(hv - self.length_scale) > 1e-14 * self.length_scale:
+                raise ValueError(f"length_scale {hv} differs from the built {self.length_scale}; rebuild the handle")
+        return fn.apply(X, length_scale, self, precision)
 
     def matvec_raw(self, Xc, Y, nrhs: int, precision: str = "fp64"):
         """Column-major device buffers (nrhs, n) in, (nrhs, n) out; no copies."""
@@ -235,6 +271,38 @@ class H2Matrix:
         Cm = np.zeros(max(m.value * k.value, 1))
         _check(lib().nnca_export_operator(self._h, level, cell, _np_ptr(Cm), Cm.size, C.byref(m), C.byref(k)))
         return Cm[: m.value * k.value].reshape(m.value, k.value)
+
+
+_fn_cache = {}
+
+
+def _autograd_function(torch):
+    """torch.autograd.Function over nnca_matvec / nnca_matvec_backward."""
+    if "fn" not in _fn_cache:
+        class H2Apply(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, x, h, op, precision):
+                ctx.op, ctx.precision = op, precision
+                ctx.h_meta = None if h is None else (h.device, h.dtype, h.shape)
+                ctx.save_for_backward(x)
+                return op._apply(x, precision, False)
+
+            @staticmethod
+            def backward(ctx, gy):
+                (x,) = ctx.saved_tensors
+                need_x, need_h = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+                if not (need_x or need_h):
+                    return None, None, None, None
+                dx, dh = ctx.op.backward(x, gy, ctx.precision, need_x, need_h)
+                if dx is not None:
+                    dx = dx.to(dtype=x.dtype)
+                if dh is not None:
+                    dev, dt, shp = ctx.h_meta
+                    dh = dh.to(device=dev, dtype=dt).reshape(shp)
+                return dx, dh, None, None
+
+        _fn_cache["fn"] = H2Apply
+    return _fn_cache["fn"]
 
 
 def direct(points, X, kernel: str = "inv_r", length_scale: float = 1.0, device="cuda:0"):
