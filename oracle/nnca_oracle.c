@@ -357,7 +357,7 @@ orc_tree *orc_tree_build(const double *pts, int64_t n, int d, int leaf_size,
         }
 
     /* Cells of every level: the distinct key prefixes, in ascending order. */
-    T->lev = (olevel *)calloc((size_t)T->kappa + 1u, sizeof(olevel));
+    T->lev = (olevel *)calloc((size_t)(T->kappa >= 0 ? T->kappa + 1 : 1), sizeof(olevel));
     for (int l = 0; l <= T->kappa; l++) {
         olevel *lv = &T->lev[l];
         int shift = d * (T->kmax - l);
