@@ -70,8 +70,9 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3"],
-                    help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop")
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
+                         "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -84,6 +85,10 @@ def main():
 
     if args.config == "c3":
         return bench_many_rhs(args)
+    if args.config == "c4":
+        return bench_backward(args)
+    if args.config == "c5":
+        return bench_batch(args)
     dev = torch.device("cuda:0")
     p, x = workload("c2", n=args.n)
     n = p.shape[0]
@@ -228,6 +233,143 @@ def bench_many_rhs(args):
            "err_block_vs_fp64_max": err_block, "err_loop_vs_fp64_max": err_loop, "build_seconds": build_s,
            "interactions_per_column": inter,
            "block_interaction_columns_per_s": inter * R / (block_ms * 1e-3)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_backward(args):
+    """Gaussian kernel, N=200000 points of the two-component mixture (h=0.5,
+    leaf 128, tol 1e-6): one step is the mixed forward y = A~ x plus the
+    backward (A~^T g and dL/dh with the pivots frozen)."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import CONFIGS, cotangent, workload
+    dev = torch.device("cuda:0")
+    c = CONFIGS["c4"]
+    p, x = workload("c4")
+    n = p.shape[0]
+    g = cotangent("c4", n)
+    t0 = time.perf_counter()
+    H = nnca.H2Matrix(p, c["kernel"], c["tol"], c["leaf"], length_scale=c["h"], device=dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    X = torch.tensor(x[:, 0], device=dev)
+    G = torch.tensor(g, device=dev)
+    t0 = time.perf_counter()
+    dx64, dh64 = H.backward(X, G, "fp64")          # first call factors K(I, J) of every ACA cell
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    y64 = H.matvec(X, "fp64")
+
+    def step():
+        y = H.matvec(X, "mixed")
+        dx, dh = H.backward(X, G, "mixed")
+        return y, dx, dh
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y, dx, dh = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    fwd = []
+    for prec in ("mixed", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            H.matvec(X, prec)
+        torch.cuda.synchronize()
+        fwd.append((time.perf_counter() - t0) / args.steps * 1e3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        H.backward(X, G, "fp64")
+    torch.cuda.synchronize()
+    bwd64 = (time.perf_counter() - t0) / args.steps * 1e3
+    relerr = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    out = {"metric": "forward+backward steps/s (Gaussian H2 matvec, x- and h-gradient)", "value": 1e3 / ms,
+           "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"3D exp(-r^2/h^2), h={c['h']}, N={n} two-component Gaussian mixture, "
+                                  f"leaf {c['leaf']}, tol {c['tol']}, 1 RHS, mixed precision passes", "n": n},
+           "forward_ms_mixed": fwd[0], "forward_ms_fp64": fwd[1], "step_ms_fp64": fwd[1] + bwd64,
+           "dldh_mixed": float(dh), "dldh_fp64": float(dh64),
+           "dldh_rel_diff_mixed_vs_fp64": abs(float(dh) - float(dh64)) / abs(float(dh64)),
+           "y_rel_err_mixed_vs_fp64": relerr(y, y64), "dx_rel_err_mixed_vs_fp64": relerr(dx, dx64),
+           "backward_setup_seconds": setup_s, "build_seconds": build_s}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """32 independent 3D 1/r problems, N_b log-uniform in [1e4, 2e5] points
+    uniform in [-1,1]^3 (leaf 64, tol 1e-6), 8 RHS each, mixed precision:
+    the batch (one graph of merged launches, autotuned transverse-pass
+    splits) against the 32 problems applied one after another."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import batch_problem, batch_sizes
+    dev = torch.device("cuda:0")
+    sizes = batch_sizes()
+    R = 8
+    t0 = time.perf_counter()
+    hs, xs = [], []
+    for b, nb in enumerate(sizes):
+        p, x = batch_problem(b, nb, R)
+        hs.append(nnca.H2Matrix(p, "inv_r", 1e-6, 64, device=dev))
+        xs.append(x)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B = nnca.H2Batch(hs, graph=True, autotune=True)
+    torch.cuda.synchronize()
+    merge_s = time.perf_counter() - t0
+    rows = B.rows
+    X = torch.tensor(np.concatenate(xs, axis=0).T.copy(), device=dev)     # (R, rows)
+    Y = torch.empty_like(X)
+    t0 = time.perf_counter()
+    B.matvec_raw(X, Y, R, "mixed")              # eager run, autotune, capture
+    torch.cuda.synchronize()
+    capture_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        B.matvec_raw(X, Y, R, "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.matvec_raw(X, Y, R, "mixed")
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    Xs = [X[:, B.offsets[b]:B.offsets[b + 1]].contiguous() for b in range(len(hs))]
+    Ys = [torch.empty_like(v) for v in Xs]
+    Y64 = [torch.empty_like(v) for v in Xs]
+    for h, xb, yb in zip(hs, Xs, Y64):
+        h.matvec_raw(xb, yb, R, "fp64")
+
+    def separate():
+        for h, xb, yb in zip(hs, Xs, Ys):
+            h.matvec_raw(xb, yb, R, "mixed")
+
+    for _ in range(args.warmup):
+        separate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        separate()
+    torch.cuda.synchronize()
+    sep_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    err_b = max(float((torch.linalg.norm(Y[:, B.offsets[b]:B.offsets[b + 1]] - Y64[b], dim=1)
+                       / torch.linalg.norm(Y64[b], dim=1)).max()) for b in range(len(hs)))
+    err_s = max(float((torch.linalg.norm(Ys[b] - Y64[b], dim=1) / torch.linalg.norm(Y64[b], dim=1)).max())
+                for b in range(len(hs)))
+    out = {"metric": "batched matvec columns/s, 32 uneven problems x 8 RHS", "value": len(hs) * R / (batch_ms * 1e-3),
+           "unit": "columns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": batch_ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(hs)} independent 3D 1/r problems, N_b log-uniform in [1e4, 2e5] "
+                                  f"(sum {rows}), uniform in [-1,1]^3, leaf 64, tol 1e-6, {R} RHS each, mixed",
+                      "rows": rows, "sizes": sizes},
+           "separate_ms": sep_ms, "batch_speedup": sep_ms / batch_ms, "err_batch_vs_fp64_max": err_b,
+           "err_separate_vs_fp64_max": err_s, "build_seconds": build_s, "merge_seconds": merge_s,
+           "first_call_seconds": capture_s}
     print(json.dumps(out), flush=True)
 
 

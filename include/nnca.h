@@ -134,6 +134,45 @@ nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld
                         int32_t kernel_kind, double length_scale, const double *X, double *Y,
                         int64_t nrhs, int64_t ldx, int64_t ldy, void *stream);
 
+/* Uneven batches (many independent problems, one set of launches).
+ * nnca_batch_create merges the apply data of `count` built handles (same
+ * dim, kernel kind and length scale; each with a far field, i.e. kappa >=
+ * lmin) into one forest whose tree levels are aligned by their distance from
+ * the leaves; each pass of Sec. 4 then runs one launch per aligned level over
+ * the cells of every problem, the transverse pass and the near field as
+ * before.  The result is the block-diagonal product Y_b = A~_b X_b.  The
+ * batch copies what it needs: the handles may be destroyed afterwards.
+ * Blocking.  flags:
+ *   NNCA_BATCH_GRAPH     the first nnca_batch_matvec with a given (X, Y,
+ *                        nrhs, ldx, ldy, precision) runs eagerly, then
+ *                        captures the whole matvec into a HIP graph on the
+ *                        batch's own stream; later calls with the same
+ *                        arguments replay it (other arguments re-capture);
+ *   NNCA_BATCH_AUTOTUNE  the first call for a column-block width and
+ *                        precision times split factors 1, 2, 4, ..., 64 of
+ *                        every level's transverse-pass launch on the live
+ *                        data and keeps the fastest (many-column path).
+ * Errors: INVALID_ARG (NULL, count < 1, unknown flags, mismatched handles),
+ * NOT_SUPPORTED (a problem without a far field, more than 2^30 rows),
+ * OUT_OF_MEMORY, HIP.                                                     */
+typedef struct nnca_batch *nnca_batch_handle;
+enum { NNCA_BATCH_GRAPH = 1, NNCA_BATCH_AUTOTUNE = 2 };
+nnca_status nnca_batch_create(const nnca_handle *handles, int32_t count, int32_t flags, nnca_batch_handle *out);
+
+/* count, total rows and the count + 1 row offsets of the problems (host;
+ * any pointer may be NULL).  Problem b owns rows [offsets[b], offsets[b+1])
+ * of the batched vectors, in its own original point order.               */
+nnca_status nnca_batch_query(nnca_batch_handle b, int32_t *count, int64_t *rows, int64_t *offsets);
+
+/* Y = diag(A~_1, ..., A~_B) X for nrhs columns; X, Y: device FP64,
+ * column-major, rows as given by nnca_batch_query, leading dimensions >= the
+ * total rows; X and Y must not overlap.  Ordered after earlier work on
+ * `stream` and before later work on it (the batch runs on its own stream).
+ * A handle's batch may be used from one thread at a time.                  */
+nnca_status nnca_batch_matvec(nnca_batch_handle b, const double *X, double *Y, int64_t nrhs, int64_t ldx,
+                              int64_t ldy, int32_t precision, void *stream);
+nnca_status nnca_batch_destroy(nnca_batch_handle b);
+
 #define NNCA_MAX_LEVELS 64
 typedef struct {
     int64_t n;

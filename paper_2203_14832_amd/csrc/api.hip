@@ -61,7 +61,7 @@ static void clear_profile(nnca_h2 *H)
     H->prof.clear();
 }
 
-static void free_handle(nnca_h2 *H)
+void nnca::destroy_handle(nnca_h2 *H)
 {
     if (!H) return;
     clear_profile(H);
@@ -71,7 +71,7 @@ static void free_handle(nnca_h2 *H)
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
                       L.rem_pos, L.crem_off, L.crem64, L.crem_t, L.piv_cell, L.rem_cell, L.pc64, L.pc32,
-                      L.ilpre, L.ilsum, L.w64, L.u64};
+                      L.ilpre, L.ilsum, L.w64, L.u64, L.hcell};
         for (void *p : ps) dfree(p);
     }
     void *ps[] = {H->pts64, H->order, H->keys, H->nbpre, H->nbsum, H->xs64, H->far64, H->xhi, H->xlo, H->m2l_part};
@@ -170,7 +170,7 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
             HIPCHECK(hipStreamSynchronize(H->stream));
         } catch (...) {
             (void)hipStreamSynchronize(H->stream);
-            free_handle(H);
+            destroy_handle(H);
             throw;
         }
         H->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -243,6 +243,50 @@ nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G
         }
         run_backward(h, X, G, nrhs, ldx, ldg, precision, DX, lddx, dLdh, (hipStream_t)stream);
     });
+}
+
+nnca_status nnca_batch_create(const nnca_handle *handles, int32_t count, int32_t flags, nnca_batch_handle *out)
+{
+    return guarded([&] {
+        if (!handles || !out) fail(NNCA_ERR_INVALID_ARG, "NULL argument");
+        if (count < 1) fail(NNCA_ERR_INVALID_ARG, "count < 1");
+        if (flags & ~(NNCA_BATCH_GRAPH | NNCA_BATCH_AUTOTUNE)) fail(NNCA_ERR_INVALID_ARG, "unknown flags");
+        for (int32_t b = 0; b < count; b++)
+            if (!handles[b]) fail(NNCA_ERR_INVALID_ARG, "a handle is NULL");
+        *out = create_batch(handles, count, flags);
+    });
+}
+
+nnca_status nnca_batch_query(nnca_batch_handle b, int32_t *count, int64_t *rows, int64_t *offsets)
+{
+    return guarded([&] {
+        if (!b) fail(NNCA_ERR_INVALID_ARG, "batch is NULL");
+        if (count) *count = batch_count(b);
+        if (rows) *rows = batch_rows(b);
+        if (offsets) std::memcpy(offsets, batch_offsets(b), sizeof(int64_t) * (batch_count(b) + 1));
+    });
+}
+
+nnca_status nnca_batch_matvec(nnca_batch_handle b, const double *X, double *Y, int64_t nrhs, int64_t ldx,
+                              int64_t ldy, int32_t precision, void *stream)
+{
+    return guarded([&] {
+        if (!b) fail(NNCA_ERR_INVALID_ARG, "batch is NULL");
+        if (!X || !Y) fail(NNCA_ERR_INVALID_ARG, "X or Y is NULL");
+        if (nrhs < 1) fail(NNCA_ERR_INVALID_ARG, "nrhs < 1");
+        const int64_t n = batch_rows(b);
+        if (ldx < n || ldy < n) fail(NNCA_ERR_INVALID_ARG, "leading dimension < total rows");
+        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+        const char *xb = (const char *)X, *xe = (const char *)(X + (nrhs - 1) * ldx + n);
+        const char *yb = (const char *)Y, *ye = (const char *)(Y + (nrhs - 1) * ldy + n);
+        if (xb < ye && yb < xe) fail(NNCA_ERR_INVALID_ARG, "X and Y overlap");
+        run_batch(b, X, Y, nrhs, ldx, ldy, precision, (hipStream_t)stream);
+    });
+}
+
+nnca_status nnca_batch_destroy(nnca_batch_handle b)
+{
+    return guarded([&] { destroy_batch(b); });
 }
 
 nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t kernel_kind,
@@ -415,7 +459,7 @@ nnca_status nnca_destroy(nnca_handle h)
     return guarded([&] {
         if (h) {
             (void)hipStreamSynchronize(h->stream);
-            free_handle(h);
+            destroy_handle(h);
         }
     });
 }

@@ -209,8 +209,8 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
                                             const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                             const int32_t *ilsum,
                                             const typename M2LTypes<MODE>::C *pc, int64_t npiv,
-                                            const int32_t *coord, float h, int d, const double *w, double *u,
-                                            double *part_out, double prm64)
+                                            const int32_t *coord, const float *hc, float h0, int d,
+                                            const double *w, double *u, double *part_out, double prm64)
 {
     using T = typename M2LTypes<MODE>::C;
     using T4 = typename M2LTypes<MODE>::V;
@@ -225,6 +225,7 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
     const int32_t e0 = il_ptr[c], e1 = il_ptr[c + 1];
     const T prm = (T)prm64;
     int32_t cc[3] = {coord[c], coord[nc + c], d == 3 ? coord[2 * nc + c] : 0};
+    const float h = hc ? hc[c] : h0;   // cell side (per cell when the level mixes problems)
     double *dst = P > 1 ? part_out + (int64_t)pp * npiv : u;
     for (int32_t tb = 0; tb < kk; tb += NT * RB) {
         Split sp(kk, tb, t);
@@ -565,7 +566,7 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
         part = H->m2l_part;
     }
     const int g = (int)(nc * P);
-#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, L.coord, (float)L.h, H->dim, L.w64, L.u64, part, prm
+#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, L.w64, L.u64, part, prm
 #define M2L_CASE(K) k_m2l<K, MODE, M2L_TILE><<<g, NT, 0, s>>>(M2L_ARGS);
     if (kind == NNCA_K_INV_R) { M2L_CASE(NNCA_K_INV_R) }
     else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }

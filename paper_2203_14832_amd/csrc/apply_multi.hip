@@ -144,8 +144,8 @@ template <int KIND, int NCB>
 __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                  const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                  const int32_t *ilsum, const float *pc, int64_t npiv,
-                                                 const int32_t *coord, float h, int d, const double *w, double *u,
-                                                 double *part_out, float prm)
+                                                 const int32_t *coord, const float *hc, float h0, int d,
+                                                 const double *w, double *u, double *part_out, float prm)
 {
     constexpr int RP = NCB * 16;
     constexpr int TS = 128;
@@ -162,6 +162,7 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
     const int32_t sb = (int32_t)(((int64_t)S * pp) / P), se = (int32_t)(((int64_t)S * (pp + 1)) / P);
     const int32_t e0 = il_ptr[c], e1 = il_ptr[c + 1];
     const int32_t cc0 = coord[c], cc1 = coord[nc + c], cc2 = d == 3 ? coord[2 * nc + c] : 0;
+    const float h = hc ? hc[c] : h0;   // cell side (per cell when the level mixes problems)
     double *dst = P > 1 ? part_out + (int64_t)pp * npiv * RP : u;
     const int32_t ntb = (kk + 15) / 16;
     for (int32_t tb0 = 0; tb0 < ntb; tb0 += 4) {
@@ -490,6 +491,114 @@ int parts_for(const Level &L)
     return P < 1 ? 1 : (int)P;
 }
 
+// transverse pass of one level for a block of NCB * 16 columns, split P ways
+template <int NCB>
+void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
+{
+    constexpr int RP = NCB * 16;
+    auto &W = H->multi;
+    Level &L = H->lev[l];
+    const int kap = H->kappa, kind = H->kind;
+    const double prm64 = 1.0 / (H->hparam * H->hparam);
+    const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
+    double *part = P > 1 ? W.part : nullptr;
+    const int g = (int)(L.ncell * P);
+    if (mixed && l >= kap - 1) {
+#define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w[l], W.u[l], part, prm32)
+        if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
+        else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
+        else MF(NNCA_K_GAUSS);
+#undef MF
+    } else {
+#define VM(K, M) k_m2l_mfma64<K, M, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc64, L.npiv, H->dim, W.w[l], W.u[l], part, prm64)
+        if (!mixed) {
+            if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 1);
+            else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 1);
+            else VM(NNCA_K_GAUSS, 1);
+        } else {
+            if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 2);
+            else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 2);
+            else VM(NNCA_K_GAUSS, 2);
+        }
+#undef VM
+    }
+    HIPCHECK(hipGetLastError());
+    if (P > 1) {
+        k_sum_parts_multi<<<grid_for(L.npiv * RP, 256), 256, 0, s>>>(L.npiv * RP, P, part, W.u[l]);
+        HIPCHECK(hipGetLastError());
+    }
+}
+
+// partial-result workspace for the split factors in use (never inside a
+// captured region: the first call with a new table allocates)
+void ensure_part(nnca_h2 *H, int RP, const std::vector<int32_t> *tab)
+{
+    auto &W = H->multi;
+    int64_t need = 1;
+    for (int l = H->lmin; l <= H->kappa; l++) {
+        const Level &L = H->lev[l];
+        const int P = tab ? (*tab)[l] : parts_for(L);
+        if (P > 1) need = std::max(need, (int64_t)P * L.npiv * RP);
+    }
+    if (W.part_cap >= need) return;
+    dfree(W.part);
+    W.part = nullptr;
+    W.part = dalloc<double>(need);
+    W.part_cap = need;
+}
+
+// Autotuner of the transverse pass: for every level, time the launch (and the
+// ordered sum of the partial vectors) for split factors P = 1, 2, 4, ..., 64
+// on the multipole vectors already in place, and keep the fastest.  Factors
+// that leave a part without a full source tile, put more than 2^18
+// workgroups in flight or need more than 1 GiB of partial vectors are not
+// tried.
+template <int NCB>
+std::vector<int32_t> tune_m2l_multi(nnca_h2 *H, bool mixed, hipStream_t s)
+{
+    constexpr int RP = NCB * 16;
+    std::vector<int32_t> best(H->kappa + 1, 1);
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    try {
+        for (int l = H->lmin; l <= H->kappa; l++) {
+            const Level &L = H->lev[l];
+            std::vector<int32_t> cand;
+            for (int P = 1; P <= 64; P *= 2) {
+                if (P > 1 && (int64_t)P * 128 > L.max_ilsum) break;
+                if ((int64_t)P * L.ncell > (1 << 18)) break;
+                if ((int64_t)P * L.npiv * RP * 8 > ((int64_t)1 << 30)) break;
+                cand.push_back(P);
+            }
+            float tbest = 0.f;
+            for (int32_t P : cand) {
+                std::vector<int32_t> one(H->kappa + 1, 1);
+                one[l] = P;
+                ensure_part(H, RP, &one);
+                m2l_level_multi<NCB>(H, l, P, mixed, s);   // warm
+                HIPCHECK(hipEventRecord(a, s));
+                for (int rep = 0; rep < 3; rep++) m2l_level_multi<NCB>(H, l, P, mixed, s);
+                HIPCHECK(hipEventRecord(b, s));
+                HIPCHECK(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPCHECK(hipEventElapsedTime(&ms, a, b));
+                if (P == cand[0] || ms < tbest) {
+                    tbest = ms;
+                    best[l] = P;
+                }
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        throw;
+    }
+    HIPCHECK(hipEventDestroy(a));
+    HIPCHECK(hipEventDestroy(b));
+    return best;
+}
+
 template <int NCB>
 void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int64_t ldy, int precision,
                  hipStream_t s)
@@ -519,36 +628,15 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
                                                   L.crem64, src, W.w[l]);
             HIPCHECK(hipGetLastError());
         }
-        for (int l = lmin; l <= kap; l++) {
-            Level &L = H->lev[l];
-            const int P = parts_for(L);
-            double *part = P > 1 ? W.part : nullptr;
-            const int g = (int)(L.ncell * P);
-            if (mixed && l >= kap - 1) {
-#define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, (float)L.h, H->dim, W.w[l], W.u[l], part, prm32)
-                if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
-                else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
-                else MF(NNCA_K_GAUSS);
-#undef MF
-            } else {
-#define VM(K, M) k_m2l_mfma64<K, M, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc64, L.npiv, H->dim, W.w[l], W.u[l], part, prm64)
-                if (!mixed) {
-                    if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 1);
-                    else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 1);
-                    else VM(NNCA_K_GAUSS, 1);
-                } else {
-                    if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 2);
-                    else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 2);
-                    else VM(NNCA_K_GAUSS, 2);
-                }
-#undef VM
-            }
-            HIPCHECK(hipGetLastError());
-            if (P > 1) {
-                k_sum_parts_multi<<<grid_for(L.npiv * RP, 256), 256, 0, s>>>(L.npiv * RP, P, part, W.u[l]);
-                HIPCHECK(hipGetLastError());
-            }
+        const std::vector<int32_t> *tab = nullptr;
+        if (H->autotune) {
+            const int key = NCB * 2 + (mixed ? 1 : 0);
+            auto it = H->m2l_tuned.find(key);
+            if (it == H->m2l_tuned.end()) it = H->m2l_tuned.emplace(key, tune_m2l_multi<NCB>(H, mixed, s)).first;
+            tab = &it->second;
         }
+        ensure_part(H, RP, tab);
+        for (int l = lmin; l <= kap; l++) m2l_level_multi<NCB>(H, l, tab ? (*tab)[l] : parts_for(H->lev[l]), mixed, s);
         far = W.far;
         for (int l = lmin; l <= kap; l++) {
             Level &L = H->lev[l];
@@ -593,6 +681,7 @@ void ensure_multi(nnca_h2 *H, int RP)
         part = std::max(part, (int64_t)parts_for(L) * L.npiv * RP);
     }
     W.part = dalloc<double>(part);
+    W.part_cap = part;
     W.rp = RP;
 }
 

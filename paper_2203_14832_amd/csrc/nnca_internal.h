@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,7 @@ struct Level {
     std::vector<int32_t> h_k, h_m;   // host copies
     int32_t max_ilsum = 0;
     int64_t m2l_inter = 0;           // sum over IL pairs of k_B k_B' at this level
+    float *hcell = nullptr;          // per-cell side, set when a level holds cells of several problems
 
     // apply state (one right-hand side at a time): multipole / local vectors
     double *w64 = nullptr, *u64 = nullptr;
@@ -124,9 +126,14 @@ struct nnca_h2 {
     struct Multi {
         int rp = 0;
         double *xs = nullptr, *far = nullptr, *part = nullptr;
+        int64_t part_cap = 0;
         float *xhi = nullptr, *xlo = nullptr;
         std::vector<double *> w, u;   // per level
     } multi;
+    // transverse-pass split factors per level picked by timing (autotune on),
+    // keyed by column-block width and precision
+    bool autotune = false;
+    std::map<int, std::vector<int32_t>> m2l_tuned;
     int64_t m2l_inter = 0, p2p_inter = 0, transfer_entries = 0;
 
     // state of the length-scale derivative (set up on first use; pivots frozen)
@@ -173,6 +180,16 @@ void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p,
 void run_backward(nnca_h2 *H, const double *X, const double *G, int64_t nrhs, int64_t ldx, int64_t ldg,
                   int precision, double *DX, int64_t lddx, double *dldh, hipStream_t s);
 void free_grad(nnca_h2 *H);
+// api.hip
+void destroy_handle(nnca_h2 *H);
+// batch.hip
+nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags);
+void destroy_batch(nnca_batch *B);
+void run_batch(nnca_batch *B, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
+               hipStream_t cs);
+int64_t batch_rows(const nnca_batch *B);
+int32_t batch_count(const nnca_batch *B);
+const int64_t *batch_offsets(const nnca_batch *B);
 enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4 };
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
                 const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);

@@ -80,6 +80,10 @@ def lib():
             "nnca_destroy": [P],
             "nnca_profile_enable": [P, i32],
             "nnca_profile_read": [P, P, P, P, P, i64],
+            "nnca_batch_create": [P, i32, i32, P],
+            "nnca_batch_query": [P, P, P, P],
+            "nnca_batch_matvec": [P, P, P, i64, i64, i64, i32, P],
+            "nnca_batch_destroy": [P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -271,6 +275,55 @@ class H2Matrix:
         Cm = np.zeros(max(m.value * k.value, 1))
         _check(lib().nnca_export_operator(self._h, level, cell, _np_ptr(Cm), Cm.size, C.byref(m), C.byref(k)))
         return Cm[: m.value * k.value].reshape(m.value, k.value)
+
+
+class H2Batch:
+    """Uneven batch of built handles applied by one set of launches
+    (``nnca_batch_create``): Y_b = A~_b X_b for every problem b, rows of the
+    batched vectors stacked in handle order."""
+
+    GRAPH, AUTOTUNE = 1, 2
+
+    def __init__(self, handles, graph: bool = True, autotune: bool = True):
+        import torch
+        self.torch = torch
+        self.device = handles[0].device
+        arr = (C.c_void_p * len(handles))(*[h._h.value for h in handles])
+        b = C.c_void_p()
+        flags = (self.GRAPH if graph else 0) | (self.AUTOTUNE if autotune else 0)
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_batch_create(arr, len(handles), flags, C.byref(b)))
+        self._b = b
+        self._destroy = lib().nnca_batch_destroy
+        cnt, rows = C.c_int32(), C.c_int64()
+        _check(lib().nnca_batch_query(b, C.byref(cnt), C.byref(rows), None))
+        off = np.zeros(cnt.value + 1, np.int64)
+        _check(lib().nnca_batch_query(b, None, None, _np_ptr(off)))
+        self.count, self.rows, self.offsets = cnt.value, rows.value, off
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._destroy(self._b)
+        self._b = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():
+            self.close()
+
+    def matvec_raw(self, Xc, Y, nrhs: int, precision: str = "fp64"):
+        """Column-major device buffers (nrhs, rows) in and out; no copies."""
+        _check(lib().nnca_batch_matvec(self._b, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs,
+                                       self.rows, self.rows, PRECISION[precision], _stream(self.torch)))
+
+    def matvec(self, X, precision: str = "fp64"):
+        """Y = diag(A~_b) X for a (rows,) or (rows, r) FP64 tensor."""
+        torch = self.torch
+        Xc, r, vec = _as_columns(torch, X, self.rows, self.device)
+        Y = torch.empty((r, self.rows), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            self.matvec_raw(Xc, Y, r, precision)
+        return Y.reshape(self.rows) if vec else Y.t()
 
 
 _fn_cache = {}

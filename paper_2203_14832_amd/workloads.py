@@ -66,6 +66,14 @@ def workload(config: str, n: int | None = None, nrhs: int | None = None, seed_of
     return pts, x
 
 
+def cotangent(config: str, n: int | None = None) -> np.ndarray:
+    """(n,) FP64 seeded output cotangent g = dL/dy ~ N(0,1) for the backward
+    of a configuration (its own stream, seed + 100)."""
+    c = CONFIGS[config]
+    n = c["n"] if n is None else int(n)
+    return np.random.default_rng(seed_of(config) + 100).standard_normal(n)
+
+
 def batch_sizes(count: int = 32, lo: float = 1e4, hi: float = 2e5, seed: int = 1004):
     """Sizes of the uneven batch: N_b = round(exp(U(ln lo, ln hi)))."""
     ss = np.random.SeedSequence(seed).spawn(count)
