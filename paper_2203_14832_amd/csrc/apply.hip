@@ -200,6 +200,8 @@ template <> struct M2LTypes<M_F32> { using C = float; using V = float4; };
 template <> struct M2LTypes<M_F64> { using C = double; using V = double4; };
 template <> struct M2LTypes<M_F64R> { using C = double; using V = double4; };
 
+constexpr int ET = 256;   // interaction-list entries staged in LDS at a time
+
 // transverse pass at one level: u^{B,i} = sum_{B' in IL(B)} K(t^{B,i}, t^{B',i}) w^{B',o}.
 // Launched with nc * P workgroups: part p of a cell takes the p-th of P equal
 // slices of its source list; with P > 1 the partial vectors go to `part_out`
@@ -217,6 +219,8 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
     constexpr int SPT = TILE / NT;   // sources loaded per thread per tile
     __shared__ T4 src[TILE];
     __shared__ double part[NT * RB];
+    __shared__ int32_t est[ET + 1], ebase[ET];
+    __shared__ float esh[3][ET];
     const int t = threadIdx.x;
     const int64_t c = blockIdx.x / P;
     const int pp = blockIdx.x % P;
@@ -243,41 +247,71 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
             acc[r] = 0.0;
         }
         // first list entry holding source sb
-        int32_t e = e0;
+        int32_t efirst = e0;
         {
             int32_t lo = e0, hi = e1 - 1;
             while (lo < hi) {
                 int32_t mid = (lo + hi + 1) >> 1;
                 if (ilpre[mid] <= sb) lo = mid; else hi = mid - 1;
             }
-            e = lo;
+            efirst = lo;
         }
-        for (int32_t s0 = sb; s0 < se; s0 += TILE) {
+        // windows of ET list entries staged in LDS: first source, pivot
+        // base and (FP32 form) the cell offset of every entry
+        for (int32_t w0 = efirst; w0 < e1; w0 += ET) {
+            const int32_t wn = e1 - w0 < ET ? e1 - w0 : ET;
+            __syncthreads();
+            for (int32_t j = t; j < wn; j += NT) {
+                const int32_t e = w0 + j, b = il[e], pre = ilpre[e];
+                est[j] = pre;
+                ebase[j] = piv_ptr[b] - pre;
+                if (MODE == M_F32) {
+                    esh[0][j] = (float)(coord[b] - cc[0]) * h;
+                    esh[1][j] = (float)(coord[nc + b] - cc[1]) * h;
+                    esh[2][j] = d == 3 ? (float)(coord[2 * nc + b] - cc[2]) * h : 0.f;
+                }
+            }
+            if (t == 0) est[wn] = w0 + wn < e1 ? ilpre[w0 + wn] : S;
+            __syncthreads();
+            const int32_t ws = est[0] > sb ? est[0] : sb, we = est[wn] < se ? est[wn] : se;
+            if (est[0] >= se) break;
+        for (int32_t s0 = ws; s0 < we; s0 += TILE) {
+            const int32_t send = we - s0 < TILE ? we : s0 + TILE;
+            // contiguous sources per thread: one search, then at most a few steps
             T4 v[SPT];
+            const int32_t sfirst = s0 + t * SPT;
+            int32_t ej = 0;
+            if (sfirst < send) {
+                int32_t lo = 0, hi = wn - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (est[mid] <= sfirst) lo = mid; else hi = mid - 1;
+                }
+                ej = lo;
+            }
 #pragma unroll
             for (int q = 0; q < SPT; q++) {
-                int32_t s = s0 + q * NT + t;
+                const int32_t s = sfirst + q;
                 v[q].x = 0; v[q].y = 0; v[q].z = 0; v[q].w = 0;
-                if (s < se) {
-                    while (e + 1 < e1 && ilpre[e + 1] <= s) e++;
-                    int32_t b = il[e];
-                    int32_t idx = piv_ptr[b] + (s - ilpre[e]);
+                if (s < send) {
+                    while (est[ej + 1] <= s) ej++;
+                    const int32_t idx = ebase[ej] + s;
                     v[q].x = pc[idx];
                     v[q].y = pc[npiv + idx];
                     v[q].z = d == 3 ? pc[2 * npiv + idx] : T(0);
                     v[q].w = (T)w[idx];
                     if (MODE == M_F32) {
-                        v[q].x += (T)(coord[b] - cc[0]) * h;
-                        v[q].y += (T)(coord[nc + b] - cc[1]) * h;
-                        if (d == 3) v[q].z += (T)(coord[2 * nc + b] - cc[2]) * h;
+                        v[q].x += esh[0][ej];
+                        v[q].y += esh[1][ej];
+                        v[q].z += esh[2][ej];
                     }
                 }
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < SPT; q++) src[q * NT + t] = v[q];
+            for (int q = 0; q < SPT; q++) src[t * SPT + q] = v[q];
             __syncthreads();
-            int32_t ns = se - s0 < TILE ? se - s0 : TILE;
+            const int32_t ns = send - s0;
             if (act) {
                 if (MODE == M_F32) {
                     for (int32_t j = sp.g; j < ns;) {
@@ -310,6 +344,7 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
                     }
                 }
             }
+        }
         }
         __syncthreads();
         if (act)
@@ -355,6 +390,7 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, co
     };
     __shared__ Src src[NT];
     __shared__ double part[NT * RB], part2[NT * RB];
+    __shared__ int32_t est[ET + 1], ebase[ET];
     const int t = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int32_t kk = count[c], po = first[c], S = nbsum[c];
@@ -376,14 +412,29 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, co
             acc[r] = 0.0;
             acc2[r] = 0.0;
         }
-        int32_t e = e0;
-        for (int32_t s0 = 0; s0 < S; s0 += NT) {
+        // windows of ET neighbour entries staged in LDS (first source, point base)
+        for (int32_t w0 = e0; w0 < e1; w0 += ET) {
+            const int32_t wn = e1 - w0 < ET ? e1 - w0 : ET;
+            __syncthreads();
+            for (int32_t j = t; j < wn; j += NT) {
+                const int32_t e = w0 + j, pre = nbpre[e];
+                est[j] = pre;
+                ebase[j] = first[nb[e]] - pre;
+            }
+            if (t == 0) est[wn] = w0 + wn < e1 ? nbpre[w0 + wn] : S;
+            __syncthreads();
+            const int32_t ws = est[0], we = est[wn];
+        for (int32_t s0 = ws; s0 < we; s0 += NT) {
             int32_t s = s0 + t;
             Src v;
             v.x = 0; v.y = 0; v.z = 0; v.w = 0; v.w2 = 0;
-            if (s < S) {
-                while (e + 1 < e1 && nbpre[e + 1] <= s) e++;
-                int32_t idx = first[nb[e]] + (s - nbpre[e]);
+            if (s < we) {
+                int32_t lo = 0, hi = wn - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (est[mid] <= s) lo = mid; else hi = mid - 1;
+                }
+                int32_t idx = ebase[lo] + s;
                 v.x = pts[idx];
                 v.y = pts[n + idx];
                 v.z = d == 3 ? pts[2 * n + idx] : 0.0;
@@ -393,7 +444,7 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, co
             __syncthreads();
             src[t] = v;
             __syncthreads();
-            int32_t ns = S - s0 < NT ? S - s0 : NT;
+            int32_t ns = we - s0 < NT ? we - s0 : NT;
             if (act) {
                 for (int32_t j = sp.g; j < ns;) {
                     int32_t je = j + CHUNK * sp.G < ns ? j + CHUNK * sp.G : ns;
@@ -418,6 +469,7 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, co
                     }
                 }
             }
+        }
         }
         __syncthreads();
         if (act)
