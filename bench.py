@@ -27,16 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H2 matvecs/s at N=1M 3D 1/r, mixed vs FP64 at rel.err≤1e-6; % roofline"
-# Roofline of the dominant kernel, the FP32 transverse pass (M2L) of the two
-# finest levels.  Its bound is plain VALU arithmetic.  Peak FP32 vector rate
-# of the chip: 157.3 TFLOP/s = 256 CU x 128 lanes/clock x 2.4 GHz x 2 (FMA),
-# i.e. 7.864e13 lane-instructions/s.  One interaction needs 3 subtractions,
-# 1 multiply and 2 FMA for r^2, one v_rsq_f32 and 1 FMA: 7 full-rate
-# instructions plus one transcendental at quarter rate (4 issue slots), 11
-# slots in all.
+# Roofline of the dominant kernel, the symmetric FP32 transverse pass (M2L)
+# of the two finest levels.  Its bound is plain VALU arithmetic.  Peak FP32
+# vector rate of the chip: 157.3 TFLOP/s = 256 CU x 128 lanes/clock x
+# 2.4 GHz x 2 (FMA), i.e. 7.864e13 lane-instructions/s.  One unordered pair
+# of pivots costs 3 subtractions, 1 multiply and 2 FMA for r^2, one v_rsq_f32
+# (quarter rate: 4 issue slots) and 2 FMA (its row and its column term): 12
+# slots.  (The plain pass spends 11 slots on each ordered pair.)
 VALU_LANE_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_INTERACTION = 11.0
-PEAK_INTERACTIONS = VALU_LANE_SLOTS / SLOTS_PER_INTERACTION
+SLOTS_PER_PAIR = 12.0
+PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
 
 
 def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3):
@@ -119,10 +119,11 @@ def main():
     torch.cuda.synchronize()
     fp64_ms = (time.perf_counter() - t0) / k64 * 1e3
 
-    # timed mixed-precision steps, with per-launch events on the library stream
+    # timed mixed-precision steps; HIP events on the library stream bracket
+    # the launches of the transverse-pass kernel only
     run("mixed", Ym, args.warmup)
     torch.cuda.synchronize()
-    H.profile(True)
+    H.profile(True, passes=[2])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run("mixed", Ym, args.steps)
@@ -133,24 +134,33 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = args.steps / dt
 
-    # the same steps without event recording, for reference
+    # the same steps without any event, for reference
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run("mixed", Ym, args.steps)
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t0) / args.steps * 1e3
 
-    # FP32 M2L launches: the two finest levels (coarser levels run refined FP64)
+    # per-pass breakdown from separate (untimed) steps with every launch bracketed
+    H.profile(True)
+    run("mixed", Ym, 5)
+    torch.cuda.synchronize()
+    bp, bl, bm = H.profile_read()
+    H.profile(False)
+    breakdown = {name: float(bm[bp == i].sum() / 5)
+                 for i, name in enumerate(["gather", "up", "m2l", "down", "p2p", "m2l_combine"])}
+
+    # dominant kernel: the symmetric FP32 transverse pass of the two finest
+    # levels (coarser levels run the FP64-refined form)
     kap = info["kappa"]
     fine = (passes == 2) & (levels >= kap - 1)
     m2l_ms = ms[fine]
     m2l_per_step = m2l_ms.sum() / args.steps
     launches_per_step = m2l_ms.size / args.steps
     fine_inter = sum(info["m2l_level"][l] for l in range(max(kap - 1, 0), kap + 1))
-    m2l_rate = fine_inter / (m2l_per_step * 1e-3)
+    pairs = fine_inter / 2
+    pair_rate = pairs / (m2l_per_step * 1e-3)
     coarse_ms = float(ms[(passes == 2) & (levels < kap - 1)].sum() / args.steps)
-    breakdown = {name: float(ms[passes == i].sum() / args.steps)
-                 for i, name in enumerate(["gather", "up", "m2l", "down", "p2p"])}
 
     err_mixed = float(torch.linalg.norm(Ym - Y64) / torch.linalg.norm(Y64))
     out = {
@@ -160,13 +170,15 @@ def main():
         "config": {"workload": f"3D 1/r, N={n} uniform in [-1,1]^3, leaf 64, tol 1e-6, 1 RHS N(0,1), "
                                f"mixed FP32 apply with FP64 pivots/operators and FP64 near-field refinement",
                    "n": n, "kappa": info["kappa"], "leaf_size": 64, "tol": 1e-6, "nrhs": 1},
-        "roofline": {"bound": "alu", "achieved": m2l_rate / 1e9, "peak": PEAK_INTERACTIONS / 1e9,
-                     "unit": "G interactions/s", "frac": m2l_rate / PEAK_INTERACTIONS, "traffic": None,
-                     "kernel": "k_m2l<1/r, FP32, 1024> (levels kappa-1, kappa)",
+        "roofline": {"bound": "alu", "achieved": pair_rate / 1e9, "peak": PEAK_PAIRS / 1e9,
+                     "unit": "G pairs/s", "frac": pair_rate / PEAK_PAIRS, "traffic": None,
+                     "kernel": "k_m2l_sym<1/r, FP32> (levels kappa-1, kappa)",
                      "launches_per_step": launches_per_step,
                      "avg_launch_ms": float(m2l_ms.mean()) if m2l_ms.size else None,
-                     "interactions_per_launch": fine_inter / max(launches_per_step, 1),
-                     "peak_derivation": "7.864e13 FP32 lane-instr/s / 11 slots per interaction"},
+                     "pairs_per_launch": pairs / max(launches_per_step, 1),
+                     "directed_interactions_per_s": 2 * pair_rate,
+                     "peak_derivation": "7.864e13 FP32 lane-instr/s / 12 slots per pair "
+                                        "(r^2: 3 sub + mul + 2 fma; 1/r: v_rsq_f32 = 4; 2 fma)"},
         "m2l_coarse_fp64_ms_per_step": coarse_ms, "m2l_level_interactions": info["m2l_level"],
         "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,

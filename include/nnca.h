@@ -127,6 +127,19 @@ nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G
                                  int64_t ldg, int32_t precision, double *DX, int64_t lddx, double *dLdh,
                                  void *stream);
 
+/* Apply options of a handle, for the matvecs issued after the call.
+ *   NNCA_APPLY_NO_SYMMETRIC: the mixed form evaluates the FP32 transverse
+ *     blocks of its two finest levels for every ordered pair of interacting
+ *     cells.  By default (flags = 0) it uses the symmetric case of Sec. 5:
+ *     K(x, y) = K(y, x) and B' in IL(B) <=> B in IL(B') make the block of
+ *     (B', B) the transpose of that of (B, B'), so each unordered pair is
+ *     evaluated once and used for both directions.  The FP64 form always
+ *     evaluates every ordered pair.  Either choice gives the product to the
+ *     accuracy of the mixed form; summation orders differ.
+ * Errors: INVALID_ARG (NULL handle, unknown bits).                        */
+enum { NNCA_APPLY_NO_SYMMETRIC = 1 };
+nnca_status nnca_set_apply_flags(nnca_handle h, int32_t flags);
+
 /* Dense FP64 direct sum Y = A X with A_ij = K(p_i, p_j) (the plain
  * definition; used for error reports).  points: device, dim x n SoA with
  * stride ld; X, Y: device FP64 column-major.  Asynchronous on `stream`.    */
@@ -220,12 +233,15 @@ nnca_status nnca_export_operator(nnca_handle h, int32_t level, int64_t cell, dou
 nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int32_t dim,
                                    const double *a, const double *b, int64_t count, double *out);
 
-/* Per-launch timing of the matvec passes with HIP events recorded on the
- * matvec stream.  nnca_profile_enable(h, 1) starts recording (and clears
- * earlier records), 0 stops.  nnca_profile_read (blocking) copies up to
- * `cap` records -- pass (0 gather/split, 1 P2M/M2M, 2 M2L, 3 L2L/L2P,
- * 4 near field + combine), tree level (-1 for none) and milliseconds -- into
- * host arrays, stores the number of records in *count and clears them.     */
+/* Per-launch timing of the single-column matvec passes with HIP events
+ * recorded on the matvec stream.  nnca_profile_enable(h, mask) clears earlier
+ * records and records the launches of every pass p whose bit (1 << p) is set
+ * in mask (-1: all, 0: stop).  Passes: 0 gather/split, 1 P2M/M2M, 2 M2L
+ * (for the symmetric form, its kernel alone), 3 L2L/L2P, 4 near field +
+ * combine, 5 M2L combine (ordered sum of split parts, the partners' column
+ * slots).  nnca_profile_read (blocking) copies up to `cap` records -- pass,
+ * tree level (-1 for none) and milliseconds -- into host arrays, stores the
+ * number of records in *count and clears them.                             */
 nnca_status nnca_profile_enable(nnca_handle h, int32_t enable);
 nnca_status nnca_profile_read(nnca_handle h, int64_t *count, int32_t *pass, int32_t *level, double *ms,
                               int64_t cap);

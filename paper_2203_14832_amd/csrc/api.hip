@@ -71,7 +71,8 @@ void nnca::destroy_handle(nnca_h2 *H)
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
                       L.rem_pos, L.crem_off, L.crem64, L.crem_t, L.piv_cell, L.rem_cell, L.pc64, L.pc32,
-                      L.ilpre, L.ilsum, L.w64, L.u64, L.hcell};
+                      L.ilpre, L.ilsum, L.w64, L.u64, L.hcell, L.own_ptr, L.own_il, L.own_pre, L.own_sum,
+                      L.own_slot, L.non_ptr, L.non_slot, L.col32, L.col64};
         for (void *p : ps) dfree(p);
     }
     void *ps[] = {H->pts64, H->order, H->keys, H->nbpre, H->nbsum, H->xs64, H->far64, H->xhi, H->xlo, H->m2l_part};
@@ -209,6 +210,15 @@ nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64
                                 int32_t precision, void *stream)
 {
     return matvec_common(h, X, Y, nrhs, ldx, ldy, precision, stream);
+}
+
+nnca_status nnca_set_apply_flags(nnca_handle h, int32_t flags)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        if (flags & ~NNCA_APPLY_NO_SYMMETRIC) fail(NNCA_ERR_INVALID_ARG, "unknown apply flags");
+        h->apply_flags = flags;
+    });
 }
 
 nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G, int64_t nrhs, int64_t ldx,
@@ -431,7 +441,7 @@ nnca_status nnca_profile_enable(nnca_handle h, int32_t enable)
         if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
         HIPCHECK(hipStreamSynchronize(h->stream));
         clear_profile(h);
-        h->profiling = enable != 0;
+        h->prof_mask = enable;
     });
 }
 

@@ -75,13 +75,15 @@ __global__ void k_up(int64_t npiv, const int32_t *piv_cell, const int32_t *piv_p
     w[g] = acc;
 }
 
-// the same for levels whose cells have non-pivot rows: one workgroup per cell,
-// the inputs of those rows staged in LDS, rows split among thread groups
+// the same for levels whose cells have non-pivot rows: workgroup (c, y) takes
+// columns [y colw, (y + 1) colw) of cell c (levels with few cells split their
+// columns over several workgroups), the inputs of the non-pivot rows staged
+// in LDS, rows split among thread groups
 constexpr int UP_TILE = 1024;
 __global__ __launch_bounds__(256) void k_up_cell(const int32_t *piv_ptr, const int32_t *tt_off, const int32_t *ipos,
                                                  const int32_t *rem_ptr, const int32_t *rem_pos,
                                                  const int64_t *crem_off, const double *crem, const double *xin,
-                                                 double *w)
+                                                 double *w, int32_t colw)
 {
     __shared__ double xr[UP_TILE];
     __shared__ double red[256];
@@ -90,8 +92,11 @@ __global__ __launch_bounds__(256) void k_up_cell(const int32_t *piv_ptr, const i
     const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
     const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
     const double *C = crem + crem_off[c];
-    for (int32_t tb = 0; tb < kk; tb += 256) {
-        const int32_t cnt = kk - tb < 256 ? kk - tb : 256;
+    const int64_t cb64 = (int64_t)blockIdx.y * colw;
+    if (cb64 >= kk) return;   // uniform for the workgroup
+    const int32_t cb = (int32_t)cb64, ce = kk - cb < colw ? kk : cb + colw;
+    for (int32_t tb = cb; tb < ce; tb += 256) {
+        const int32_t cnt = ce - tb < 256 ? ce - tb : 256;
         const int32_t G = 256 / cnt, ti = t % cnt, g = t / cnt;
         double acc = 0.0;
         for (int32_t r0 = 0; r0 < nr; r0 += UP_TILE) {
@@ -217,8 +222,12 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
     using T = typename M2LTypes<MODE>::C;
     using T4 = typename M2LTypes<MODE>::V;
     constexpr int SPT = TILE / NT;   // sources loaded per thread per tile
-    __shared__ T4 src[TILE];
-    __shared__ double part[NT * RB];
+    // the source tile and, after the last tile of a target block, the
+    // per-thread row sums share one LDS buffer
+    constexpr size_t SRC_BYTES = sizeof(T4) * TILE, PART_BYTES = sizeof(double) * NT * RB;
+    __shared__ __align__(16) unsigned char smem[SRC_BYTES > PART_BYTES ? SRC_BYTES : PART_BYTES];
+    T4 *src = reinterpret_cast<T4 *>(smem);
+    double *part = reinterpret_cast<double *>(smem);
     __shared__ int32_t est[ET + 1], ebase[ET];
     __shared__ float esh[3][ET];
     const int t = threadIdx.x;
@@ -587,6 +596,299 @@ __global__ void k_transpose_blocks(int64_t nc, const int32_t *piv_ptr, const int
     }
 }
 
+// Symmetric transverse pass of one level.  K(x, y) = K(y, x) and B' in IL(B)
+// <=> B in IL(B'), so the block of the pair (B', B) is the transpose of the
+// block of (B, B').  The workgroups of cell B take the pairs it owns: for
+// each source pivot s of an owned partner B' they form K(t^{B,i}, s) once and
+// use it twice, for the row sums u^{B,i} += K w^{B',o} (in registers) and for
+// the column sum (K^T w^{B,o})_s (over a thread's targets, then over the
+// lanes of its group), which goes to the pair's slot of the column buffer.
+// k_m2l_gather then adds to every cell the slots of the pairs its partners
+// own, in list order.  Two arithmetic forms, as in the plain pass:
+//   M_F32   cell-local FP32 coordinates, FP32 kernel and products, row sums
+//           in FP32 chunks folded into FP64, FP32 column slots;
+//   M_F64R  FP64 coordinates and products, 1/r from an FP32 seed and one
+//           FP64 Newton step, FP64 column slots (the coarse levels of the
+//           mixed matvec).
+// Levels with few cells split each cell's owned sources over P workgroups;
+// their row sums go to P partial vectors added in order by k_sum_parts.
+
+// Sum over an aligned group of TPG (a power of two, at most 32) lanes, left
+// in every lane of the group: DPP quad permutations (xor 1, xor 2) and row
+// mirrors (lane i <-> 7 - i, then i <-> 15 - i, each pairing the two halves
+// of the group so far), then a swizzle exchanging the 16-lane halves.  The
+// exchanges move bits, so an FP64 value moves as two 32-bit halves.
+template <int CTRL>
+__device__ inline float lane_xchg(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double lane_xchg(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+__device__ inline float swap16(float v) { return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)); }
+__device__ inline double swap16(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_ds_swizzle(hi, 0x401F), __builtin_amdgcn_ds_swizzle(lo, 0x401F));
+}
+template <int TPG, typename T>
+__device__ inline T group_sum(T v)
+{
+    if (TPG > 1) v += lane_xchg<0xB1>(v);
+    if (TPG > 2) v += lane_xchg<0x4E>(v);
+    if (TPG > 4) v += lane_xchg<0x141>(v);
+    if (TPG > 8) v += lane_xchg<0x140>(v);
+    if (TPG > 16) v += swap16(v);
+    return v;
+}
+
+constexpr int SYM_MAXK = 256;   // largest rank of a level on this pass (one target tile)
+constexpr int SYM_TS = 512;     // sources per LDS tile
+
+struct SymArgs {
+    const int32_t *k, *piv_ptr, *own_ptr, *own_il, *own_pre, *own_sum, *own_slot;
+    const float *pc32;
+    const double *pc64;
+    int64_t npiv, nc;
+    const int32_t *coord;
+    const float *hc;
+    float h0;
+    int d, P;
+    const double *w;
+    double *u, *part;
+    float *col32;
+    double *col64;
+    double prm;
+};
+
+template <int MODE> struct SymT;
+template <> struct SymT<M_F32> { using T = float; using T4 = float4; };
+template <> struct SymT<M_F64R> { using T = double; using T4 = double4; };
+
+template <int MODE>
+struct SymShared {
+    using T4 = typename SymT<MODE>::T4;
+    union {   // the tiles, then (after the last tile) the per-thread row sums
+        struct {
+            T4 src[SYM_TS];
+            int32_t sslot[SYM_TS];
+        } tile;
+        double part[NT * 8];
+    } u;
+    int32_t est[ET + 1], ebase[ET], eslot[ET];
+    float esh[3][ET];
+};
+
+// Part pp of cell c.  Targets: groups of TPG lanes (aligned inside a
+// wavefront, TPG * R >= k), G = NT / TPG groups; target i is held by lane
+// i % TPG as its (i / TPG)-th register.  Group g takes sources g, g + G, ...
+// of each tile; all its lanes run the same sources, so the column partial of
+// a source is summed inside the group by group_sum; lane ti keeps the sums of
+// the sources whose running index is ti mod TPG and the group stores them
+// together once every TPG sources.
+template <int KIND, int MODE, int TPG, int R>
+__device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int pp, int32_t kk)
+{
+    using T = typename SymT<MODE>::T;
+    using T4 = typename SymT<MODE>::T4;
+    constexpr bool F32 = MODE == M_F32;
+    constexpr int G = NT / TPG;
+    constexpr int SPT = SYM_TS / NT;
+    const int t = threadIdx.x, g = t / TPG, ti = t % TPG;
+    const int32_t po = A.piv_ptr[c], S = A.own_sum[c];
+    const int32_t sb = (int32_t)(((int64_t)S * pp) / A.P), se = (int32_t)(((int64_t)S * (pp + 1)) / A.P);
+    const int32_t e0 = A.own_ptr[c], e1 = A.own_ptr[c + 1];
+    const int64_t nc = A.nc, npiv = A.npiv;
+    const int d = A.d;
+    const int32_t cc[3] = {A.coord[c], A.coord[nc + c], d == 3 ? A.coord[2 * nc + c] : 0};
+    const float h = A.hc ? A.hc[c] : A.h0;
+    const T *pc;
+    if constexpr (F32) pc = A.pc32; else pc = A.pc64;
+    double *dst = A.P > 1 ? A.part + (int64_t)pp * npiv : A.u;
+    T tx[R], ty[R], tz[R], tw[R];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int32_t i = ti + r * TPG;
+        const bool ok = i < kk;
+        const int32_t q = po + (ok ? i : 0);
+        tx[r] = pc[q];
+        ty[r] = pc[npiv + q];
+        tz[r] = d == 3 ? pc[2 * npiv + q] : T(0);
+        tw[r] = ok ? (T)A.w[q] : T(0);   // padding targets add nothing to column sums
+        acc[r] = 0.0;
+    }
+    const T prm = (T)A.prm;
+    // first owned entry holding source sb
+    int32_t efirst = e0;
+    {
+        int32_t lo = e0, hi = e1 - 1;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (A.own_pre[mid] <= sb) lo = mid; else hi = mid - 1;
+        }
+        efirst = lo;
+    }
+    for (int32_t w0 = efirst; w0 < e1; w0 += ET) {
+        const int32_t wn = e1 - w0 < ET ? e1 - w0 : ET;
+        __syncthreads();
+        for (int32_t j = t; j < wn; j += NT) {
+            const int32_t e = w0 + j, b = A.own_il[e], pre = A.own_pre[e];
+            sh.est[j] = pre;
+            sh.ebase[j] = A.piv_ptr[b] - pre;
+            sh.eslot[j] = A.own_slot[e];
+            if (F32) {
+                sh.esh[0][j] = (float)(A.coord[b] - cc[0]) * h;
+                sh.esh[1][j] = (float)(A.coord[nc + b] - cc[1]) * h;
+                sh.esh[2][j] = d == 3 ? (float)(A.coord[2 * nc + b] - cc[2]) * h : 0.f;
+            }
+        }
+        if (t == 0) sh.est[wn] = w0 + wn < e1 ? A.own_pre[w0 + wn] : S;
+        __syncthreads();
+        if (sh.est[0] >= se) break;
+        const int32_t ws = sh.est[0] > sb ? sh.est[0] : sb, we = sh.est[wn] < se ? sh.est[wn] : se;
+        for (int32_t s0 = ws; s0 < we; s0 += SYM_TS) {
+            const int32_t ns = we - s0 < SYM_TS ? we - s0 : SYM_TS;
+            // contiguous sources per thread: one search, then a few steps
+            T4 v[SPT];
+            int32_t sl[SPT];
+            const int32_t sfirst = s0 + t * SPT;
+            int32_t lo = 0;
+            if (sfirst < s0 + ns) {
+                int32_t hi = wn - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (sh.est[mid] <= sfirst) lo = mid; else hi = mid - 1;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < SPT; q++) {
+                const int32_t s = sfirst + q;
+                v[q].x = 0; v[q].y = 0; v[q].z = 0; v[q].w = 0;
+                sl[q] = 0;
+                if (s < s0 + ns) {
+                    while (sh.est[lo + 1] <= s) lo++;
+                    const int32_t idx = sh.ebase[lo] + s;
+                    v[q].x = pc[idx];
+                    v[q].y = pc[npiv + idx];
+                    v[q].z = d == 3 ? pc[2 * npiv + idx] : T(0);
+                    v[q].w = (T)A.w[idx];
+                    if (F32) {
+                        v[q].x += sh.esh[0][lo];
+                        v[q].y += sh.esh[1][lo];
+                        v[q].z += sh.esh[2][lo];
+                    }
+                    sl[q] = sh.eslot[lo] + s;
+                }
+            }
+            __syncthreads();   // the previous tile is done with src and sslot
+#pragma unroll
+            for (int q = 0; q < SPT; q++) {
+                sh.u.tile.src[t * SPT + q] = v[q];
+                sh.u.tile.sslot[t * SPT + q] = sl[q];
+            }
+            __syncthreads();
+            T a[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) a[r] = T(0);
+            T keep = T(0);
+            int32_t kj = -1;
+            int it = 0;
+            for (int32_t j = g; j < ns; j += G, it++) {
+                const T4 q = sh.u.tile.src[j];
+                T cp = T(0);
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const T dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
+                    T kv_;
+                    if constexpr (F32) kv_ = kv32<KIND>(dx * dx + dy * dy + dz * dz, prm);
+                    else kv_ = kv_refined<KIND, MODE>(dx * dx + dy * dy + dz * dz, prm);
+                    a[r] += kv_ * q.w;
+                    cp += kv_ * tw[r];
+                }
+                cp = group_sum<TPG>(cp);
+                if ((it & (TPG - 1)) == ti) {
+                    keep = cp;
+                    kj = j;
+                }
+                if ((it & (TPG - 1)) == TPG - 1) {
+                    if constexpr (F32) A.col32[sh.u.tile.sslot[kj]] = keep;
+                    else A.col64[sh.u.tile.sslot[kj]] = keep;
+                    kj = -1;
+                }
+                if (F32 && (it & (CHUNK - 1)) == CHUNK - 1) {
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        acc[r] += (double)a[r];
+                        a[r] = T(0);
+                    }
+                }
+            }
+            if (kj >= 0) {
+                if constexpr (F32) A.col32[sh.u.tile.sslot[kj]] = keep;
+                else A.col64[sh.u.tile.sslot[kj]] = keep;
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) acc[r] += (double)a[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; r++) sh.u.part[(g * TPG + ti) * R + r] = acc[r];
+    __syncthreads();
+    for (int32_t i = t; i < kk; i += NT) {
+        const int32_t li = i % TPG, r = i / TPG;
+        double sum = 0.0;
+        for (int gg = 0; gg < G; gg++) sum += sh.u.part[(gg * TPG + li) * R + r];
+        dst[po + i] = sum;
+    }
+}
+
+template <int KIND, int MODE>
+__global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
+{
+    __shared__ SymShared<MODE> sh;
+    const int64_t c = blockIdx.x / A.P;
+    const int pp = blockIdx.x % A.P;
+    const int32_t kk = A.k[c];
+    if (kk == 0) return;   // such a cell owns no pairs and has no rows (uniform exit)
+    // lanes per group and registers per lane fitted to the rank
+    if (kk <= 8) sym_cell<KIND, MODE, 2, 4>(A, sh, c, pp, kk);
+    else if (kk <= 16) sym_cell<KIND, MODE, 4, 4>(A, sh, c, pp, kk);
+    else if (kk <= 24) sym_cell<KIND, MODE, 8, 3>(A, sh, c, pp, kk);
+    else if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
+    else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
+    else if (kk <= 48) sym_cell<KIND, MODE, 8, 6>(A, sh, c, pp, kk);
+    else if (kk <= 56) sym_cell<KIND, MODE, 8, 7>(A, sh, c, pp, kk);
+    else if (kk <= 64) sym_cell<KIND, MODE, 8, 8>(A, sh, c, pp, kk);
+    else if (kk <= 80) sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
+    else if (kk <= 96) sym_cell<KIND, MODE, 16, 6>(A, sh, c, pp, kk);
+    else if (kk <= 112) sym_cell<KIND, MODE, 16, 7>(A, sh, c, pp, kk);
+    else if (kk <= 128) sym_cell<KIND, MODE, 16, 8>(A, sh, c, pp, kk);
+    else if (kk <= 160) sym_cell<KIND, MODE, 32, 5>(A, sh, c, pp, kk);
+    else if (kk <= 192) sym_cell<KIND, MODE, 32, 6>(A, sh, c, pp, kk);
+    else if (kk <= 224) sym_cell<KIND, MODE, 32, 7>(A, sh, c, pp, kk);
+    else sym_cell<KIND, MODE, 32, 8>(A, sh, c, pp, kk);
+}
+
+// u^{B,i} += the column sums of the pairs owned by B's partners, in list order
+template <typename C>
+__global__ void k_m2l_gather(int64_t npiv, const int32_t *piv_cell, const int32_t *piv_ptr, const int32_t *non_ptr,
+                             const int32_t *non_slot, const C *colbuf, double *u)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= npiv) return;
+    const int32_t c = piv_cell[g], j = (int32_t)g - piv_ptr[c];
+    double sum = u[g];
+    for (int32_t e = non_ptr[c]; e < non_ptr[c + 1]; e++) sum += (double)colbuf[non_slot[e] + j];
+    u[g] = sum;
+}
+
 // Sources per LDS tile: long inner loops also for cells with few targets.
 constexpr int M2L_TILE = 4 * NT;
 
@@ -633,28 +935,13 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
     }
 }
 
-template <typename T>
-void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *far, double *y, T prm,
-                hipStream_t s)
-{
-    const nnca::Level &L = H->lev[H->kappa];
-    int64_t nc = L.ncell;
-#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(nc, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
-    if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
-    else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
-    else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
-    else P2P_CASE(NNCA_K_GAUSS);
-#undef P2P_CASE
-    HIPCHECK(hipGetLastError());
-}
-
 // event pair around one launch when the handle is profiling
 struct Span {
     nnca_h2 *H;
     hipStream_t s;
     bool on;
     nnca_h2::ProfRec r;
-    Span(nnca_h2 *H_, hipStream_t s_, int pass, int level) : H(H_), s(s_), on(H_->profiling)
+    Span(nnca_h2 *H_, hipStream_t s_, int pass, int level) : H(H_), s(s_), on(((H_->prof_mask >> pass) & 1) != 0)
     {
         if (!on) return;
         r.pass = pass;
@@ -670,6 +957,76 @@ struct Span {
         H->prof.push_back(r);
     }
 };
+
+// split factor of the symmetric pass: as for the plain pass, on the owned sources
+static int sym_parts(const nnca::Level &L)
+{
+    const int64_t want = 4096;
+    if (L.ncell >= want) return 1;
+    int64_t P = (want + L.ncell - 1) / L.ncell;
+    int64_t maxp = (L.max_own + 1023) / 1024;
+    if (P > maxp) P = maxp;
+    if (P > 64) P = 64;
+    return P < 1 ? 1 : (int)P;
+}
+
+template <int MODE>
+static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level, double prm, hipStream_t s)
+{
+    const int64_t nc = L.ncell;
+    const int P = sym_parts(L);
+    double *part = nullptr;
+    if (P > 1) {
+        if (H->m2l_part_cap < (int64_t)P * L.npiv) {
+            dfree(H->m2l_part);
+            H->m2l_part = nullptr;
+            H->m2l_part = dalloc<double>((int64_t)P * L.npiv);
+            H->m2l_part_cap = (int64_t)P * L.npiv;
+        }
+        part = H->m2l_part;
+    }
+    SymArgs A{L.k, L.piv_ptr, L.own_ptr, L.own_il, L.own_pre, L.own_sum, L.own_slot, L.pc32, L.pc64, L.npiv, nc,
+              L.coord, L.hcell, (float)L.h, H->dim, P, L.w64, L.u64, part, L.col32, L.col64, prm};
+    const int g = (int)(nc * P);
+    {
+        Span sp(H, s, PASS_M2L, level);
+#define SYM_CASE(K) k_m2l_sym<K, MODE><<<g, NT, 0, s>>>(A)
+        if (kind == NNCA_K_INV_R) SYM_CASE(NNCA_K_INV_R);
+        else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
+        else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
+        else SYM_CASE(NNCA_K_GAUSS);
+#undef SYM_CASE
+        HIPCHECK(hipGetLastError());
+    }
+    Span sp(H, s, PASS_M2L_COMBINE, level);
+    if (P > 1) {
+        k_sum_parts<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, P, part, L.u64);
+        HIPCHECK(hipGetLastError());
+    }
+    if (MODE == M_F32)
+        k_m2l_gather<float><<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, L.piv_cell, L.piv_ptr, L.non_ptr,
+                                                                  L.non_slot, L.col32, L.u64);
+    else
+        k_m2l_gather<double><<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, L.piv_cell, L.piv_ptr, L.non_ptr,
+                                                                   L.non_slot, L.col64, L.u64);
+    HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *far, double *y, T prm,
+                hipStream_t s)
+{
+    const nnca::Level &L = H->lev[H->kappa];
+    int64_t nc = L.ncell;
+#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(nc, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
+    if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
+    else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
+    else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
+    else P2P_CASE(NNCA_K_GAUSS);
+#undef P2P_CASE
+    HIPCHECK(hipGetLastError());
+}
+
 
 // One right-hand side.  xs64: x in tree order (FP64).  Mixed: x_hi, x_lo.
 // The transfer passes run in FP64 for both precisions; the M2L and near-field
@@ -698,9 +1055,13 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             if (L.nrem == 0)
                 k_up<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, L.piv_cell, L.piv_ptr, L.tt_off, L.ipos,
                                                            L.rem_ptr, L.rem_pos, L.crem_off, L.crem64, src, L.w64);
-            else
-                k_up_cell<<<(int)L.ncell, 256, 0, s>>>(L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off,
-                                                       L.crem64, src, L.w64);
+            else {
+                // few cells: 32 columns per workgroup; else a whole cell each
+                const int32_t colw = L.ncell < 2048 ? 32 : INT32_MAX;
+                const unsigned gy = L.ncell < 2048 ? (unsigned)((L.max_k + 31) / 32) : 1u;
+                k_up_cell<<<dim3((unsigned)L.ncell, gy > 0 ? gy : 1u), 256, 0, s>>>(
+                    L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off, L.crem64, src, L.w64, colw);
+            }
             HIPCHECK(hipGetLastError());
         }
         // transverse pass; the mixed matvec keeps the coarse levels
@@ -708,6 +1069,12 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
         const double prm64 = 1.0 / (H->hparam * H->hparam);
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
+            const bool sym = L.sym && !(H->apply_flags & NNCA_APPLY_NO_SYMMETRIC);
+            if (f32 && sym) {   // the launcher times its kernel and its combine step apart
+                if (l <= kap - 2) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s);
+                else launch_m2l_sym<M_F32>(kind, H, L, l, (double)prm, s);
+                continue;
+            }
             Span sp(H, s, PASS_M2L, l);
             if (!f32) launch_m2l_mode<M_F64>(kind, H, L, L.pc64, prm64, s);
             else if (l <= kap - 2) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s);
@@ -749,6 +1116,74 @@ void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p,
 {
     if (precision == NNCA_PREC_MIXED) one_column<float>(H, H->xs64, H->xhi, H->xlo, y, s, kind, do_up, do_p2p);
     else one_column<double>(H, H->xs64, nullptr, nullptr, y, s, kind, do_up, do_p2p);
+}
+
+// Ownership of the interacting pairs of a level for the symmetric transverse
+// pass: the pair {B, B'} belongs to the smaller index when B + B' is even and
+// to the larger one otherwise (about half of every list each); pairs with an
+// empty cell carry nothing and are left out.  Levels whose ranks exceed
+// SYM_MAXK or whose slot count exceeds 32-bit offsets keep the plain pass.
+// fp64_slots: FP64 column slots (levels the mixed matvec runs in the
+// FP64-refined form), else FP32.
+void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots)
+{
+    if (L.sym || L.ncell < 1 || L.max_k > SYM_MAXK) return;
+    const int64_t nc = L.ncell;
+    std::vector<int32_t> ilp(nc + 1), il(L.nil > 0 ? L.nil : 1);
+    HIPCHECK(hipMemcpy(ilp.data(), L.il_ptr, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToHost));
+    if (L.nil) HIPCHECK(hipMemcpy(il.data(), L.il, sizeof(int32_t) * L.nil, hipMemcpyDeviceToHost));
+    const std::vector<int32_t> &kh = L.h_k;
+    if ((int64_t)kh.size() != nc) fail(NNCA_ERR_INTERNAL, "host ranks missing for the symmetric pass");
+    auto owned = [](int64_t a, int64_t b) { return ((a + b) & 1) ? a > b : a < b; };
+    std::vector<int32_t> optr(nc + 1, 0), oil, opre, osum(nc, 0), oslot, nptr(nc + 1, 0), nslot;
+    std::vector<int64_t> slot_of(L.nil > 0 ? L.nil : 1, -1);
+    int64_t col = 0;
+    int32_t max_own = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        int64_t pre = 0;
+        for (int32_t e = ilp[c]; e < ilp[c + 1]; e++) {
+            const int32_t b = il[e];
+            if (kh[c] == 0 || kh[b] == 0 || !owned(c, b)) continue;
+            oil.push_back(b);
+            opre.push_back((int32_t)pre);
+            oslot.push_back((int32_t)std::max<int64_t>(INT32_MIN, std::min<int64_t>(INT32_MAX, col - pre)));
+            slot_of[e] = col;
+            pre += kh[b];
+            col += kh[b];
+        }
+        osum[c] = (int32_t)pre;
+        max_own = std::max<int32_t>(max_own, (int32_t)pre);
+        optr[c + 1] = (int32_t)oil.size();
+    }
+    if (col >= INT32_MAX) return;
+    for (int64_t c = 0; c < nc; c++) {
+        for (int32_t e = ilp[c]; e < ilp[c + 1]; e++) {
+            const int32_t b = il[e];
+            if (kh[c] == 0 || kh[b] == 0 || owned(c, b)) continue;
+            auto beg = il.begin() + ilp[b], end = il.begin() + ilp[b + 1];
+            auto it = std::lower_bound(beg, end, (int32_t)c);
+            if (it == end || *it != c) fail(NNCA_ERR_INTERNAL, "interaction lists are not symmetric");
+            nslot.push_back((int32_t)slot_of[it - il.begin()]);
+        }
+        nptr[c + 1] = (int32_t)nslot.size();
+    }
+    auto up = [&](const std::vector<int32_t> &v) {
+        int32_t *d = dalloc<int32_t>(v.size());
+        if (!v.empty()) HIPCHECK(hipMemcpy(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
+        return d;
+    };
+    L.own_ptr = up(optr);
+    L.own_il = up(oil);
+    L.own_pre = up(opre);
+    L.own_sum = up(osum);
+    L.own_slot = up(oslot);
+    L.non_ptr = up(nptr);
+    L.non_slot = up(nslot);
+    if (fp64_slots) L.col64 = dalloc<double>(col);
+    else L.col32 = dalloc<float>(col);
+    L.ncol = col;
+    L.max_own = max_own;
+    L.sym = true;
 }
 
 void prepare_apply(nnca_h2 *H)
@@ -807,6 +1242,9 @@ void prepare_apply(nnca_h2 *H)
         p2p += (int64_t)hc[c] * nbs[c];
         H->max_leaf = std::max(H->max_leaf, hc[c]);
     }
+    // the mixed matvec runs the two finest levels in the FP32 form, the
+    // coarser ones in the FP64-refined form
+    for (int l = H->lmin; l <= H->kappa; l++) prepare_symmetric(H, H->lev[l], l <= H->kappa - 2);
     H->m2l_inter = m2l;
     H->p2p_inter = p2p;
     H->transfer_entries = trans;

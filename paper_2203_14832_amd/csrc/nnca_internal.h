@@ -85,6 +85,19 @@ struct Level {
     int64_t m2l_inter = 0;           // sum over IL pairs of k_B k_B' at this level
     float *hcell = nullptr;          // per-cell side, set when a level holds cells of several problems
 
+    // symmetric transverse pass (mixed form): each unordered pair of
+    // interacting cells is evaluated once, by its owner; the owner's row sums
+    // go to its local vector, its column sums to a slot of colbuf that the
+    // partner adds afterwards
+    bool sym = false;
+    int32_t *own_ptr = nullptr, *own_il = nullptr, *own_pre = nullptr, *own_sum = nullptr;
+    int32_t *own_slot = nullptr;     // per owned entry: colbuf offset of its first source minus own_pre
+    int32_t *non_ptr = nullptr, *non_slot = nullptr;   // per cell: slots of the pairs it does not own
+    float *col32 = nullptr;          // column slots, FP32 (FP32 form) or
+    double *col64 = nullptr;         //   FP64 (FP64-refined form)
+    int64_t ncol = 0;
+    int32_t max_own = 0;
+
     // apply state (one right-hand side at a time): multipole / local vectors
     double *w64 = nullptr, *u64 = nullptr;
 };
@@ -101,6 +114,7 @@ struct nnca_h2 {
     int32_t policy = 1;
     int64_t ws_budget = 0;
     int32_t rank_reserve = 256;
+    int32_t apply_flags = 0;      // NNCA_APPLY_* bits
     int32_t kmax = 20, kappa = 0, lmin = 1;
     double lo[3] = {0, 0, 0}, L = 0.0;
     hipStream_t stream = nullptr;
@@ -155,7 +169,7 @@ struct nnca_h2 {
         int32_t pass, level;
         hipEvent_t a, b;
     };
-    bool profiling = false;
+    int32_t prof_mask = 0;        // bit p: record launches of pass p
     std::vector<ProfRec> prof;
 };
 
@@ -175,6 +189,7 @@ void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int6
                       int precision, hipStream_t s);
 void free_multi(nnca_h2 *H);
 void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s);
+void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots);
 void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, double *y, hipStream_t s);
 // grad.hip
 void run_backward(nnca_h2 *H, const double *X, const double *G, int64_t nrhs, int64_t ldx, int64_t ldg,
@@ -190,7 +205,7 @@ void run_batch(nnca_batch *B, const double *X, double *Y, int64_t nrhs, int64_t 
 int64_t batch_rows(const nnca_batch *B);
 int32_t batch_count(const nnca_batch *B);
 const int64_t *batch_offsets(const nnca_batch *B);
-enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4 };
+enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4, PASS_M2L_COMBINE = 5 };
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
                 const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);
 

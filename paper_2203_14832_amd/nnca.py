@@ -80,6 +80,7 @@ def lib():
             "nnca_destroy": [P],
             "nnca_profile_enable": [P, i32],
             "nnca_profile_read": [P, P, P, P, P, i64],
+            "nnca_set_apply_flags": [P, i32],
             "nnca_batch_create": [P, i32, i32, P],
             "nnca_batch_query": [P, P, P, P],
             "nnca_batch_matvec": [P, P, P, i64, i64, i64, i32, P],
@@ -171,6 +172,10 @@ class H2Matrix:
         """Y = A~^T X."""
         return self._apply(X, precision, True)
 
+    def set_symmetric(self, enable: bool = True):
+        """Use (default) or not the symmetric FP32 transverse pass of the mixed form."""
+        _check(lib().nnca_set_apply_flags(self._h, 0 if enable else 1))
+
     def backward(self, X, G, precision: str = "fp64", need_x: bool = True, need_h: bool = True):
         """Backward of Y = A~ X with G = dL/dY: (A~^T G or None, dL/dh or
         None); dL/dh (Gaussian kernel, pivots frozen) is a 0-dim FP64 device
@@ -209,9 +214,13 @@ class H2Matrix:
         _check(lib().nnca_matvec(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs, self.n,
                                  self.n, PRECISION[precision], _stream(self.torch)))
 
-    def profile(self, enable: bool = True):
-        """Start (and clear) or stop per-launch event timing of matvec passes."""
-        _check(lib().nnca_profile_enable(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, passes=None):
+        """Start (and clear) or stop per-launch event timing of matvec passes
+        (``passes``: iterable of pass numbers, default all)."""
+        mask = 0
+        if enable:
+            mask = -1 if passes is None else sum(1 << int(p) for p in passes)
+        _check(lib().nnca_profile_enable(self._h, mask))
 
     def profile_read(self, cap: int = 1 << 16):
         """Records (pass, level, ms) since profile(True); clears them."""

@@ -127,6 +127,16 @@ def test_matvec_parity(built, name):
     print(name, "mixed vs fp64:", [rel(Ym[:, c], Y64[:, c]) for c in range(3)])
     for c in range(3):
         assert rel(Ym[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c, rel(Ym[:, c], Y64[:, c]))
+    # the plain (every ordered pair) FP32 transverse pass gives the same
+    # product to the same bound; the symmetric one is the default
+    G.set_symmetric(False)
+    try:
+        Yp = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
+    finally:
+        G.set_symmetric(True)
+    for c in range(3):
+        assert rel(Yp[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c)
+        assert rel(Yp[:, c], Ym[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c)
     # adjoint: <A x, y> = <x, A^T y>
     Ya = G.rmatvec(Xt, "fp64").cpu().numpy()
     lhs, rhs = X[:, 0] @ Ya[:, 1], Y64[:, 0] @ X[:, 1]
