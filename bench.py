@@ -37,6 +37,11 @@ METRIC = "H2 matvecs/s at N=1M 3D 1/r, mixed vs FP64 at rel.err≤1e-6; % roofli
 VALU_LANE_SLOTS = 256 * 128 * 2.4e9
 SLOTS_PER_PAIR = 12.0
 PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
+# HBM bytes per launch of that kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs of `bench.py --probe` (profiles/h2_matvec_c2_hbm_bytes.md), scaled by
+# the counters' reading of a 256 MiB copy: fetch + write MiB at kappa and
+# kappa-1.  Valid for this version of k_m2l_sym; None once the kernel changes.
+M2L_SYM_HBM_MIB = ((277.8, 339.2), (94.5, 116.8))
 
 
 def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3):
@@ -70,6 +75,9 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter runs: one 256 MiB device copy (calibration of byte counters) and --steps "
+                         "mixed matvecs of the workload, no timing")
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
                          "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
@@ -83,6 +91,8 @@ def main():
     from paper_2203_14832_amd import nnca
     from paper_2203_14832_amd.workloads import workload
 
+    if args.probe:
+        return probe(args)
     if args.config == "c3":
         return bench_many_rhs(args)
     if args.config == "c4":
@@ -171,7 +181,10 @@ def main():
                                f"mixed FP32 apply with FP64 pivots/operators and FP64 near-field refinement",
                    "n": n, "kappa": info["kappa"], "leaf_size": 64, "tol": 1e-6, "nrhs": 1},
         "roofline": {"bound": "alu", "achieved": pair_rate / 1e9, "peak": PEAK_PAIRS / 1e9,
-                     "unit": "G pairs/s", "frac": pair_rate / PEAK_PAIRS, "traffic": None,
+                     "unit": "G pairs/s", "frac": pair_rate / PEAK_PAIRS,
+                     "traffic": (sum(f + w for f, w in M2L_SYM_HBM_MIB) / len(M2L_SYM_HBM_MIB) * 2 ** 20
+                                 if M2L_SYM_HBM_MIB else None),
+                     "traffic_unit": "bytes per launch (HBM, counters)",
                      "kernel": "k_m2l_sym<1/r, FP32> (levels kappa-1, kappa)",
                      "launches_per_step": launches_per_step,
                      "avg_launch_ms": float(m2l_ms.mean()) if m2l_ms.size else None,
@@ -192,6 +205,29 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inter)
     print(json.dumps(out), flush=True)
+
+
+def probe(args):
+    """For hardware-counter runs (rocprofv3 --pmc): a plain device-to-device
+    copy of 256 MiB (known bytes read and written, to scale the byte
+    counters) and `steps` mixed matvecs of the default workload."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import workload
+    dev = torch.device("cuda:0")
+    a = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    p, x = workload("c2", n=args.n)
+    n = p.shape[0]
+    H = nnca.H2Matrix(p, "inv_r", 1e-6, 64, device=dev)
+    X = torch.tensor(x[:, 0], device=dev).reshape(1, n).contiguous()
+    Y = torch.empty_like(X)
+    for _ in range(args.steps):
+        H.matvec_raw(X, Y, 1, "mixed")
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy 268435456 bytes + mixed matvecs", "n": n, "steps": args.steps}), flush=True)
 
 
 def bench_many_rhs(args):

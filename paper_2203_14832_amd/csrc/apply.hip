@@ -885,7 +885,17 @@ __global__ void k_m2l_gather(int64_t npiv, const int32_t *piv_cell, const int32_
     if (g >= npiv) return;
     const int32_t c = piv_cell[g], j = (int32_t)g - piv_ptr[c];
     double sum = u[g];
-    for (int32_t e = non_ptr[c]; e < non_ptr[c + 1]; e++) sum += (double)colbuf[non_slot[e] + j];
+    int32_t e = non_ptr[c];
+    const int32_t e1 = non_ptr[c + 1];
+    // eight independent loads in flight, added in list order
+    for (; e + 8 <= e1; e += 8) {
+        C v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = colbuf[non_slot[e + q] + j];
+#pragma unroll
+        for (int q = 0; q < 8; q++) sum += (double)v[q];
+    }
+    for (; e < e1; e++) sum += (double)colbuf[non_slot[e] + j];
     u[g] = sum;
 }
 
