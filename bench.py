@@ -151,6 +151,18 @@ def main():
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t0) / args.steps * 1e3
 
+    # the mixed form with the plain (every ordered pair) transverse pass, to
+    # separate the gain of FP32 arithmetic from that of the symmetric pass
+    H.set_symmetric(False)
+    run("mixed", Ym, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run("mixed", Ym, args.steps)
+    torch.cuda.synchronize()
+    ms_nosym = (time.perf_counter() - t0) / args.steps * 1e3
+    H.set_symmetric(True)
+    run("mixed", Ym, 1)
+
     # per-pass breakdown from separate (untimed) steps with every launch bracketed
     H.profile(True)
     run("mixed", Ym, 5)
@@ -196,6 +208,7 @@ def main():
         "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,
         "interactions_per_step": inter, "ms_per_step_without_events": ms_plain,
+        "mixed_plain_pass_ms_per_step": ms_nosym, "speedup_vs_fp64_plain_pass": fp64_ms / ms_nosym,
     }
     if not args.no_direct:
         yd = nnca.direct(p, X.reshape(n), "inv_r", device=dev)
