@@ -67,6 +67,12 @@ void nnca::destroy_handle(nnca_h2 *H)
     clear_profile(H);
     free_multi(H);
     free_grad(H);
+    if (H->aux) {
+        (void)hipStreamSynchronize(H->aux);
+        (void)hipStreamDestroy(H->aux);
+    }
+    if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+    if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     for (auto &L : H->lev) {
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,

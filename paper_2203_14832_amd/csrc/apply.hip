@@ -134,15 +134,18 @@ __global__ __launch_bounds__(256) void k_up_cell(const int32_t *piv_ptr, const i
 // written as the far field of the leaf's points (L2P).  crem_t holds every
 // cell's block transposed (k x (m-k)) so that neighbouring rows read
 // neighbouring addresses.
+// With `order` (leaf level), the rows are points and go to out[order[row]],
+// the result in the original point order.
 __global__ void k_down(int64_t npiv, int64_t nrem, const int32_t *piv_cell, const int32_t *rem_cell,
                        const int32_t *piv_ptr, const int32_t *tt_off, const int32_t *ipos, const int32_t *rem_ptr,
                        const int32_t *rem_pos, const int64_t *crem_off, const double *crem_t, const double *u,
-                       double *out, int accumulate)
+                       double *out, int accumulate, const int32_t *order)
 {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g < npiv) {
         int32_t c = piv_cell[g];
         int32_t dst = tt_off[c] + ipos[g];
+        if (order) dst = order[dst];
         out[dst] = accumulate ? out[dst] + u[g] : u[g];
         return;
     }
@@ -164,6 +167,7 @@ __global__ void k_down(int64_t npiv, int64_t nrem, const int32_t *piv_cell, cons
     for (; q < kk; q++) acc += Ct[(int64_t)q * nr] * ub[q];
     acc += (a1 + a2) + a3;
     int32_t dst = tt_off[c] + rem_pos[g];
+    if (order) dst = order[dst];
     out[dst] = accumulate ? out[dst] + acc : acc;
 }
 
@@ -1056,6 +1060,21 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
                                : (T)(1.0 / (H->hparam * H->hparam)))
                         : T(0);
     double *far = nullptr;
+    // With a far field, the near field runs on the handle's second stream
+    // while the far-field passes run here (it reads only x and the points);
+    // it writes the near-field sums to y, and the leaf-level L2P adds the far
+    // field to y after the join.
+    const bool overlap = do_p2p && kap >= lmin;
+    if (overlap) {
+        HIPCHECK(hipEventRecord(H->ev_fork, s));
+        HIPCHECK(hipStreamWaitEvent(H->aux, H->ev_fork, 0));
+        {
+            Span sp(H, H->aux, PASS_P2P, kap);
+            if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, y, prm, H->aux);
+            else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, y, prm, H->aux);
+        }
+        HIPCHECK(hipEventRecord(H->ev_join, H->aux));
+    }
     if (kap >= lmin) {
         // upward pass
         for (int l = kap; l >= lmin && do_up; l--) {
@@ -1090,23 +1109,26 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             else if (l <= kap - 2) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s);
             else launch_m2l_mode<M_F32>(kind, H, L, L.pc32, (double)prm, s);
         }
-        // downward pass
+        // downward pass; with the near field overlapped, the leaf level adds
+        // the far field to y (original order) after the join
         far = H->far64;
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
-            double *out = (l == kap) ? far : H->lev[l + 1].u64;
+            const bool leaf = l == kap;
+            double *out = leaf ? (overlap ? y : far) : H->lev[l + 1].u64;
+            if (leaf && overlap) HIPCHECK(hipStreamWaitEvent(s, H->ev_join, 0));
             Span sp(H, s, PASS_DOWN, l);
-            k_down<<<grid_for(L.npiv + L.nrem, 256), 256, 0, s>>>(L.npiv, L.nrem, L.piv_cell, L.rem_cell, L.piv_ptr,
-                                                                  L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off,
-                                                                  L.crem_t, L.u64, out, l == kap ? 0 : 1);
+            k_down<<<grid_for(L.npiv + L.nrem, 256), 256, 0, s>>>(
+                L.npiv, L.nrem, L.piv_cell, L.rem_cell, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
+                L.crem_off, L.crem_t, L.u64, out, leaf ? (overlap ? 1 : 0) : 1, leaf && overlap ? H->order : nullptr);
             HIPCHECK(hipGetLastError());
         }
     }
-    if (!do_p2p) return;
-    // near field and combine
+    if (!do_p2p || overlap) return;
+    // near field alone (no far field)
     Span sp(H, s, PASS_P2P, kap);
-    if (f32) launch_p2p<T>(kind, H, xhi, xlo, far, y, prm, s);
-    else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, far, y, prm, s);
+    if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, y, prm, s);
+    else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, y, prm, s);
 }
 
 }  // namespace
@@ -1258,6 +1280,9 @@ void prepare_apply(nnca_h2 *H)
     H->m2l_inter = m2l;
     H->p2p_inter = p2p;
     H->transfer_entries = trans;
+    HIPCHECK(hipStreamCreateWithFlags(&H->aux, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
     H->xs64 = dalloc<double>(H->n);
     H->far64 = dalloc<double>(H->n);
     H->xhi = dalloc<float>(H->n);

@@ -275,6 +275,9 @@ nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags)
         for (int32_t b = 0; b < count; b++) M->p2p_inter += hs[b]->p2p_inter;
         HIPCHECK(hipStreamSynchronize(s));
         for (int l = 0; l <= M->kappa; l++) prepare_symmetric(M, M->lev[l], l <= M->kappa - 2);
+        HIPCHECK(hipStreamCreateWithFlags(&M->aux, hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
         M->xs64 = dalloc<double>(N);
         M->far64 = dalloc<double>(N);
         M->xhi = dalloc<float>(N);

@@ -118,6 +118,8 @@ struct nnca_h2 {
     int32_t kmax = 20, kappa = 0, lmin = 1;
     double lo[3] = {0, 0, 0}, L = 0.0;
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;               // second stream of the matvec (near field)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double build_seconds = 0.0;
 
     double *pts64 = nullptr;      // 3 x n, tree order
