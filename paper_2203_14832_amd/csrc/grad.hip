@@ -71,39 +71,24 @@ __global__ __launch_bounds__(NT) void k_lu(const int32_t *piv_ptr, const int32_t
     }
 }
 
-// Transfer-operator term of one level, one workgroup per cell:
-//   out[c] = a(x)^T D(t~, J) z(g) + a(g)^T D(t~, J) z(x).
-// Rows 0..m-1 are t~ (coordinates tpc with leading dimension tld, weights
-// the upward inputs inx / ing), rows m..m+k-1 the pivots I (coordinates ipc,
-// weights minus the multipole vectors wx / wg).
-__global__ __launch_bounds__(NT) void k_tgrad(const int32_t *piv_ptr, const int32_t *jid, const int32_t *mm,
-                                              const int32_t *tt_off, const int64_t *lu_off, const double *lu,
-                                              const double *ux, const double *ug, const double *wx,
-                                              const double *wg, const double *inx, const double *ing,
-                                              const double *tpc, int64_t tld, const double *ipc, int64_t npiv,
-                                              const double *pts, int64_t n, int d, double prm, double *out)
+// z = K(I, J)^{-1} u for the local vectors of x and of the cotangent, one
+// workgroup per ACA cell of a level (z of other cells is not used).
+__global__ __launch_bounds__(NT) void k_tsolve(const int32_t *piv_ptr, const int32_t *jid, const int64_t *lu_off,
+                                               const double *lu, const double *ux, const double *ug, double *zx,
+                                               double *zg)
 {
-    __shared__ double bg[KMAX], bx[KMAX], zg[KMAX], zx[KMAX];
-    __shared__ double jx[KMAX], jy[KMAX], jz[KMAX];
-    __shared__ double red[NT];
+    __shared__ double bg[KMAX], bx[KMAX];
     const int t = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int32_t po = piv_ptr[c], k = piv_ptr[c + 1] - po;
-    if (k == 0 || jid[po] < 0) {
-        if (t == 0) out[c] = 0.0;
-        return;
-    }
+    if (k == 0 || jid[po] < 0) return;   // uniform for the workgroup
     const double *A = lu + lu_off[c];
     for (int32_t i = t; i < k; i += NT) {
         bg[i] = ug[po + i];
         bx[i] = ux[po + i];
-        const int32_t j = jid[po + i];
-        jx[i] = pts[j];
-        jy[i] = pts[n + j];
-        jz[i] = d == 3 ? pts[2 * n + j] : 0.0;
     }
-    // z = U^{-1} L^{-1} u for both vectors: step p only changes entries
-    // other than p, so one barrier per step suffices
+    // forward substitution with the unit lower factor; step p only changes
+    // entries other than p, so one barrier per step suffices
     for (int32_t p = 0; p < k; p++) {
         __syncthreads();
         const double vg = bg[p], vx = bx[p];
@@ -113,13 +98,14 @@ __global__ __launch_bounds__(NT) void k_tgrad(const int32_t *piv_ptr, const int3
             bx[i] -= l * vx;
         }
     }
+    // back substitution with the upper factor
     for (int32_t p = k - 1; p >= 0; p--) {
         __syncthreads();
         const double upp = A[p + (int64_t)p * k];
         const double vg = bg[p] / upp, vx = bx[p] / upp;
         if (t == 0) {
-            zg[p] = vg;
-            zx[p] = vx;
+            zg[po + p] = vg;
+            zx[po + p] = vx;
         }
         for (int32_t i = t; i < p; i += NT) {
             const double uu = A[i + (int64_t)p * k];
@@ -127,10 +113,42 @@ __global__ __launch_bounds__(NT) void k_tgrad(const int32_t *piv_ptr, const int3
             bx[i] -= uu * vx;
         }
     }
+}
+
+// Transfer-operator term of one row block of an ACA cell:
+//   out[item] = sum over the block's rows r of
+//               al_r * (D(r, J) z(g)) + be_r * (D(r, J) z(x)).
+// Rows 0..m-1 are t~ (coordinates tpc with leading dimension tld, weights
+// the upward inputs inx / ing), rows m..m+k-1 the pivots I (coordinates ipc,
+// weights minus the multipole vectors wx / wg).  Item = (cell, first row);
+// a block has at most NT rows.
+__global__ __launch_bounds__(NT) void k_tgrad(const int32_t *items, const int32_t *piv_ptr, const int32_t *jid,
+                                              const int32_t *mm, const int32_t *tt_off, const double *zx,
+                                              const double *zg, const double *wx, const double *wg,
+                                              const double *inx, const double *ing, const double *tpc, int64_t tld,
+                                              const double *ipc, int64_t npiv, const double *pts, int64_t n, int d,
+                                              double prm, double *out)
+{
+    __shared__ double szg[KMAX], szx[KMAX];
+    __shared__ double jx[KMAX], jy[KMAX], jz[KMAX];
+    __shared__ double red[NT];
+    const int t = threadIdx.x;
+    const int64_t it = blockIdx.x;
+    const int32_t c = items[2 * it], r0 = items[2 * it + 1];
+    const int32_t po = piv_ptr[c], k = piv_ptr[c + 1] - po;
+    for (int32_t i = t; i < k; i += NT) {
+        szg[i] = zg[po + i];
+        szx[i] = zx[po + i];
+        const int32_t j = jid[po + i];
+        jx[i] = pts[j];
+        jy[i] = pts[n + j];
+        jz[i] = d == 3 ? pts[2 * n + j] : 0.0;
+    }
     __syncthreads();
     const int32_t m = mm[c], to = tt_off[c];
     double acc = 0.0;
-    for (int32_t r = t; r < m + k; r += NT) {
+    const int32_t r = r0 + t;
+    if (r < m + k) {
         double px, py, pz, al, be;
         if (r < m) {
             const int64_t q = to + r;
@@ -151,10 +169,10 @@ __global__ __launch_bounds__(NT) void k_tgrad(const int32_t *piv_ptr, const int3
         for (int32_t j = 0; j < k; j++) {
             const double dx = px - jx[j], dy = py - jy[j], dz = pz - jz[j];
             const double v = kv64<K_GAUSS_DH>(dx * dx + dy * dy + dz * dz, prm);
-            sg += v * zg[j];
-            sx += v * zx[j];
+            sg += v * szg[j];
+            sx += v * szx[j];
         }
-        acc += al * sg + be * sx;
+        acc = al * sg + be * sx;
     }
     red[t] = acc;
     __syncthreads();
@@ -162,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_tgrad(const int32_t *piv_ptr, const int3
         if (t < s) red[t] += red[t + s];
         __syncthreads();
     }
-    if (t == 0) out[c] = red[0];
+    if (t == 0) out[it] = red[0];
 }
 
 // partial dot products a . b, one per workgroup (fixed shape)
@@ -210,15 +228,11 @@ void prepare_grad(nnca_h2 *H)
     G.lu.assign(nl, nullptr);
     G.gw.assign(nl, nullptr);
     G.gu.assign(nl, nullptr);
+    G.zx.assign(nl, nullptr);
+    G.zg.assign(nl, nullptr);
+    G.items.assign(nl, nullptr);
+    G.nitems.assign(nl, 0);
     G.term_off.assign(nl + 1, 0);
-    int64_t nterm = 0;
-    for (int l = lmin; l <= kap; l++) {
-        G.term_off[l] = nterm;
-        nterm += H->lev[l].ncell;
-    }
-    G.term_off[nl] = nterm;
-    G.nterms = nterm + DOT_PARTS;
-    G.terms = dalloc<double>(G.nterms);
     G.gs = dalloc<double>(H->n);
     G.yd = dalloc<double>(H->n);
     G.flag = dalloc<int32_t>(1);
@@ -240,6 +254,24 @@ void prepare_grad(nnca_h2 *H)
             off[c + 1] = off[c] + (aca ? k * k : 0);
             po += k;
         }
+        // row blocks of NT rows over t~ and the pivots of every ACA cell
+        std::vector<int32_t> items;
+        po = 0;
+        for (int64_t c = 0; c < nc; c++) {
+            const int32_t k = L.h_k[c];
+            if (k > 0 && jid[po] >= 0)
+                for (int32_t r0 = 0; r0 < L.h_m[c] + k; r0 += NT) {
+                    items.push_back((int32_t)c);
+                    items.push_back(r0);
+                }
+            po += k;
+        }
+        G.nitems[l] = (int64_t)items.size() / 2;
+        G.items[l] = dalloc<int32_t>(items.size());
+        if (!items.empty())
+            HIPCHECK(hipMemcpy(G.items[l], items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice));
+        G.zx[l] = dalloc<double>(L.npiv);
+        G.zg[l] = dalloc<double>(L.npiv);
         G.lu_off[l] = dalloc<int64_t>(nc + 1);
         G.lu[l] = dalloc<double>(off[nc]);
         G.gw[l] = dalloc<double>(L.npiv);
@@ -252,6 +284,14 @@ void prepare_grad(nnca_h2 *H)
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(s));   // `off` leaves scope
     }
+    int64_t nterm = 0;
+    for (int l = lmin; l <= kap; l++) {
+        G.term_off[l] = nterm;
+        nterm += G.nitems[l];
+    }
+    G.term_off[nl] = nterm;
+    G.nterms = nterm + DOT_PARTS;
+    G.terms = dalloc<double>(G.nterms);
     int32_t bad = 0;
     HIPCHECK(hipMemcpy(&bad, G.flag, sizeof(int32_t), hipMemcpyDeviceToHost));
     if (bad) fail(NNCA_ERR_NUMERICAL, "zero pivot in K(I, J) of the length-scale derivative");
@@ -267,6 +307,9 @@ void free_grad(nnca_h2 *H)
     for (auto p : G.lu) dfree(p);
     for (auto p : G.gw) dfree(p);
     for (auto p : G.gu) dfree(p);
+    for (auto p : G.zx) dfree(p);
+    for (auto p : G.zg) dfree(p);
+    for (auto p : G.items) dfree(p);
     dfree(G.gs);
     dfree(G.yd);
     dfree(G.terms);
@@ -318,9 +361,13 @@ void run_backward(nnca_h2 *H, const double *X, const double *Gv, int64_t nrhs, i
             const double *ing = leaf ? G.gs : G.gw[l + 1];
             const double *tpc = leaf ? H->pts64 : H->lev[l + 1].pc64;
             const int64_t tld = leaf ? n : H->lev[l + 1].npiv;
-            k_tgrad<<<(int)L.ncell, NT, 0, s>>>(L.piv_ptr, L.jid, L.m, L.tt_off, G.lu_off[l], G.lu[l], L.u64, G.gu[l],
-                                                L.w64, G.gw[l], inx, ing, tpc, tld, L.pc64, L.npiv, H->pts64, n,
-                                                H->dim, prm, G.terms + G.term_off[l]);
+            k_tsolve<<<(int)L.ncell, NT, 0, s>>>(L.piv_ptr, L.jid, G.lu_off[l], G.lu[l], L.u64, G.gu[l], G.zx[l],
+                                                 G.zg[l]);
+            HIPCHECK(hipGetLastError());
+            if (G.nitems[l] > 0)
+                k_tgrad<<<(int)G.nitems[l], NT, 0, s>>>(G.items[l], L.piv_ptr, L.jid, L.m, L.tt_off, G.zx[l], G.zg[l],
+                                                        L.w64, G.gw[l], inx, ing, tpc, tld, L.pc64, L.npiv, H->pts64,
+                                                        n, H->dim, prm, G.terms + G.term_off[l]);
             HIPCHECK(hipGetLastError());
         }
         // 4. the derivative kernel in the M2L and near-field blocks on x

@@ -158,7 +158,10 @@ struct nnca_h2 {
         std::vector<int64_t *> lu_off;   // per level: ncell + 1 offsets into lu
         std::vector<double *> lu;        // per level: L U = K(I, J) of every ACA cell, column-major
         std::vector<double *> gw, gu;    // per level: multipole / local vectors of the cotangent
-        std::vector<int64_t> term_off;   // per level: first per-cell term; the dot parts follow
+        std::vector<double *> zx, zg;    // per level: K(I, J)^{-1} u of x and of the cotangent
+        std::vector<int32_t *> items;    // per level: (cell, first row) of every row block
+        std::vector<int64_t> nitems;
+        std::vector<int64_t> term_off;   // per level: first row-block term; the dot parts follow
         double *gs = nullptr;            // cotangent in tree order
         double *yd = nullptr;            // derivative-kernel product, original order
         double *terms = nullptr;
