@@ -138,6 +138,8 @@ __device__ inline int32_t list_entry(const int32_t *pre, int32_t e0, int32_t e1,
     return lo;
 }
 
+constexpr int MET = 256;   // interaction-list entries staged in LDS at a time
+
 // M2L, FP32 on the matrix cores.  Four wavefronts; each takes one block of 16
 // targets (or, with fewer than four blocks, a phase of the 4-source steps).
 template <int KIND, int NCB>
@@ -148,11 +150,13 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
                                                  const double *w, double *u, double *part_out, float prm)
 {
     constexpr int RP = NCB * 16;
-    constexpr int TS = 128;
+    constexpr int TS = NCB == 1 ? 256 : 128;         // sources per LDS tile
     constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
     __shared__ float4 sx[TS];
     __shared__ int32_t sidx[TS];
     __shared__ double swt_raw[TS * SW / 2 > NT * NCB * 4 ? TS * SW / 2 : NT * NCB * 4];
+    __shared__ int32_t est[MET + 1], ebase[MET];
+    __shared__ float esh[3][MET];
     float *swt = reinterpret_cast<float *>(swt_raw);
     double *red = swt_raw;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -165,6 +169,7 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
     const float h = hc ? hc[c] : h0;   // cell side (per cell when the level mixes problems)
     double *dst = P > 1 ? part_out + (int64_t)pp * npiv * RP : u;
     const int32_t ntb = (kk + 15) / 16;
+    const int32_t efirst = sb < se ? list_entry(ilpre, e0, e1, sb) : e1;
     for (int32_t tb0 = 0; tb0 < ntb; tb0 += 4) {
         const int nb = ntb - tb0 < 4 ? ntb - tb0 : 4;
         const int nph = 4 / nb;
@@ -181,19 +186,39 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
             accf[b] = floatx4{0.f, 0.f, 0.f, 0.f};
             for (int i = 0; i < 4; i++) accd[b][i] = 0.0;
         }
-        for (int32_t s0 = sb; s0 < se; s0 += TS) {
-            const int32_t ns = se - s0 < TS ? se - s0 : TS;
+        // windows of MET list entries staged in LDS: first source, pivot base
+        // and cell offset of every entry
+        for (int32_t w0 = efirst; w0 < e1; w0 += MET) {
+            const int32_t wn = e1 - w0 < MET ? e1 - w0 : MET;
+            __syncthreads();
+            for (int32_t j = t; j < wn; j += NT) {
+                const int32_t e = w0 + j, b = il[e], pre = ilpre[e];
+                est[j] = pre;
+                ebase[j] = piv_ptr[b] - pre;
+                esh[0][j] = (float)(coord[b] - cc0) * h;
+                esh[1][j] = (float)(coord[nc + b] - cc1) * h;
+                esh[2][j] = d == 3 ? (float)(coord[2 * nc + b] - cc2) * h : 0.f;
+            }
+            if (t == 0) est[wn] = w0 + wn < e1 ? ilpre[w0 + wn] : S;
+            __syncthreads();
+            if (est[0] >= se) break;
+            const int32_t ws = est[0] > sb ? est[0] : sb, we = est[wn] < se ? est[wn] : se;
+        for (int32_t s0 = ws; s0 < we; s0 += TS) {
+            const int32_t ns = we - s0 < TS ? we - s0 : TS;
             __syncthreads();
             if (t < ns) {
-                int32_t s = s0 + t;
-                int32_t e = list_entry(ilpre, e0, e1, s);
-                int32_t b = il[e];
-                int32_t idx = piv_ptr[b] + (s - ilpre[e]);
+                const int32_t s = s0 + t;
+                int32_t lo = 0, hi = wn - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (est[mid] <= s) lo = mid; else hi = mid - 1;
+                }
+                const int32_t idx = ebase[lo] + s;
                 sidx[t] = idx;
                 float4 v;
-                v.x = pc[idx] + (float)(coord[b] - cc0) * h;
-                v.y = pc[npiv + idx] + (float)(coord[nc + b] - cc1) * h;
-                v.z = d == 3 ? pc[2 * npiv + idx] + (float)(coord[2 * nc + b] - cc2) * h : 0.f;
+                v.x = pc[idx] + esh[0][lo];
+                v.y = pc[npiv + idx] + esh[1][lo];
+                v.z = d == 3 ? pc[2 * npiv + idx] + esh[2][lo] : 0.f;
                 v.w = 0.f;
                 sx[t] = v;
             }
@@ -226,6 +251,7 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
                     }
                 }
             }
+        }
         }
 #pragma unroll
         for (int b = 0; b < NCB; b++)
