@@ -140,21 +140,32 @@ __device__ inline int32_t list_entry(const int32_t *pre, int32_t e0, int32_t e1,
 
 constexpr int MET = 256;   // interaction-list entries staged in LDS at a time
 
-// M2L, FP32 on the matrix cores.  Four wavefronts; each takes one block of 16
-// targets (or, with fewer than four blocks, a phase of the 4-source steps).
+__global__ void k_to_f32(int64_t cnt, const double *a, float *b)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < cnt) b[i] = (float)a[i];
+}
+
+// M2L, FP32 on the matrix cores.  Four wavefronts; each takes a unit of TB
+// blocks of 16 targets (TB = 2 for up to 32 columns: one source step then
+// feeds two kernel values per lane into two matrix products that share the
+// weight operand), or, with fewer than four units, a phase of the 4-source
+// steps of one unit.
 template <int KIND, int NCB>
 __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                  const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                  const int32_t *ilsum, const float *pc, int64_t npiv,
                                                  const int32_t *coord, const float *hc, float h0, int d,
-                                                 const double *w, double *u, double *part_out, float prm)
+                                                 const float *w32, int R, double *u, double *part_out, float prm)
 {
     constexpr int RP = NCB * 16;
+    constexpr int TB = NCB <= 2 ? 2 : 1;             // target blocks per wavefront
     constexpr int TS = NCB == 1 ? 256 : 128;         // sources per LDS tile
     constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
+    constexpr int RED = NT * NCB * 4 * TB;           // doubles of the phase reduction
     __shared__ float4 sx[TS];
     __shared__ int32_t sidx[TS];
-    __shared__ double swt_raw[TS * SW / 2 > NT * NCB * 4 ? TS * SW / 2 : NT * NCB * 4];
+    __shared__ double swt_raw[TS * SW / 2 > RED ? TS * SW / 2 : RED];
     __shared__ int32_t est[MET + 1], ebase[MET];
     __shared__ float esh[3][MET];
     float *swt = reinterpret_cast<float *>(swt_raw);
@@ -169,23 +180,32 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
     const float h = hc ? hc[c] : h0;   // cell side (per cell when the level mixes problems)
     double *dst = P > 1 ? part_out + (int64_t)pp * npiv * RP : u;
     const int32_t ntb = (kk + 15) / 16;
+    const int32_t nun = (ntb + TB - 1) / TB;
     const int32_t efirst = sb < se ? list_entry(ilpre, e0, e1, sb) : e1;
-    for (int32_t tb0 = 0; tb0 < ntb; tb0 += 4) {
-        const int nb = ntb - tb0 < 4 ? ntb - tb0 : 4;
+    for (int32_t tu0 = 0; tu0 < nun; tu0 += 4) {
+        const int nb = nun - tu0 < 4 ? nun - tu0 : 4;
         const int nph = 4 / nb;
         const int myb = wave % nb, ph = wave / nb;
         const bool wact = ph < nph;
-        const int32_t tb = tb0 + myb;
-        int32_t row = tb * 16 + (lane & 15);
-        int32_t rc = row < kk ? row : kk - 1;
-        const float tx = pc[po + rc], ty = pc[npiv + po + rc], tz = d == 3 ? pc[2 * npiv + po + rc] : 0.f;
-        floatx4 accf[NCB];
-        double accd[NCB][4];
+        const int32_t tu = tu0 + myb;
+        float tx[TB], ty[TB], tz[TB];
 #pragma unroll
-        for (int b = 0; b < NCB; b++) {
-            accf[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-            for (int i = 0; i < 4; i++) accd[b][i] = 0.0;
+        for (int j = 0; j < TB; j++) {
+            const int32_t row = (tu * TB + j) * 16 + (lane & 15);
+            const int32_t rc = row < kk ? row : kk - 1;
+            tx[j] = pc[po + rc];
+            ty[j] = pc[npiv + po + rc];
+            tz[j] = d == 3 ? pc[2 * npiv + po + rc] : 0.f;
         }
+        floatx4 accf[TB][NCB];
+        double accd[TB][NCB][4];
+#pragma unroll
+        for (int j = 0; j < TB; j++)
+#pragma unroll
+            for (int b = 0; b < NCB; b++) {
+                accf[j][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int i = 0; i < 4; i++) accd[j][b][i] = 0.0;
+            }
         // windows of MET list entries staged in LDS: first source, pivot base
         // and cell offset of every entry
         for (int32_t w0 = efirst; w0 < e1; w0 += MET) {
@@ -203,76 +223,92 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
             __syncthreads();
             if (est[0] >= se) break;
             const int32_t ws = est[0] > sb ? est[0] : sb, we = est[wn] < se ? est[wn] : se;
-        for (int32_t s0 = ws; s0 < we; s0 += TS) {
-            const int32_t ns = we - s0 < TS ? we - s0 : TS;
-            __syncthreads();
-            if (t < ns) {
-                const int32_t s = s0 + t;
-                int32_t lo = 0, hi = wn - 1;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi + 1) >> 1;
-                    if (est[mid] <= s) lo = mid; else hi = mid - 1;
+            for (int32_t s0 = ws; s0 < we; s0 += TS) {
+                const int32_t ns = we - s0 < TS ? we - s0 : TS;
+                __syncthreads();
+                if (t < ns) {
+                    const int32_t s = s0 + t;
+                    int32_t lo = 0, hi = wn - 1;
+                    while (lo < hi) {
+                        int32_t mid = (lo + hi + 1) >> 1;
+                        if (est[mid] <= s) lo = mid; else hi = mid - 1;
+                    }
+                    const int32_t idx = ebase[lo] + s;
+                    sidx[t] = idx;
+                    float4 v;
+                    v.x = pc[idx] + esh[0][lo];
+                    v.y = pc[npiv + idx] + esh[1][lo];
+                    v.z = d == 3 ? pc[2 * npiv + idx] + esh[2][lo] : 0.f;
+                    v.w = 0.f;
+                    sx[t] = v;
                 }
-                const int32_t idx = ebase[lo] + s;
-                sidx[t] = idx;
-                float4 v;
-                v.x = pc[idx] + esh[0][lo];
-                v.y = pc[npiv + idx] + esh[1][lo];
-                v.z = d == 3 ? pc[2 * npiv + idx] + esh[2][lo] : 0.f;
-                v.w = 0.f;
-                sx[t] = v;
-            }
-            __syncthreads();
-            for (int32_t e = t; e < ns * RP; e += NT) swt[(e / RP) * SW + e % RP] = (float)w[(int64_t)sidx[e / RP] * RP + e % RP];
-            __syncthreads();
-            if (wact) {
-                int steps = 0;
-                for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
-                    int32_t src = s4 + (lane >> 4);
-                    float kvv = 0.f;
-                    int32_t srcc = src < ns ? src : ns - 1;
-                    if (src < ns) {
-                        float4 q = sx[src];
-                        float dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
-                        kvv = kv32<KIND>(dx * dx + dy * dy + dz * dz, prm);
-                    }
+                __syncthreads();
+                // FP32 weights of the R real columns; the padding columns are zero
+                for (int32_t e = t; e < ns * RP; e += NT) {
+                    const int32_t sr = e / RP, col = e % RP;
+                    swt[sr * SW + col] = col < R ? w32[(int64_t)sidx[sr] * RP + col] : 0.f;
+                }
+                __syncthreads();
+                if (wact) {
+                    int steps = 0;
+                    for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
+                        const int32_t src = s4 + (lane >> 4);
+                        const int32_t srcc = src < ns ? src : ns - 1;
+                        const float4 q = sx[srcc];
+                        float kvv[TB];
 #pragma unroll
-                    for (int b = 0; b < NCB; b++) {
-                        float bw = swt[srcc * SW + b * 16 + (lane & 15)];
-                        accf[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, bw, accf[b], 0, 0, 0);
-                    }
-                    if (++steps == 4) {
-                        steps = 0;
+                        for (int j = 0; j < TB; j++) {
+                            const float dx = tx[j] - q.x, dy = ty[j] - q.y, dz = tz[j] - q.z;
+                            kvv[j] = src < ns ? kv32<KIND>(dx * dx + dy * dy + dz * dz, prm) : 0.f;
+                        }
 #pragma unroll
                         for (int b = 0; b < NCB; b++) {
-                            for (int i = 0; i < 4; i++) accd[b][i] += (double)accf[b][i];
-                            accf[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                            const float bw = swt[srcc * SW + b * 16 + (lane & 15)];
+#pragma unroll
+                            for (int j = 0; j < TB; j++)
+                                accf[j][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv[j], bw, accf[j][b], 0, 0, 0);
+                        }
+                        if (++steps == 4) {
+                            steps = 0;
+#pragma unroll
+                            for (int j = 0; j < TB; j++)
+#pragma unroll
+                                for (int b = 0; b < NCB; b++) {
+                                    for (int i = 0; i < 4; i++) accd[j][b][i] += (double)accf[j][b][i];
+                                    accf[j][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                                }
                         }
                     }
                 }
             }
         }
-        }
 #pragma unroll
-        for (int b = 0; b < NCB; b++)
-            for (int i = 0; i < 4; i++) accd[b][i] += (double)accf[b][i];
-        // phases of the same block are added in order ph = 0, 1, ...
+        for (int j = 0; j < TB; j++)
+#pragma unroll
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) accd[j][b][i] += (double)accf[j][b][i];
+        // phases of the same unit are added in order ph = 0, 1, ...
         __syncthreads();
         if (nph > 1 && wact)
-            for (int b = 0; b < NCB; b++)
-                for (int i = 0; i < 4; i++) red[(wave * 64 + lane) * NCB * 4 + b * 4 + i] = accd[b][i];
+            for (int j = 0; j < TB; j++)
+                for (int b = 0; b < NCB; b++)
+                    for (int i = 0; i < 4; i++)
+                        red[((wave * 64 + lane) * TB + j) * NCB * 4 + b * 4 + i] = accd[j][b][i];
         __syncthreads();
         if (wact && ph == 0) {
             for (int p2 = 1; p2 < nph; p2++) {
-                int w2 = p2 * nb + myb;
-                for (int b = 0; b < NCB; b++)
-                    for (int i = 0; i < 4; i++) accd[b][i] += red[(w2 * 64 + lane) * NCB * 4 + b * 4 + i];
+                const int w2 = p2 * nb + myb;
+                for (int j = 0; j < TB; j++)
+                    for (int b = 0; b < NCB; b++)
+                        for (int i = 0; i < 4; i++)
+                            accd[j][b][i] += red[((w2 * 64 + lane) * TB + j) * NCB * 4 + b * 4 + i];
             }
-            for (int b = 0; b < NCB; b++)
-                for (int i = 0; i < 4; i++) {
-                    int32_t r = tb * 16 + 4 * (lane >> 4) + i;
-                    if (r < kk) dst[(int64_t)(po + r) * RP + b * 16 + (lane & 15)] = accd[b][i];
-                }
+            for (int j = 0; j < TB; j++)
+                for (int b = 0; b < NCB; b++)
+                    for (int i = 0; i < 4; i++) {
+                        const int32_t r = (tu * TB + j) * 16 + 4 * (lane >> 4) + i;
+                        if (r < kk) dst[(int64_t)(po + r) * RP + b * 16 + (lane & 15)] = accd[j][b][i];
+                    }
         }
         __syncthreads();
     }
@@ -530,7 +566,7 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
     double *part = P > 1 ? W.part : nullptr;
     const int g = (int)(L.ncell * P);
     if (mixed && l >= kap - 1) {
-#define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w[l], W.u[l], part, prm32)
+#define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w32[l], W.R, W.u[l], part, prm32)
         if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
         else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
         else MF(NNCA_K_GAUSS);
@@ -654,6 +690,14 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
                                                   L.crem64, src, W.w[l]);
             HIPCHECK(hipGetLastError());
         }
+        // FP32 copies of the multipole vectors the FP32 transverse pass reads
+        W.R = R;
+        if (mixed)
+            for (int l = std::max(lmin, kap - 1); l <= kap; l++) {
+                const int64_t cnt = H->lev[l].npiv * RP;
+                k_to_f32<<<grid_for(cnt, 256), 256, 0, s>>>(cnt, W.w[l], W.w32[l]);
+                HIPCHECK(hipGetLastError());
+            }
         const std::vector<int32_t> *tab = nullptr;
         if (H->autotune) {
             const int key = NCB * 2 + (mixed ? 1 : 0);
@@ -699,10 +743,12 @@ void ensure_multi(nnca_h2 *H, int RP)
     W.xlo = dalloc<float>(n * RP);
     W.w.assign(H->kappa + 2, nullptr);
     W.u.assign(H->kappa + 2, nullptr);
+    W.w32.assign(H->kappa + 2, nullptr);
     int64_t part = 1;
     for (int l = H->lmin; l <= H->kappa; l++) {
         const Level &L = H->lev[l];
         W.w[l] = dalloc<double>(L.npiv * RP);
+        if (l >= H->kappa - 1) W.w32[l] = dalloc<float>(L.npiv * RP);
         W.u[l] = dalloc<double>(L.npiv * RP);
         part = std::max(part, (int64_t)parts_for(L) * L.npiv * RP);
     }
@@ -719,6 +765,7 @@ void free_multi(nnca_h2 *H)
     dfree(W.xs); dfree(W.far); dfree(W.xhi); dfree(W.xlo); dfree(W.part);
     for (auto p : W.w) dfree(p);
     for (auto p : W.u) dfree(p);
+    for (auto p : W.w32) dfree(p);
     W = nnca_h2::Multi();
 }
 

@@ -145,6 +145,8 @@ struct nnca_h2 {
         int64_t part_cap = 0;
         float *xhi = nullptr, *xlo = nullptr;
         std::vector<double *> w, u;   // per level
+        std::vector<float *> w32;     // per level: FP32 copy of w for the FP32 transverse pass
+        int R = 0;                    // columns of the block in flight
     } multi;
     // transverse-pass split factors per level picked by timing (autotune on),
     // keyed by column-block width and precision
