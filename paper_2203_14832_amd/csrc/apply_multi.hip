@@ -164,8 +164,7 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
     constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
     constexpr int RED = NT * NCB * 4 * TB;           // doubles of the phase reduction
     __shared__ float4 sx[TS];
-    __shared__ int32_t sidx[TS];
-    __shared__ double swt_raw[TS * SW / 2 > RED ? TS * SW / 2 : RED];
+    __shared__ __align__(16) double swt_raw[TS * SW / 2 > RED ? TS * SW / 2 : RED];
     __shared__ int32_t est[MET + 1], ebase[MET];
     __shared__ float esh[3][MET];
     float *swt = reinterpret_cast<float *>(swt_raw);
@@ -234,19 +233,18 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
                         if (est[mid] <= s) lo = mid; else hi = mid - 1;
                     }
                     const int32_t idx = ebase[lo] + s;
-                    sidx[t] = idx;
                     float4 v;
                     v.x = pc[idx] + esh[0][lo];
                     v.y = pc[npiv + idx] + esh[1][lo];
                     v.z = d == 3 ? pc[2 * npiv + idx] + esh[2][lo] : 0.f;
                     v.w = 0.f;
                     sx[t] = v;
-                }
-                __syncthreads();
-                // FP32 weights of the R real columns; the padding columns are zero
-                for (int32_t e = t; e < ns * RP; e += NT) {
-                    const int32_t sr = e / RP, col = e % RP;
-                    swt[sr * SW + col] = col < R ? w32[(int64_t)sidx[sr] * RP + col] : 0.f;
+                    // this source's FP32 weights, four columns at a time: the
+                    // columns up to R (padding columns of w are zero), then zeros
+                    const float4 *wr = reinterpret_cast<const float4 *>(w32 + (int64_t)idx * RP);
+                    float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
+#pragma unroll
+                    for (int q = 0; q < RP / 4; q++) wd[q] = 4 * q < R ? wr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 __syncthreads();
                 if (wact) {
