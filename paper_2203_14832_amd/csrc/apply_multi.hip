@@ -321,13 +321,12 @@ template <int KIND, int MODE, int NCB>
 __global__ __launch_bounds__(NT) void k_m2l_mfma64(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                    const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                    const int32_t *ilsum, const double *pc, int64_t npiv, int d,
-                                                   const double *w, double *u, double *part_out, double prm)
+                                                   const double *w, int R, double *u, double *part_out, double prm)
 {
     constexpr int RP = NCB * 16;
     constexpr int TS = 64;
     __shared__ double4 sx[TS];
-    __shared__ int32_t sidx[TS];
-    __shared__ double swt[TS * RP > NT * NCB * 4 ? TS * RP : NT * NCB * 4];
+    __shared__ __align__(16) double swt[TS * RP > NT * NCB * 4 ? TS * RP : NT * NCB * 4];
     double *red = swt;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int64_t c = blockIdx.x / P;
@@ -356,11 +355,13 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma64(int64_t nc, int P, const int3
                 int32_t s = s0 + t;
                 int32_t e = list_entry(ilpre, e0, e1, s);
                 int32_t idx = piv_ptr[il[e]] + (s - ilpre[e]);
-                sidx[t] = idx;
                 sx[t] = make_double4(pc[idx], pc[npiv + idx], d == 3 ? pc[2 * npiv + idx] : 0.0, 0.0);
+                // this source's weights, two columns at a time (padding columns are zero)
+                const double2 *wr = reinterpret_cast<const double2 *>(w + (int64_t)idx * RP);
+                double2 *wd = reinterpret_cast<double2 *>(swt + t * RP);
+#pragma unroll
+                for (int q = 0; q < RP / 2; q++) wd[q] = 2 * q < R ? wr[q] : make_double2(0.0, 0.0);
             }
-            __syncthreads();
-            for (int32_t e = t; e < ns * RP; e += NT) swt[e] = w[(int64_t)sidx[e / RP] * RP + e % RP];
             __syncthreads();
             if (wact)
                 for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
@@ -417,9 +418,8 @@ __global__ __launch_bounds__(NT) void k_p2p_mfma(int64_t nc, const int32_t *firs
     constexpr bool mixed = sizeof(T) == 4;
     constexpr int SW = (mixed && !(NCB & 1)) ? RP + 16 : RP;   // LDS row stride (bank spread)
     __shared__ double4 sx[TS];
-    __shared__ int32_t sidx[TS];
-    __shared__ T swt[TS * SW];
-    __shared__ T swt2[mixed ? TS * SW : 1];
+    __shared__ __align__(16) T swt[TS * SW];
+    __shared__ __align__(16) T swt2[mixed ? TS * SW : 1];
     __shared__ double red[NT * NCB * 4];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int64_t c = blockIdx.x;
@@ -452,14 +452,24 @@ __global__ __launch_bounds__(NT) void k_p2p_mfma(int64_t nc, const int32_t *firs
                 int32_t s = s0 + t;
                 int32_t e = list_entry(nbpre, e0, e1, s);
                 int32_t idx = first[nb[e]] + (s - nbpre[e]);
-                sidx[t] = idx;
                 sx[t] = make_double4(pts[idx], pts[n + idx], d == 3 ? pts[2 * n + idx] : 0.0, 0.0);
-            }
-            __syncthreads();
-            for (int32_t e = t; e < ns * RP; e += NT) {
-                int64_t src = (int64_t)sidx[e / RP] * RP + e % RP;
-                swt[(e / RP) * SW + e % RP] = xw[src];
-                if (mixed) swt2[(e / RP) * SW + e % RP] = xw2[src];
+                // this source's weights, 16 bytes at a time (padding columns are zero)
+                if constexpr (mixed) {
+                    const float4 *a = reinterpret_cast<const float4 *>(xw + (int64_t)idx * RP);
+                    const float4 *b = reinterpret_cast<const float4 *>(xw2 + (int64_t)idx * RP);
+                    float4 *da = reinterpret_cast<float4 *>(swt + t * SW);
+                    float4 *db = reinterpret_cast<float4 *>(swt2 + t * SW);
+#pragma unroll
+                    for (int q = 0; q < RP / 4; q++) {
+                        da[q] = 4 * q < R ? a[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                        db[q] = 4 * q < R ? b[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                } else {
+                    const double2 *a = reinterpret_cast<const double2 *>(xw + (int64_t)idx * RP);
+                    double2 *da = reinterpret_cast<double2 *>(swt + t * SW);
+#pragma unroll
+                    for (int q = 0; q < RP / 2; q++) da[q] = 2 * q < R ? a[q] : make_double2(0.0, 0.0);
+                }
             }
             __syncthreads();
             if (wact) {
@@ -570,7 +580,7 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
         else MF(NNCA_K_GAUSS);
 #undef MF
     } else {
-#define VM(K, M) k_m2l_mfma64<K, M, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc64, L.npiv, H->dim, W.w[l], W.u[l], part, prm64)
+#define VM(K, M) k_m2l_mfma64<K, M, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc64, L.npiv, H->dim, W.w[l], W.R, W.u[l], part, prm64)
         if (!mixed) {
             if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 1);
             else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 1);
