@@ -681,6 +681,7 @@ struct SymShared {
         struct {
             T4 src[SYM_TS];
             int32_t sslot[SYM_TS];
+            float sn[SYM_TS];   // FP32 form: |s|^2 of the shifted source
         } tile;
         double part[NT * 8];
     } u;
@@ -695,6 +696,12 @@ struct SymShared {
 // a source is summed inside the group by group_sum; lane ti keeps the sums of
 // the sources whose running index is ti mod TPG and the group stores them
 // together once every TPG sources.
+//
+// FP32 form: r^2 = |t|^2 + |s|^2 - 2 t.s, one addition and three FMAs per
+// pair with -2t and |t|^2 per target and |s|^2 per source (all in the
+// target cell's frame, where |t|, |s| are at most a few cell widths and an
+// admissible r is at least one, so the cancellation costs a few units in the
+// last place of r^2), against three differences, a product and two FMAs.
 template <int KIND, int MODE, int TPG, int R>
 __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int pp, int32_t kk)
 {
@@ -714,7 +721,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
     const T *pc;
     if constexpr (F32) pc = A.pc32; else pc = A.pc64;
     double *dst = A.P > 1 ? A.part + (int64_t)pp * npiv : A.u;
-    T tx[R], ty[R], tz[R], tw[R];
+    T tx[R], ty[R], tz[R], tw[R], tn[R];
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -726,6 +733,12 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
         tz[r] = d == 3 ? pc[2 * npiv + q] : T(0);
         tw[r] = ok ? (T)A.w[q] : T(0);   // padding targets add nothing to column sums
         acc[r] = 0.0;
+        if constexpr (F32) {
+            tn[r] = tx[r] * tx[r] + ty[r] * ty[r] + tz[r] * tz[r];
+            tx[r] *= -2.f;
+            ty[r] *= -2.f;
+            tz[r] *= -2.f;
+        }
     }
     const T prm = (T)A.prm;
     // first owned entry holding source sb
@@ -761,6 +774,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             // contiguous sources per thread: one search, then a few steps
             T4 v[SPT];
             int32_t sl[SPT];
+            float sn[SPT];
             const int32_t sfirst = s0 + t * SPT;
             int32_t lo = 0;
             if (sfirst < s0 + ns) {
@@ -775,6 +789,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                 const int32_t s = sfirst + q;
                 v[q].x = 0; v[q].y = 0; v[q].z = 0; v[q].w = 0;
                 sl[q] = 0;
+                sn[q] = 0.f;
                 if (s < s0 + ns) {
                     while (sh.est[lo + 1] <= s) lo++;
                     const int32_t idx = sh.ebase[lo] + s;
@@ -786,6 +801,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                         v[q].x += sh.esh[0][lo];
                         v[q].y += sh.esh[1][lo];
                         v[q].z += sh.esh[2][lo];
+                        sn[q] = (float)(v[q].x * v[q].x + v[q].y * v[q].y + v[q].z * v[q].z);
                     }
                     sl[q] = sh.eslot[lo] + s;
                 }
@@ -795,6 +811,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             for (int q = 0; q < SPT; q++) {
                 sh.u.tile.src[t * SPT + q] = v[q];
                 sh.u.tile.sslot[t * SPT + q] = sl[q];
+                if (F32) sh.u.tile.sn[t * SPT + q] = sn[q];
             }
             __syncthreads();
             T a[R];
@@ -805,13 +822,22 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             int it = 0;
             for (int32_t j = g; j < ns; j += G, it++) {
                 const T4 q = sh.u.tile.src[j];
+                T qn = T(0);
+                if constexpr (F32) qn = sh.u.tile.sn[j];
                 T cp = T(0);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
-                    const T dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
                     T kv_;
-                    if constexpr (F32) kv_ = kv32<KIND>(dx * dx + dy * dy + dz * dz, prm);
-                    else kv_ = kv_refined<KIND, MODE>(dx * dx + dy * dy + dz * dz, prm);
+                    if constexpr (F32) {
+                        T r2 = tn[r] + qn;
+                        r2 = fmaf(tz[r], q.z, r2);
+                        r2 = fmaf(ty[r], q.y, r2);
+                        r2 = fmaf(tx[r], q.x, r2);
+                        kv_ = kv32<KIND>(r2, prm);
+                    } else {
+                        const T dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
+                        kv_ = kv_refined<KIND, MODE>(dx * dx + dy * dy + dz * dz, prm);
+                    }
                     a[r] += kv_ * q.w;
                     cp += kv_ * tw[r];
                 }
@@ -853,7 +879,9 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
     }
 }
 
-template <int KIND, int MODE>
+// BIG: levels with ranks above 224 (the only shape with eight registers per
+// lane; with it in the kernel every cell would pay its register footprint).
+template <int KIND, int MODE, bool BIG>
 __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
 {
     __shared__ SymShared<MODE> sh;
@@ -869,15 +897,15 @@ __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
     else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
     else if (kk <= 48) sym_cell<KIND, MODE, 8, 6>(A, sh, c, pp, kk);
     else if (kk <= 56) sym_cell<KIND, MODE, 8, 7>(A, sh, c, pp, kk);
-    else if (kk <= 64) sym_cell<KIND, MODE, 8, 8>(A, sh, c, pp, kk);
+    else if (kk <= 64) sym_cell<KIND, MODE, 16, 4>(A, sh, c, pp, kk);
     else if (kk <= 80) sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
     else if (kk <= 96) sym_cell<KIND, MODE, 16, 6>(A, sh, c, pp, kk);
     else if (kk <= 112) sym_cell<KIND, MODE, 16, 7>(A, sh, c, pp, kk);
-    else if (kk <= 128) sym_cell<KIND, MODE, 16, 8>(A, sh, c, pp, kk);
+    else if (kk <= 128) sym_cell<KIND, MODE, 32, 4>(A, sh, c, pp, kk);
     else if (kk <= 160) sym_cell<KIND, MODE, 32, 5>(A, sh, c, pp, kk);
     else if (kk <= 192) sym_cell<KIND, MODE, 32, 6>(A, sh, c, pp, kk);
-    else if (kk <= 224) sym_cell<KIND, MODE, 32, 7>(A, sh, c, pp, kk);
-    else sym_cell<KIND, MODE, 32, 8>(A, sh, c, pp, kk);
+    else if (!BIG || kk <= 224) sym_cell<KIND, MODE, 32, 7>(A, sh, c, pp, kk);
+    else if constexpr (BIG) sym_cell<KIND, MODE, 32, 8>(A, sh, c, pp, kk);
 }
 
 // u^{B,i} += the column sums of the pairs owned by B's partners, in list order
@@ -984,6 +1012,13 @@ static int sym_parts(const nnca::Level &L)
     return P < 1 ? 1 : (int)P;
 }
 
+template <int KIND, int MODE>
+static void sym_launch(bool big, int g, const SymArgs &A, hipStream_t s)
+{
+    if (big) k_m2l_sym<KIND, MODE, true><<<g, NT, 0, s>>>(A);
+    else k_m2l_sym<KIND, MODE, false><<<g, NT, 0, s>>>(A);
+}
+
 template <int MODE>
 static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level, double prm, hipStream_t s)
 {
@@ -1004,7 +1039,7 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
     const int g = (int)(nc * P);
     {
         Span sp(H, s, PASS_M2L, level);
-#define SYM_CASE(K) k_m2l_sym<K, MODE><<<g, NT, 0, s>>>(A)
+#define SYM_CASE(K) sym_launch<K, MODE>(L.max_k > 224, g, A, s)
         if (kind == NNCA_K_INV_R) SYM_CASE(NNCA_K_INV_R);
         else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
         else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
