@@ -31,17 +31,17 @@ METRIC = "H2 matvecs/s at N=1M 3D 1/r, mixed vs FP64 at rel.err≤1e-6; % roofli
 # of the two finest levels.  Its bound is plain VALU arithmetic.  Peak FP32
 # vector rate of the chip: 157.3 TFLOP/s = 256 CU x 128 lanes/clock x
 # 2.4 GHz x 2 (FMA), i.e. 7.864e13 lane-instructions/s.  One unordered pair
-# of pivots costs 3 subtractions, 1 multiply and 2 FMA for r^2, one v_rsq_f32
-# (quarter rate: 4 issue slots) and 2 FMA (its row and its column term): 12
-# slots.  (The plain pass spends 11 slots on each ordered pair.)
+# of pivots costs 1 addition and 3 FMA for r^2 = |t|^2 + |s|^2 - 2 t.s, one
+# v_rsq_f32 (quarter rate: 4 issue slots) and 2 FMA (its row and its column
+# term): 10 slots.
 VALU_LANE_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_PAIR = 12.0
+SLOTS_PER_PAIR = 10.0
 PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
 # HBM bytes per launch of that kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs of `bench.py --probe` (profiles/h2_matvec_c2_hbm_bytes.md), scaled by
 # the counters' reading of a 256 MiB copy: fetch + write MiB at kappa and
-# kappa-1.  Valid for this version of k_m2l_sym; None once the kernel changes.
-M2L_SYM_HBM_MIB = ((277.8, 339.2), (94.5, 116.8))
+# kappa-1.  Valid for one version of k_m2l_sym; None once the kernel changes.
+M2L_SYM_HBM_MIB = None
 
 
 def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3):
@@ -202,8 +202,8 @@ def main():
                      "avg_launch_ms": float(m2l_ms.mean()) if m2l_ms.size else None,
                      "pairs_per_launch": pairs / max(launches_per_step, 1),
                      "directed_interactions_per_s": 2 * pair_rate,
-                     "peak_derivation": "7.864e13 FP32 lane-instr/s / 12 slots per pair "
-                                        "(r^2: 3 sub + mul + 2 fma; 1/r: v_rsq_f32 = 4; 2 fma)"},
+                     "peak_derivation": "7.864e13 FP32 lane-instr/s / 10 slots per pair "
+                                        "(r^2: add + 3 fma; 1/r: v_rsq_f32 = 4; 2 fma)"},
         "m2l_coarse_fp64_ms_per_step": coarse_ms, "m2l_level_interactions": info["m2l_level"],
         "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,

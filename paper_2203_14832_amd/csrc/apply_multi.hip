@@ -187,7 +187,9 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
         const int myb = wave % nb, ph = wave / nb;
         const bool wact = ph < nph;
         const int32_t tu = tu0 + myb;
-        float tx[TB], ty[TB], tz[TB];
+        // r^2 = |t|^2 + |s|^2 - 2 t.s in the target cell's frame (one
+        // addition and three FMAs): -2t and |t|^2 per target, |s|^2 per source
+        float tx[TB], ty[TB], tz[TB], tn[TB];
 #pragma unroll
         for (int j = 0; j < TB; j++) {
             const int32_t row = (tu * TB + j) * 16 + (lane & 15);
@@ -195,6 +197,10 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
             tx[j] = pc[po + rc];
             ty[j] = pc[npiv + po + rc];
             tz[j] = d == 3 ? pc[2 * npiv + po + rc] : 0.f;
+            tn[j] = tx[j] * tx[j] + ty[j] * ty[j] + tz[j] * tz[j];
+            tx[j] *= -2.f;
+            ty[j] *= -2.f;
+            tz[j] *= -2.f;
         }
         floatx4 accf[TB][NCB];
         double accd[TB][NCB][4];
@@ -237,7 +243,7 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
                     v.x = pc[idx] + esh[0][lo];
                     v.y = pc[npiv + idx] + esh[1][lo];
                     v.z = d == 3 ? pc[2 * npiv + idx] + esh[2][lo] : 0.f;
-                    v.w = 0.f;
+                    v.w = v.x * v.x + v.y * v.y + v.z * v.z;
                     sx[t] = v;
                     // this source's FP32 weights, four columns at a time: the
                     // columns up to R (padding columns of w are zero), then zeros
@@ -256,8 +262,11 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
                         float kvv[TB];
 #pragma unroll
                         for (int j = 0; j < TB; j++) {
-                            const float dx = tx[j] - q.x, dy = ty[j] - q.y, dz = tz[j] - q.z;
-                            kvv[j] = src < ns ? kv32<KIND>(dx * dx + dy * dy + dz * dz, prm) : 0.f;
+                            float r2 = tn[j] + q.w;
+                            r2 = fmaf(tz[j], q.z, r2);
+                            r2 = fmaf(ty[j], q.y, r2);
+                            r2 = fmaf(tx[j], q.x, r2);
+                            kvv[j] = src < ns ? kv32<KIND>(r2, prm) : 0.f;
                         }
 #pragma unroll
                         for (int b = 0; b < NCB; b++) {
