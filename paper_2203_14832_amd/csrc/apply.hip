@@ -682,6 +682,7 @@ struct SymShared {
             T4 src[SYM_TS];
             int32_t sslot[SYM_TS];
             float sn[SYM_TS];   // FP32 form: |s|^2 of the shifted source
+            typename SymT<MODE>::T scol[SYM_TS];   // column sums of the tile's sources
         } tile;
         double part[NT * 8];
     } u;
@@ -693,9 +694,11 @@ struct SymShared {
 // wavefront, TPG * R >= k), G = NT / TPG groups; target i is held by lane
 // i % TPG as its (i / TPG)-th register.  Group g takes sources g, g + G, ...
 // of each tile; all its lanes run the same sources, so the column partial of
-// a source is summed inside the group by group_sum; lane ti keeps the sums of
-// the sources whose running index is ti mod TPG and the group stores them
-// together once every TPG sources.
+// a source is summed inside the group by group_sum (a butterfly: every lane
+// of the group ends with the sum), written to the tile's column slots in LDS
+// and flushed to the column buffer after the tile.  Tiles are padded to whole
+// rounds of G sources with zero-weight sources far from every target, so all
+// groups run the same number of steps.
 //
 // FP32 form: r^2 = |t|^2 + |s|^2 - 2 t.s, one addition and three FMAs per
 // pair with -2t and |t|^2 per target and |s|^2 per source (all in the
@@ -787,9 +790,10 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
 #pragma unroll
             for (int q = 0; q < SPT; q++) {
                 const int32_t s = sfirst + q;
-                v[q].x = 0; v[q].y = 0; v[q].z = 0; v[q].w = 0;
+                // padding of a round: weight 0, far from every target (finite kernel value)
+                v[q].x = T(1e15); v[q].y = v[q].x; v[q].z = v[q].x; v[q].w = 0;
                 sl[q] = 0;
-                sn[q] = 0.f;
+                sn[q] = 3e30f;
                 if (s < s0 + ns) {
                     while (sh.est[lo + 1] <= s) lo++;
                     const int32_t idx = sh.ebase[lo] + s;
@@ -817,10 +821,9 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             T a[R];
 #pragma unroll
             for (int r = 0; r < R; r++) a[r] = T(0);
-            T keep = T(0);
-            int32_t kj = -1;
-            int it = 0;
-            for (int32_t j = g; j < ns; j += G, it++) {
+            const int32_t nr = (ns + G - 1) / G;   // rounds: source g + it G in round it
+            for (int it = 0; it < nr; it++) {
+                const int32_t j = g + it * G;
                 const T4 q = sh.u.tile.src[j];
                 T qn = T(0);
                 if constexpr (F32) qn = sh.u.tile.sn[j];
@@ -841,16 +844,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                     a[r] += kv_ * q.w;
                     cp += kv_ * tw[r];
                 }
-                cp = group_sum<TPG>(cp);
-                if ((it & (TPG - 1)) == ti) {
-                    keep = cp;
-                    kj = j;
-                }
-                if ((it & (TPG - 1)) == TPG - 1) {
-                    if constexpr (F32) A.col32[sh.u.tile.sslot[kj]] = keep;
-                    else A.col64[sh.u.tile.sslot[kj]] = keep;
-                    kj = -1;
-                }
+                sh.u.tile.scol[j] = group_sum<TPG>(cp);   // the same value from every lane of the group
                 if (F32 && (it & (CHUNK - 1)) == CHUNK - 1) {
 #pragma unroll
                     for (int r = 0; r < R; r++) {
@@ -859,9 +853,10 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                     }
                 }
             }
-            if (kj >= 0) {
-                if constexpr (F32) A.col32[sh.u.tile.sslot[kj]] = keep;
-                else A.col64[sh.u.tile.sslot[kj]] = keep;
+            __syncthreads();
+            for (int32_t j = t; j < ns; j += NT) {
+                if constexpr (F32) A.col32[sh.u.tile.sslot[j]] = sh.u.tile.scol[j];
+                else A.col64[sh.u.tile.sslot[j]] = sh.u.tile.scol[j];
             }
 #pragma unroll
             for (int r = 0; r < R; r++) acc[r] += (double)a[r];
