@@ -887,7 +887,9 @@ __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
     // lanes per group and registers per lane fitted to the rank
     if (kk <= 8) sym_cell<KIND, MODE, 2, 4>(A, sh, c, pp, kk);
     else if (kk <= 16) sym_cell<KIND, MODE, 4, 4>(A, sh, c, pp, kk);
-    else if (kk <= 24) sym_cell<KIND, MODE, 8, 3>(A, sh, c, pp, kk);
+    else if (kk <= 20) sym_cell<KIND, MODE, 4, 5>(A, sh, c, pp, kk);
+    else if (kk <= 24) sym_cell<KIND, MODE, 4, 6>(A, sh, c, pp, kk);
+    else if (kk <= 28) sym_cell<KIND, MODE, 4, 7>(A, sh, c, pp, kk);
     else if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
     else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
     else if (kk <= 48) sym_cell<KIND, MODE, 8, 6>(A, sh, c, pp, kk);
