@@ -769,6 +769,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             }
         }
         if (t == 0) sh.est[wn] = w0 + wn < e1 ? A.own_pre[w0 + wn] : S;
+        for (int32_t j = wn + 1 + t; j <= ET; j += NT) sh.est[j] = INT32_MAX;   // past the window
         __syncthreads();
         if (sh.est[0] >= se) break;
         const int32_t ws = sh.est[0] > sb ? sh.est[0] : sb, we = sh.est[wn] < se ? sh.est[wn] : se;
@@ -779,14 +780,12 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             int32_t sl[SPT];
             float sn[SPT];
             const int32_t sfirst = s0 + t * SPT;
+            // the last entry starting at or before sfirst: a fixed, branchless
+            // search over the ET + 1 starts (est[0] <= sfirst for every source
+            // of the window; starts past the window are INT32_MAX)
             int32_t lo = 0;
-            if (sfirst < s0 + ns) {
-                int32_t hi = wn - 1;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi + 1) >> 1;
-                    if (sh.est[mid] <= sfirst) lo = mid; else hi = mid - 1;
-                }
-            }
+#pragma unroll
+            for (int hstep = ET / 2; hstep >= 1; hstep >>= 1) lo = sh.est[lo + hstep] <= sfirst ? lo + hstep : lo;
 #pragma unroll
             for (int q = 0; q < SPT; q++) {
                 const int32_t s = sfirst + q;
