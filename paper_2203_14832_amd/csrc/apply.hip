@@ -651,6 +651,14 @@ __device__ inline T group_sum(T v)
     return v;
 }
 
+// a load at a 32-bit byte offset from a base pointer (the base stays in
+// scalar registers; no 64-bit address arithmetic per lane)
+template <typename T>
+__device__ inline T ld_off(const T *base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 constexpr int SYM_MAXK = 256;   // largest rank of a level on this pass (one target tile)
 constexpr int SYM_TS = 512;     // sources per LDS tile
 
@@ -789,17 +797,20 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
 #pragma unroll
             for (int q = 0; q < SPT; q++) {
                 const int32_t s = sfirst + q;
-                // padding of a round: weight 0, far from every target (finite kernel value)
-                v[q].x = T(1e15); v[q].y = v[q].x; v[q].z = v[q].x; v[q].w = 0;
-                sl[q] = 0;
-                sn[q] = 3e30f;
-                if (s < s0 + ns) {
-                    while (sh.est[lo + 1] <= s) lo++;
-                    const int32_t idx = sh.ebase[lo] + s;
-                    v[q].x = pc[idx];
-                    v[q].y = pc[npiv + idx];
-                    v[q].z = d == 3 ? pc[2 * npiv + idx] : T(0);
-                    v[q].w = (T)A.w[idx];
+                // every list entry holds at least one source (cells without
+                // pivots own no pairs and are no partners): one step at most
+                if (q > 0) lo = sh.est[lo + 1] <= s ? lo + 1 : lo;
+                if (s >= s0 + ns) {   // padding of a round: weight 0, far from every target
+                    v[q].x = T(1e15); v[q].y = v[q].x; v[q].z = v[q].x; v[q].w = 0;
+                    sl[q] = 0;
+                    sn[q] = 3e30f;
+                } else {
+                    // 32-bit byte offsets from the arrays' bases (scalar registers)
+                    const uint32_t idx = (uint32_t)(sh.ebase[lo] + s);
+                    v[q].x = ld_off(pc, idx * (uint32_t)sizeof(T));
+                    v[q].y = ld_off(pc + npiv, idx * (uint32_t)sizeof(T));
+                    v[q].z = d == 3 ? ld_off(pc + 2 * npiv, idx * (uint32_t)sizeof(T)) : T(0);
+                    v[q].w = (T)ld_off(A.w, idx * 8u);
                     if (F32) {
                         v[q].x += sh.esh[0][lo];
                         v[q].y += sh.esh[1][lo];
@@ -812,9 +823,10 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             __syncthreads();   // the previous tile is done with src and sslot
 #pragma unroll
             for (int q = 0; q < SPT; q++) {
-                sh.u.tile.src[t * SPT + q] = v[q];
-                sh.u.tile.sslot[t * SPT + q] = sl[q];
-                if (F32) sh.u.tile.sn[t * SPT + q] = sn[q];
+                const int32_t pos = t * SPT + q;
+                sh.u.tile.src[pos] = v[q];
+                sh.u.tile.sslot[pos] = sl[q];
+                if (F32) sh.u.tile.sn[pos] = sn[q];
             }
             __syncthreads();
             T a[R];
