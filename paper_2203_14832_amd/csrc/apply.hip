@@ -885,9 +885,12 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
     }
 }
 
-// BIG: levels with ranks above 224 (the only shape with eight registers per
-// lane; with it in the kernel every cell would pay its register footprint).
-template <int KIND, int MODE, bool BIG>
+// Shape sets, picked per level from its largest rank: the registers of the
+// largest shape in a kernel set its occupancy.  SET 0 (ranks <= 80): at most
+// five registers per lane (80 VGPRs, six waves per SIMD); SET 1 (<= 224): at
+// most seven (five waves); SET 2: SET 1 and eight registers per lane for
+// ranks above 224.
+template <int KIND, int MODE, int SET>
 __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
 {
     __shared__ SymShared<MODE> sh;
@@ -899,21 +902,29 @@ __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
     if (kk <= 8) sym_cell<KIND, MODE, 2, 4>(A, sh, c, pp, kk);
     else if (kk <= 16) sym_cell<KIND, MODE, 4, 4>(A, sh, c, pp, kk);
     else if (kk <= 20) sym_cell<KIND, MODE, 4, 5>(A, sh, c, pp, kk);
-    else if (kk <= 24) sym_cell<KIND, MODE, 4, 6>(A, sh, c, pp, kk);
-    else if (kk <= 28) sym_cell<KIND, MODE, 4, 7>(A, sh, c, pp, kk);
-    else if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
-    else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
-    else if (kk <= 48) sym_cell<KIND, MODE, 8, 6>(A, sh, c, pp, kk);
-    else if (kk <= 56) sym_cell<KIND, MODE, 8, 7>(A, sh, c, pp, kk);
-    else if (kk <= 64) sym_cell<KIND, MODE, 16, 4>(A, sh, c, pp, kk);
-    else if (kk <= 80) sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
-    else if (kk <= 96) sym_cell<KIND, MODE, 16, 6>(A, sh, c, pp, kk);
-    else if (kk <= 112) sym_cell<KIND, MODE, 16, 7>(A, sh, c, pp, kk);
-    else if (kk <= 128) sym_cell<KIND, MODE, 32, 4>(A, sh, c, pp, kk);
-    else if (kk <= 160) sym_cell<KIND, MODE, 32, 5>(A, sh, c, pp, kk);
-    else if (kk <= 192) sym_cell<KIND, MODE, 32, 6>(A, sh, c, pp, kk);
-    else if (!BIG || kk <= 224) sym_cell<KIND, MODE, 32, 7>(A, sh, c, pp, kk);
-    else if constexpr (BIG) sym_cell<KIND, MODE, 32, 8>(A, sh, c, pp, kk);
+    else if constexpr (SET == 0) {
+        if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
+        else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
+        else if (kk <= 48) sym_cell<KIND, MODE, 16, 3>(A, sh, c, pp, kk);
+        else if (kk <= 64) sym_cell<KIND, MODE, 16, 4>(A, sh, c, pp, kk);
+        else sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
+    } else {
+        if (kk <= 24) sym_cell<KIND, MODE, 4, 6>(A, sh, c, pp, kk);
+        else if (kk <= 28) sym_cell<KIND, MODE, 4, 7>(A, sh, c, pp, kk);
+        else if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
+        else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
+        else if (kk <= 48) sym_cell<KIND, MODE, 8, 6>(A, sh, c, pp, kk);
+        else if (kk <= 56) sym_cell<KIND, MODE, 8, 7>(A, sh, c, pp, kk);
+        else if (kk <= 64) sym_cell<KIND, MODE, 16, 4>(A, sh, c, pp, kk);
+        else if (kk <= 80) sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
+        else if (kk <= 96) sym_cell<KIND, MODE, 16, 6>(A, sh, c, pp, kk);
+        else if (kk <= 112) sym_cell<KIND, MODE, 16, 7>(A, sh, c, pp, kk);
+        else if (kk <= 128) sym_cell<KIND, MODE, 32, 4>(A, sh, c, pp, kk);
+        else if (kk <= 160) sym_cell<KIND, MODE, 32, 5>(A, sh, c, pp, kk);
+        else if (kk <= 192) sym_cell<KIND, MODE, 32, 6>(A, sh, c, pp, kk);
+        else if (SET == 1 || kk <= 224) sym_cell<KIND, MODE, 32, 7>(A, sh, c, pp, kk);
+        else if constexpr (SET == 2) sym_cell<KIND, MODE, 32, 8>(A, sh, c, pp, kk);
+    }
 }
 
 // u^{B,i} += the column sums of the pairs owned by B's partners, in list order
@@ -1021,10 +1032,11 @@ static int sym_parts(const nnca::Level &L)
 }
 
 template <int KIND, int MODE>
-static void sym_launch(bool big, int g, const SymArgs &A, hipStream_t s)
+static void sym_launch(int32_t max_k, int g, const SymArgs &A, hipStream_t s)
 {
-    if (big) k_m2l_sym<KIND, MODE, true><<<g, NT, 0, s>>>(A);
-    else k_m2l_sym<KIND, MODE, false><<<g, NT, 0, s>>>(A);
+    if (max_k <= 80) k_m2l_sym<KIND, MODE, 0><<<g, NT, 0, s>>>(A);
+    else if (max_k <= 224) k_m2l_sym<KIND, MODE, 1><<<g, NT, 0, s>>>(A);
+    else k_m2l_sym<KIND, MODE, 2><<<g, NT, 0, s>>>(A);
 }
 
 template <int MODE>
@@ -1047,7 +1059,7 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
     const int g = (int)(nc * P);
     {
         Span sp(H, s, PASS_M2L, level);
-#define SYM_CASE(K) sym_launch<K, MODE>(L.max_k > 224, g, A, s)
+#define SYM_CASE(K) sym_launch<K, MODE>(L.max_k, g, A, s)
         if (kind == NNCA_K_INV_R) SYM_CASE(NNCA_K_INV_R);
         else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
         else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
