@@ -202,6 +202,10 @@ typedef struct {
     int64_t m2l_interactions;             /* sum over IL pairs of k_B k_B'      */
     int64_t p2p_interactions;             /* sum over near pairs |t^B| |t^B'|   */
     double build_seconds;
+    int32_t mixed_fp32_levels;            /* NNCA_PREC_MIXED: the finest levels whose
+                                             transverse pass runs in FP32 (2 for
+                                             1/r, 1 for the other kernels; the
+                                             coarser ones in refined FP64)      */
 } nnca_info;
 
 /* Structure and statistics of a handle (blocking). */

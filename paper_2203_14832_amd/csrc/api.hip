@@ -347,6 +347,7 @@ nnca_status nnca_query(nnca_handle h, nnca_info *info)
         info->m2l_interactions = h->m2l_inter;
         info->p2p_interactions = h->p2p_inter;
         info->build_seconds = h->build_seconds;
+        info->mixed_fp32_levels = h->fp32_levels;
     });
 }
 

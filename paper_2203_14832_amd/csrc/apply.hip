@@ -1149,19 +1149,20 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             HIPCHECK(hipGetLastError());
         }
         // transverse pass; the mixed matvec keeps the coarse levels
-        // (l <= kappa - 2) in refined FP64 arithmetic
+        // (l <= kappa - fp32_levels) in refined FP64 arithmetic
         const double prm64 = 1.0 / (H->hparam * H->hparam);
+        const int lf64 = kap - H->fp32_levels;
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
             const bool sym = L.sym && !(H->apply_flags & NNCA_APPLY_NO_SYMMETRIC);
             if (f32 && sym) {   // the launcher times its kernel and its combine step apart
-                if (l <= kap - 2) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s);
+                if (l <= lf64) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s);
                 else launch_m2l_sym<M_F32>(kind, H, L, l, (double)prm, s);
                 continue;
             }
             Span sp(H, s, PASS_M2L, l);
             if (!f32) launch_m2l_mode<M_F64>(kind, H, L, L.pc64, prm64, s);
-            else if (l <= kap - 2) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s);
+            else if (l <= lf64) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s);
             else launch_m2l_mode<M_F32>(kind, H, L, L.pc32, (double)prm, s);
         }
         // downward pass; with the near field overlapped, the leaf level adds
@@ -1329,9 +1330,11 @@ void prepare_apply(nnca_h2 *H)
         p2p += (int64_t)hc[c] * nbs[c];
         H->max_leaf = std::max(H->max_leaf, hc[c]);
     }
-    // the mixed matvec runs the two finest levels in the FP32 form, the
-    // coarser ones in the FP64-refined form
-    for (int l = H->lmin; l <= H->kappa; l++) prepare_symmetric(H, H->lev[l], l <= H->kappa - 2);
+    // the mixed matvec runs the finest levels in the FP32 form, the coarser
+    // ones in the FP64-refined form
+    H->fp32_levels = mixed_fp32_levels(H->kind);
+    for (int l = H->lmin; l <= H->kappa; l++)
+        prepare_symmetric(H, H->lev[l], l <= H->kappa - H->fp32_levels);
     H->m2l_inter = m2l;
     H->p2p_inter = p2p;
     H->transfer_entries = trans;
@@ -1343,6 +1346,15 @@ void prepare_apply(nnca_h2 *H)
     H->xhi = dalloc<float>(H->n);
     H->xlo = dalloc<float>(H->n);
 }
+
+// Levels of the mixed matvec whose transverse pass runs in FP32, counted
+// from the leaves; the coarser ones run in refined FP64.  The nested
+// interpolation operators amplify FP32 rounding injected at a level on its
+// way down; measured against FP64 (three right-hand sides each): 1/r at 2^20
+// points 3.8e-7 with two FP32 levels; the Gaussian mixture of 200 000 points
+// 0.45-1.08e-6 with two, 0.14-0.38e-6 with one.  The 2D log kernel's
+// operators have the largest entries.
+int mixed_fp32_levels(int kind) { return kind == NNCA_K_INV_R ? 2 : 1; }
 
 void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
                 hipStream_t s)

@@ -582,7 +582,7 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
     const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
     double *part = P > 1 ? W.part : nullptr;
     const int g = (int)(L.ncell * P);
-    if (mixed && l >= kap - 1) {
+    if (mixed && l > kap - H->fp32_levels) {
 #define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w32[l], W.R, W.u[l], part, prm32)
         if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
         else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
@@ -710,7 +710,7 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
         // FP32 copies of the multipole vectors the FP32 transverse pass reads
         W.R = R;
         if (mixed)
-            for (int l = std::max(lmin, kap - 1); l <= kap; l++) {
+            for (int l = std::max(lmin, kap - H->fp32_levels + 1); l <= kap; l++) {
                 const int64_t cnt = H->lev[l].npiv * RP;
                 k_to_f32<<<grid_for(cnt, 256), 256, 0, s>>>(cnt, W.w[l], W.w32[l]);
                 HIPCHECK(hipGetLastError());
@@ -765,7 +765,7 @@ void ensure_multi(nnca_h2 *H, int RP)
     for (int l = H->lmin; l <= H->kappa; l++) {
         const Level &L = H->lev[l];
         W.w[l] = dalloc<double>(L.npiv * RP);
-        if (l >= H->kappa - 1) W.w32[l] = dalloc<float>(L.npiv * RP);
+        if (l > H->kappa - H->fp32_levels) W.w32[l] = dalloc<float>(L.npiv * RP);
         W.u[l] = dalloc<double>(L.npiv * RP);
         part = std::max(part, (int64_t)parts_for(L) * L.npiv * RP);
     }

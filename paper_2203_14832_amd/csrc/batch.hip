@@ -274,7 +274,8 @@ nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags)
         }
         for (int32_t b = 0; b < count; b++) M->p2p_inter += hs[b]->p2p_inter;
         HIPCHECK(hipStreamSynchronize(s));
-        for (int l = 0; l <= M->kappa; l++) prepare_symmetric(M, M->lev[l], l <= M->kappa - 2);
+        M->fp32_levels = mixed_fp32_levels(M->kind);
+        for (int l = 0; l <= M->kappa; l++) prepare_symmetric(M, M->lev[l], l <= M->kappa - M->fp32_levels);
         HIPCHECK(hipStreamCreateWithFlags(&M->aux, hipStreamNonBlocking));
         HIPCHECK(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));

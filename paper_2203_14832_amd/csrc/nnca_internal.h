@@ -115,6 +115,7 @@ struct nnca_h2 {
     int64_t ws_budget = 0;
     int32_t rank_reserve = 256;
     int32_t apply_flags = 0;      // NNCA_APPLY_* bits
+    int32_t fp32_levels = 2;      // mixed matvec: finest levels whose transverse pass runs in FP32
     int32_t kmax = 20, kappa = 0, lmin = 1;
     double lo[3] = {0, 0, 0}, L = 0.0;
     hipStream_t stream = nullptr;
@@ -197,6 +198,7 @@ void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int6
 void free_multi(nnca_h2 *H);
 void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s);
 void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots);
+int mixed_fp32_levels(int kind);
 void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, double *y, hipStream_t s);
 // grad.hip
 void run_backward(nnca_h2 *H, const double *X, const double *G, int64_t nrhs, int64_t ldx, int64_t ldg,

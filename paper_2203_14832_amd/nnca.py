@@ -42,7 +42,8 @@ class Info(C.Structure):
                 ("nlist", (C.c_int64 * 2) * MAX_LEVELS), ("max_rank", C.c_int32 * MAX_LEVELS),
                 ("m2l_level", C.c_int64 * MAX_LEVELS),
                 ("transfer_entries", C.c_int64), ("m2l_interactions", C.c_int64),
-                ("p2p_interactions", C.c_int64), ("build_seconds", C.c_double)]
+                ("p2p_interactions", C.c_int64), ("build_seconds", C.c_double),
+                ("mixed_fp32_levels", C.c_int32)]
 
 
 _lib = None
@@ -243,7 +244,7 @@ class H2Matrix:
                     max_rank=[inf.max_rank[l] for l in range(L)], m2l_level=[inf.m2l_level[l] for l in range(L)],
                     transfer_entries=inf.transfer_entries,
                     m2l_interactions=inf.m2l_interactions, p2p_interactions=inf.p2p_interactions,
-                    build_seconds=inf.build_seconds)
+                    build_seconds=inf.build_seconds, mixed_fp32_levels=inf.mixed_fp32_levels)
 
     # parity exports -----------------------------------------------------
     def order(self):

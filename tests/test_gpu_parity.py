@@ -125,6 +125,9 @@ def test_matvec_parity(built, name):
     assert rel(Y64, Yo) <= 1e-12
     Ym = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
     print(name, "mixed vs fp64:", [rel(Ym[:, c], Y64[:, c]) for c in range(3)])
+    # FP32 transverse pass at the two finest levels for 1/r, the leaf level
+    # only for the kernels whose interpolation operators amplify more
+    assert G.info()["mixed_fp32_levels"] == (2 if kind == "inv_r" else 1)
     for c in range(3):
         assert rel(Ym[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c, rel(Ym[:, c], Y64[:, c]))
     # the plain (every ordered pair) FP32 transverse pass gives the same
