@@ -73,6 +73,7 @@ void nnca::destroy_handle(nnca_h2 *H)
     }
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+    if (H->ev_leafk) (void)hipEventDestroy(H->ev_leafk);
     for (auto &L : H->lev) {
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,

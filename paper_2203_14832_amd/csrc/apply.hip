@@ -391,7 +391,7 @@ __global__ void k_sum_parts(int64_t npiv, int P, const double *part, double *u)
 // relative accuracy to the rounding of the coordinates themselves).  The far
 // field and the partial results are added in FP64.
 template <typename T, int KIND>
-__global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, const int32_t *count,
+__global__ __launch_bounds__(NT) void k_p2p(int64_t c0, const int32_t *first, const int32_t *count,
                                             const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
                                             const int32_t *nbsum, const double *pts, int64_t n, int d,
                                             const T *xw, const T *xw2, const double *far,
@@ -405,7 +405,10 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t nc, const int32_t *first, co
     __shared__ double part[NT * RB], part2[NT * RB];
     __shared__ int32_t est[ET + 1], ebase[ET];
     const int t = threadIdx.x;
-    const int64_t c = blockIdx.x;
+    // leaf cell of this workgroup (launches may cover a range [c0, c1));
+    // every array is indexed by global cell number, also first[] of the
+    // neighbour cells below
+    const int64_t c = c0 + blockIdx.x;
     const int32_t kk = count[c], po = first[c], S = nbsum[c];
     const int32_t e0 = nb_ptr[c], e1 = nb_ptr[c + 1];
     const bool mixed = sizeof(T) == 4;
@@ -966,7 +969,8 @@ static int m2l_parts(const nnca::Level &L)
 }
 
 template <int MODE, typename C>
-static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C *pc, double prm, hipStream_t s)
+static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C *pc, double prm, hipStream_t s,
+                            hipEvent_t after = nullptr)
 {
     const int64_t nc = L.ncell;
     const int P = m2l_parts(L);
@@ -990,6 +994,7 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
 #undef M2L_CASE
 #undef M2L_ARGS
     HIPCHECK(hipGetLastError());
+    if (after) HIPCHECK(hipEventRecord(after, s));
     if (P > 1) {
         k_sum_parts<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, P, part, L.u64);
         HIPCHECK(hipGetLastError());
@@ -1039,8 +1044,11 @@ static void sym_launch(int32_t max_k, int g, const SymArgs &A, hipStream_t s)
     else k_m2l_sym<KIND, MODE, 2><<<g, NT, 0, s>>>(A);
 }
 
+// `after`, if given, is recorded on s right after the transverse kernel
+// (before its combine step).
 template <int MODE>
-static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level, double prm, hipStream_t s)
+static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level, double prm, hipStream_t s,
+                           hipEvent_t after = nullptr)
 {
     const int64_t nc = L.ncell;
     const int P = sym_parts(L);
@@ -1067,6 +1075,7 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
 #undef SYM_CASE
         HIPCHECK(hipGetLastError());
     }
+    if (after) HIPCHECK(hipEventRecord(after, s));
     Span sp(H, s, PASS_M2L_COMBINE, level);
     if (P > 1) {
         k_sum_parts<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, P, part, L.u64);
@@ -1081,13 +1090,16 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
     HIPCHECK(hipGetLastError());
 }
 
+// the near field of leaf cells [c0, c1)
 template <typename T>
 void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *far, double *y, T prm,
-                hipStream_t s)
+                hipStream_t s, int64_t c0 = 0, int64_t c1 = -1)
 {
     const nnca::Level &L = H->lev[H->kappa];
-    int64_t nc = L.ncell;
-#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(nc, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
+    if (c1 < 0) c1 = L.ncell;
+    const int64_t nc = c1 - c0;
+    if (nc <= 0) return;
+#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(c0, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
     if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
     else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
@@ -1118,17 +1130,23 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
     // With a far field, the near field runs on the handle's second stream
     // while the far-field passes run here (it reads only x and the points);
     // it writes the near-field sums to y, and the leaf-level L2P adds the far
-    // field to y after the join.
+    // field to y after the join.  It runs in two parts of equal work, both
+    // beside memory-bound passes: the first beside the upward pass, the
+    // second after the leaf level's transverse kernel, beside its combine
+    // step and the downward pass (the transverse kernels, bound by VALU
+    // issue, then have the chip to themselves).
     const bool overlap = do_p2p && kap >= lmin;
+    const int64_t ncl = H->lev[kap].ncell;
+    const int64_t csplit = H->p2p_split > 0 && H->p2p_split <= ncl ? H->p2p_split : ncl / 2;
+    auto near_part = [&](int64_t c0, int64_t c1) {
+        Span sp(H, H->aux, PASS_P2P, kap);
+        if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, y, prm, H->aux, c0, c1);
+        else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, y, prm, H->aux, c0, c1);
+    };
     if (overlap) {
         HIPCHECK(hipEventRecord(H->ev_fork, s));
         HIPCHECK(hipStreamWaitEvent(H->aux, H->ev_fork, 0));
-        {
-            Span sp(H, H->aux, PASS_P2P, kap);
-            if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, y, prm, H->aux);
-            else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, y, prm, H->aux);
-        }
-        HIPCHECK(hipEventRecord(H->ev_join, H->aux));
+        near_part(0, csplit);
     }
     if (kap >= lmin) {
         // upward pass
@@ -1155,15 +1173,21 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
             const bool sym = L.sym && !(H->apply_flags & NNCA_APPLY_NO_SYMMETRIC);
+            hipEvent_t after = overlap && l == kap ? H->ev_leafk : nullptr;
             if (f32 && sym) {   // the launcher times its kernel and its combine step apart
-                if (l <= lf64) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s);
-                else launch_m2l_sym<M_F32>(kind, H, L, l, (double)prm, s);
+                if (l <= lf64) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s, after);
+                else launch_m2l_sym<M_F32>(kind, H, L, l, (double)prm, s, after);
                 continue;
             }
             Span sp(H, s, PASS_M2L, l);
-            if (!f32) launch_m2l_mode<M_F64>(kind, H, L, L.pc64, prm64, s);
-            else if (l <= lf64) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s);
-            else launch_m2l_mode<M_F32>(kind, H, L, L.pc32, (double)prm, s);
+            if (!f32) launch_m2l_mode<M_F64>(kind, H, L, L.pc64, prm64, s, after);
+            else if (l <= lf64) launch_m2l_mode<M_F64R>(kind, H, L, L.pc64, prm64, s, after);
+            else launch_m2l_mode<M_F32>(kind, H, L, L.pc32, (double)prm, s, after);
+        }
+        if (overlap) {
+            HIPCHECK(hipStreamWaitEvent(H->aux, H->ev_leafk, 0));
+            near_part(csplit, ncl);
+            HIPCHECK(hipEventRecord(H->ev_join, H->aux));
         }
         // downward pass; with the near field overlapped, the leaf level adds
         // the far field to y (original order) after the join
@@ -1330,6 +1354,15 @@ void prepare_apply(nnca_h2 *H)
         p2p += (int64_t)hc[c] * nbs[c];
         H->max_leaf = std::max(H->max_leaf, hc[c]);
     }
+    // the near field runs in two parts of equal work (see one_column)
+    H->p2p_split = nc;
+    for (int64_t c = 0, acc = 0; c < nc; c++) {
+        acc += (int64_t)hc[c] * nbs[c];
+        if (2 * acc >= p2p) {
+            H->p2p_split = c + 1;
+            break;
+        }
+    }
     // the mixed matvec runs the finest levels in the FP32 form, the coarser
     // ones in the FP64-refined form
     H->fp32_levels = mixed_fp32_levels(H->kind);
@@ -1341,6 +1374,7 @@ void prepare_apply(nnca_h2 *H)
     HIPCHECK(hipStreamCreateWithFlags(&H->aux, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_leafk, hipEventDisableTiming));
     H->xs64 = dalloc<double>(H->n);
     H->far64 = dalloc<double>(H->n);
     H->xhi = dalloc<float>(H->n);

@@ -279,6 +279,7 @@ nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags)
         HIPCHECK(hipStreamCreateWithFlags(&M->aux, hipStreamNonBlocking));
         HIPCHECK(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&M->ev_leafk, hipEventDisableTiming));
         M->xs64 = dalloc<double>(N);
         M->far64 = dalloc<double>(N);
         M->xhi = dalloc<float>(N);

@@ -121,6 +121,7 @@ struct nnca_h2 {
     hipStream_t stream = nullptr;
     hipStream_t aux = nullptr;               // second stream of the matvec (near field)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_leafk = nullptr;           // after the leaf level's transverse kernel
     double build_seconds = 0.0;
 
     double *pts64 = nullptr;      // 3 x n, tree order
@@ -131,6 +132,7 @@ struct nnca_h2 {
     int32_t *nbpre = nullptr;     // leaf level: per N entry, sources before it
     int32_t *nbsum = nullptr;     // leaf level: near-field sources per cell
     int32_t max_leaf = 0;
+    int64_t p2p_split = 0;        // leaf cell where half of the near-field work is done
 
     // matvec workspace
     double *xs64 = nullptr, *far64 = nullptr;
