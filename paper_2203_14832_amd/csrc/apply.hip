@@ -692,7 +692,7 @@ struct SymShared {
         struct {
             T4 src[SYM_TS];
             int32_t sslot[SYM_TS];
-            float sn[SYM_TS];   // FP32 form: |s|^2 of the shifted source
+            typename SymT<MODE>::T sn[SYM_TS];   // |s|^2 of the (shifted) source
             typename SymT<MODE>::T scol[SYM_TS];   // column sums of the tile's sources
         } tile;
         double part[NT * 8];
@@ -711,11 +711,14 @@ struct SymShared {
 // rounds of G sources with zero-weight sources far from every target, so all
 // groups run the same number of steps.
 //
-// FP32 form: r^2 = |t|^2 + |s|^2 - 2 t.s, one addition and three FMAs per
-// pair with -2t and |t|^2 per target and |s|^2 per source (all in the
-// target cell's frame, where |t|, |s| are at most a few cell widths and an
-// admissible r is at least one, so the cancellation costs a few units in the
-// last place of r^2), against three differences, a product and two FMAs.
+// r^2 = |t|^2 + |s|^2 - 2 t.s: one addition and three FMAs per pair with -2t
+// and |t|^2 per target and |s|^2 per source, against three differences, a
+// product and two FMAs.  FP32 form: in the target cell's frame, where |t|,
+// |s| are at most a few cell widths and an admissible r is at least one, so
+// the cancellation costs a few units in the last place of r^2.  FP64-refined
+// form: absolute coordinates, (|t|^2 + |s|^2) / r^2 at most a few thousand
+// (a relative error of r^2 below 1e-12, far under the FP32 rounding of the
+// finer levels).
 template <int KIND, int MODE, int TPG, int R>
 __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int pp, int32_t kk)
 {
@@ -747,12 +750,10 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
         tz[r] = d == 3 ? pc[2 * npiv + q] : T(0);
         tw[r] = ok ? (T)A.w[q] : T(0);   // padding targets add nothing to column sums
         acc[r] = 0.0;
-        if constexpr (F32) {
-            tn[r] = tx[r] * tx[r] + ty[r] * ty[r] + tz[r] * tz[r];
-            tx[r] *= -2.f;
-            ty[r] *= -2.f;
-            tz[r] *= -2.f;
-        }
+        tn[r] = tx[r] * tx[r] + ty[r] * ty[r] + tz[r] * tz[r];
+        tx[r] *= T(-2);
+        ty[r] *= T(-2);
+        tz[r] *= T(-2);
     }
     const T prm = (T)A.prm;
     // first owned entry holding source sb
@@ -789,7 +790,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
             // contiguous sources per thread: one search, then a few steps
             T4 v[SPT];
             int32_t sl[SPT];
-            float sn[SPT];
+            T sn[SPT];
             const int32_t sfirst = s0 + t * SPT;
             // the last entry starting at or before sfirst: a fixed, branchless
             // search over the ET + 1 starts (est[0] <= sfirst for every source
@@ -806,7 +807,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                 if (s >= s0 + ns) {   // padding of a round: weight 0, far from every target
                     v[q].x = T(1e15); v[q].y = v[q].x; v[q].z = v[q].x; v[q].w = 0;
                     sl[q] = 0;
-                    sn[q] = 3e30f;
+                    sn[q] = T(3e30);
                 } else {
                     // 32-bit byte offsets from the arrays' bases (scalar registers)
                     const uint32_t idx = (uint32_t)(sh.ebase[lo] + s);
@@ -818,8 +819,8 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                         v[q].x += sh.esh[0][lo];
                         v[q].y += sh.esh[1][lo];
                         v[q].z += sh.esh[2][lo];
-                        sn[q] = (float)(v[q].x * v[q].x + v[q].y * v[q].y + v[q].z * v[q].z);
                     }
+                    sn[q] = v[q].x * v[q].x + v[q].y * v[q].y + v[q].z * v[q].z;
                     sl[q] = sh.eslot[lo] + s;
                 }
             }
@@ -829,7 +830,7 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                 const int32_t pos = t * SPT + q;
                 sh.u.tile.src[pos] = v[q];
                 sh.u.tile.sslot[pos] = sl[q];
-                if (F32) sh.u.tile.sn[pos] = sn[q];
+                sh.u.tile.sn[pos] = sn[q];
             }
             __syncthreads();
             T a[R];
@@ -840,21 +841,17 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                 const int32_t j = g + it * G;
                 const T4 q = sh.u.tile.src[j];
                 T qn = T(0);
-                if constexpr (F32) qn = sh.u.tile.sn[j];
+                qn = sh.u.tile.sn[j];
                 T cp = T(0);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     T kv_;
-                    if constexpr (F32) {
-                        T r2 = tn[r] + qn;
-                        r2 = fmaf(tz[r], q.z, r2);
-                        r2 = fmaf(ty[r], q.y, r2);
-                        r2 = fmaf(tx[r], q.x, r2);
-                        kv_ = kv32<KIND>(r2, prm);
-                    } else {
-                        const T dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
-                        kv_ = kv_refined<KIND, MODE>(dx * dx + dy * dy + dz * dz, prm);
-                    }
+                    T r2 = tn[r] + qn;
+                    r2 = fma(tz[r], q.z, r2);
+                    r2 = fma(ty[r], q.y, r2);
+                    r2 = fma(tx[r], q.x, r2);
+                    if constexpr (F32) kv_ = kv32<KIND>(r2, prm);
+                    else kv_ = kv_refined<KIND, MODE>(r2, prm);
                     a[r] += kv_ * q.w;
                     cp += kv_ * tw[r];
                 }
@@ -892,7 +889,8 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
 // largest shape in a kernel set its occupancy.  SET 0 (ranks <= 80): at most
 // five registers per lane (80 VGPRs, six waves per SIMD); SET 1 (<= 224): at
 // most seven (five waves); SET 2: SET 1 and eight registers per lane for
-// ranks above 224.
+// ranks above 224; SET 3 (the FP64-refined form up to rank 160): at most
+// five registers per lane, wider groups for the larger ranks.
 template <int KIND, int MODE, int SET>
 __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
 {
@@ -905,12 +903,17 @@ __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
     if (kk <= 8) sym_cell<KIND, MODE, 2, 4>(A, sh, c, pp, kk);
     else if (kk <= 16) sym_cell<KIND, MODE, 4, 4>(A, sh, c, pp, kk);
     else if (kk <= 20) sym_cell<KIND, MODE, 4, 5>(A, sh, c, pp, kk);
-    else if constexpr (SET == 0) {
+    else if constexpr (SET == 0 || SET == 3) {
         if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
         else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
         else if (kk <= 48) sym_cell<KIND, MODE, 16, 3>(A, sh, c, pp, kk);
         else if (kk <= 64) sym_cell<KIND, MODE, 16, 4>(A, sh, c, pp, kk);
-        else sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
+        else if (SET == 0 || kk <= 80) sym_cell<KIND, MODE, 16, 5>(A, sh, c, pp, kk);
+        else if constexpr (SET == 3) {
+            if (kk <= 96) sym_cell<KIND, MODE, 32, 3>(A, sh, c, pp, kk);
+            else if (kk <= 128) sym_cell<KIND, MODE, 32, 4>(A, sh, c, pp, kk);
+            else sym_cell<KIND, MODE, 32, 5>(A, sh, c, pp, kk);
+        }
     } else {
         if (kk <= 24) sym_cell<KIND, MODE, 4, 6>(A, sh, c, pp, kk);
         else if (kk <= 28) sym_cell<KIND, MODE, 4, 7>(A, sh, c, pp, kk);
@@ -1039,6 +1042,11 @@ static int sym_parts(const nnca::Level &L)
 template <int KIND, int MODE>
 static void sym_launch(int32_t max_k, int g, const SymArgs &A, hipStream_t s)
 {
+    if constexpr (MODE == M_F64R)
+        if (max_k > 80 && max_k <= 160) {
+            k_m2l_sym<KIND, MODE, 3><<<g, NT, 0, s>>>(A);
+            return;
+        }
     if (max_k <= 80) k_m2l_sym<KIND, MODE, 0><<<g, NT, 0, s>>>(A);
     else if (max_k <= 224) k_m2l_sym<KIND, MODE, 1><<<g, NT, 0, s>>>(A);
     else k_m2l_sym<KIND, MODE, 2><<<g, NT, 0, s>>>(A);
