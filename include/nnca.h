@@ -129,13 +129,15 @@ nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G
 
 /* Apply options of a handle, for the matvecs issued after the call.
  *   NNCA_APPLY_NO_SYMMETRIC: the mixed form evaluates the FP32 transverse
- *     blocks of its two finest levels for every ordered pair of interacting
- *     cells.  By default (flags = 0) it uses the symmetric case of Sec. 5:
- *     K(x, y) = K(y, x) and B' in IL(B) <=> B in IL(B') make the block of
- *     (B', B) the transpose of that of (B, B'), so each unordered pair is
- *     evaluated once and used for both directions.  The FP64 form always
- *     evaluates every ordered pair.  Either choice gives the product to the
- *     accuracy of the mixed form; summation orders differ.
+ *     blocks of its finest levels, and the near-field blocks, for every
+ *     ordered pair of cells.  By default (flags = 0) it uses the symmetric
+ *     case of Sec. 5: K(x, y) = K(y, x) and B' in IL(B) <=> B in IL(B')
+ *     (likewise for N(B)) make the block of (B', B) the transpose of that of
+ *     (B, B'), so each unordered pair is evaluated once and used for both
+ *     directions (the near field so only where near pairs exceed 1/12 of
+ *     the transverse interactions).  The FP64 form always evaluates every
+ *     ordered pair.  Either choice gives the product to the accuracy of the
+ *     mixed form; summation orders differ.
  * Errors: INVALID_ARG (NULL handle, unknown bits).                        */
 enum { NNCA_APPLY_NO_SYMMETRIC = 1 };
 nnca_status nnca_set_apply_flags(nnca_handle h, int32_t flags);

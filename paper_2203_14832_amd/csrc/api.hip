@@ -82,7 +82,10 @@ void nnca::destroy_handle(nnca_h2 *H)
                       L.own_slot, L.non_ptr, L.non_slot, L.col32, L.col64};
         for (void *p : ps) dfree(p);
     }
-    void *ps[] = {H->pts64, H->order, H->keys, H->nbpre, H->nbsum, H->xs64, H->far64, H->xhi, H->xlo, H->m2l_part};
+    void *ps[] = {H->pts64,    H->order,    H->keys,     H->nbpre,    H->nbsum,     H->xs64,
+                  H->far64,    H->xhi,      H->xlo,      H->m2l_part, H->pown_ptr,  H->pown_nb,
+                  H->pown_pre, H->pown_sum, H->pown_slot, H->pnon_ptr, H->pnon_slot, H->pcell,
+                  H->pcol_hi,  H->pcol_lo,  H->prow};
     for (void *p : ps) dfree(p);
     delete H;
 }

@@ -137,6 +137,16 @@ struct nnca_h2 {
     // matvec workspace
     double *xs64 = nullptr, *far64 = nullptr;
     float *xhi = nullptr, *xlo = nullptr;
+    // symmetric near field of the mixed matvec (leaf level): per cell the
+    // owned neighbour entries (cell, first source, column slot of source 0),
+    // the owned source count, the slots of the pairs owned by neighbours;
+    // FP32 column slots (x_hi and x_lo parts), FP64 row sums (2 x n), the
+    // leaf cell of every point
+    bool p2p_sym = false;
+    int32_t *pown_ptr = nullptr, *pown_nb = nullptr, *pown_pre = nullptr, *pown_sum = nullptr;
+    int32_t *pown_slot = nullptr, *pnon_ptr = nullptr, *pnon_slot = nullptr, *pcell = nullptr;
+    float *pcol_hi = nullptr, *pcol_lo = nullptr;
+    double *prow = nullptr;
     double *m2l_part = nullptr;   // partial M2L vectors of split launches
     int64_t m2l_part_cap = 0;
 
