@@ -208,6 +208,8 @@ typedef struct {
                                              transverse pass runs in FP32 (2 for
                                              1/r, 1 for the other kernels; the
                                              coarser ones in refined FP64)      */
+    int32_t mixed_near_symmetric;         /* 1: the mixed near field evaluates each
+                                             pair of neighbouring leaves once  */
 } nnca_info;
 
 /* Structure and statistics of a handle (blocking). */

@@ -352,6 +352,7 @@ nnca_status nnca_query(nnca_handle h, nnca_info *info)
         info->p2p_interactions = h->p2p_inter;
         info->build_seconds = h->build_seconds;
         info->mixed_fp32_levels = h->fp32_levels;
+        info->mixed_near_symmetric = h->p2p_sym ? 1 : 0;
     });
 }
 

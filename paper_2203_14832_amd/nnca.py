@@ -43,7 +43,7 @@ class Info(C.Structure):
                 ("m2l_level", C.c_int64 * MAX_LEVELS),
                 ("transfer_entries", C.c_int64), ("m2l_interactions", C.c_int64),
                 ("p2p_interactions", C.c_int64), ("build_seconds", C.c_double),
-                ("mixed_fp32_levels", C.c_int32)]
+                ("mixed_fp32_levels", C.c_int32), ("mixed_near_symmetric", C.c_int32)]
 
 
 _lib = None
@@ -174,7 +174,8 @@ class H2Matrix:
         return self._apply(X, precision, True)
 
     def set_symmetric(self, enable: bool = True):
-        """Use (default) or not the symmetric FP32 transverse pass of the mixed form."""
+        """Use (default) or not the symmetric evaluation (transverse pass and
+        near field) of the mixed form."""
         _check(lib().nnca_set_apply_flags(self._h, 0 if enable else 1))
 
     def backward(self, X, G, precision: str = "fp64", need_x: bool = True, need_h: bool = True):
@@ -244,7 +245,8 @@ class H2Matrix:
                     max_rank=[inf.max_rank[l] for l in range(L)], m2l_level=[inf.m2l_level[l] for l in range(L)],
                     transfer_entries=inf.transfer_entries,
                     m2l_interactions=inf.m2l_interactions, p2p_interactions=inf.p2p_interactions,
-                    build_seconds=inf.build_seconds, mixed_fp32_levels=inf.mixed_fp32_levels)
+                    build_seconds=inf.build_seconds, mixed_fp32_levels=inf.mixed_fp32_levels,
+                    mixed_near_symmetric=bool(inf.mixed_near_symmetric))
 
     # parity exports -----------------------------------------------------
     def order(self):

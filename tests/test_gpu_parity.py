@@ -126,12 +126,16 @@ def test_matvec_parity(built, name):
     Ym = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
     print(name, "mixed vs fp64:", [rel(Ym[:, c], Y64[:, c]) for c in range(3)])
     # FP32 transverse pass at the two finest levels for 1/r, the leaf level
-    # only for the kernels whose interpolation operators amplify more
-    assert G.info()["mixed_fp32_levels"] == (2 if kind == "inv_r" else 1)
+    # only for the kernels whose interpolation operators amplify more; the
+    # symmetric near field where near pairs exceed 1/12 of the transverse
+    # interactions (all of these small problems)
+    inf = G.info()
+    assert inf["mixed_fp32_levels"] == (2 if kind == "inv_r" else 1)
+    assert inf["mixed_near_symmetric"] == (12 * inf["p2p_interactions"] > inf["m2l_interactions"])
     for c in range(3):
         assert rel(Ym[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c, rel(Ym[:, c], Y64[:, c]))
-    # the plain (every ordered pair) FP32 transverse pass gives the same
-    # product to the same bound; the symmetric one is the default
+    # the plain (every ordered pair) FP32 transverse pass and near field give
+    # the same product to the same bound; the symmetric ones are the default
     G.set_symmetric(False)
     try:
         Yp = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
@@ -144,6 +148,26 @@ def test_matvec_parity(built, name):
     Ya = G.rmatvec(Xt, "fp64").cpu().numpy()
     lhs, rhs = X[:, 0] @ Ya[:, 1], Y64[:, 0] @ X[:, 1]
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(X[:, 0]) * np.linalg.norm(Y64[:, 1])
+
+
+def test_symmetric_near_field(built):
+    # at least one of the parity problems runs the symmetric near field; its
+    # mixed product equals the plain one (every ordered near pair) to the
+    # mixed bound and the FP64 product to the same bound
+    used = [nm for nm in CASES if built(nm)[1].info()["mixed_near_symmetric"]]
+    assert used, "no parity problem exercises the symmetric near field"
+    for nm in used:
+        p, G, T, O, kind, h = built(nm)
+        x = torch.tensor(np.random.default_rng(21).standard_normal(p.shape[0]), device="cuda")
+        y64 = G.matvec(x, "fp64").cpu().numpy()
+        ys = G.matvec(x, "mixed").cpu().numpy()
+        G.set_symmetric(False)
+        try:
+            yp = G.matvec(x, "mixed").cpu().numpy()
+        finally:
+            G.set_symmetric(True)
+        tol = MIXED_TOL.get(nm, 1e-6)
+        assert rel(ys, y64) <= tol and rel(yp, y64) <= tol and rel(ys, yp) <= tol, nm
 
 
 @pytest.mark.parametrize("kind,d,h", [("inv_r", 3, 1.0), ("log_r", 2, 1.0), ("gauss", 3, 0.6)])
