@@ -904,7 +904,8 @@ __global__ __launch_bounds__(NT) void k_m2l_sym(SymArgs A)
     else if (kk <= 16) sym_cell<KIND, MODE, 4, 4>(A, sh, c, pp, kk);
     else if (kk <= 20) sym_cell<KIND, MODE, 4, 5>(A, sh, c, pp, kk);
     else if constexpr (SET == 0 || SET == 3) {
-        if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
+        if (kk <= 24) sym_cell<KIND, MODE, 8, 3>(A, sh, c, pp, kk);
+        else if (kk <= 32) sym_cell<KIND, MODE, 8, 4>(A, sh, c, pp, kk);
         else if (kk <= 40) sym_cell<KIND, MODE, 8, 5>(A, sh, c, pp, kk);
         else if (kk <= 48) sym_cell<KIND, MODE, 16, 3>(A, sh, c, pp, kk);
         else if (kk <= 64) sym_cell<KIND, MODE, 16, 4>(A, sh, c, pp, kk);
