@@ -1417,7 +1417,10 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             nnca::Level &L = H->lev[l];
             const double *src = (l == kap) ? xs64 : H->lev[l + 1].w64;
             Span sp(H, s, PASS_UP, l);
-            if (L.nrem == 0)
+            // one thread per output entry where cells have few non-pivot
+            // rows (the leaf level: at most the leaf size, most leaves full
+            // rank); a workgroup per cell (column slices) above
+            if (L.nrem == 0 || l == kap)
                 k_up<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, L.piv_cell, L.piv_ptr, L.tt_off, L.ipos,
                                                            L.rem_ptr, L.rem_pos, L.crem_off, L.crem64, src, L.w64);
             else {
