@@ -156,16 +156,15 @@ __global__ void k_down(int64_t npiv, int64_t nrem, const int32_t *piv_cell, cons
     int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro, r = (int32_t)g - ro;
     const double *Ct = crem_t + crem_off[c] + r;
     const double *ub = u + po;
-    double acc = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // eight independent partial sums keep eight loads in flight
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int32_t q = 0;
-    for (; q + 3 < kk; q += 4) {
-        acc += Ct[(int64_t)q * nr] * ub[q];
-        a1 += Ct[(int64_t)(q + 1) * nr] * ub[q + 1];
-        a2 += Ct[(int64_t)(q + 2) * nr] * ub[q + 2];
-        a3 += Ct[(int64_t)(q + 3) * nr] * ub[q + 3];
+    for (; q + 7 < kk; q += 8) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) a[i] += Ct[(int64_t)(q + i) * nr] * ub[q + i];
     }
-    for (; q < kk; q++) acc += Ct[(int64_t)q * nr] * ub[q];
-    acc += (a1 + a2) + a3;
+    for (; q < kk; q++) a[0] += Ct[(int64_t)q * nr] * ub[q];
+    double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     int32_t dst = tt_off[c] + rem_pos[g];
     if (order) dst = order[dst];
     out[dst] = accumulate ? out[dst] + acc : acc;
