@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H2 matvecs/s at N=1M 3D 1/r, mixed vs FP64 at rel.err≤1e-6; % roofline"
 # Roofline of the dominant kernel, the symmetric FP32 transverse pass (M2L)
-# of the two finest levels.  Its bound is plain VALU arithmetic.  Peak FP32
+# of the two finest levels (1/r).  Its bound is plain VALU arithmetic.  Peak FP32
 # vector rate of the chip: 157.3 TFLOP/s = 256 CU x 128 lanes/clock x
 # 2.4 GHz x 2 (FMA), i.e. 7.864e13 lane-instructions/s.  One unordered pair
 # of pivots costs 1 addition and 3 FMA for r^2 = |t|^2 + |s|^2 - 2 t.s, one

@@ -3,7 +3,8 @@
 // innermost and padded to RP = 16 * NCB columns, so one source row of weights
 // is contiguous.
 //
-// Transverse pass, mixed precision, two finest levels: the kernel tile
+// Transverse pass, mixed precision, finest levels (two for 1/r, one for the
+// other kernels, as for one column): the kernel tile
 // K(t^{B,i}, sources) is generated in FP32 on the vector ALUs, one entry per
 // lane in the A-operand layout of v_mfma_f32_16x16x4f32, and multiplied by the
 // weight tile (4 sources x 16 columns) on the matrix cores, R/16 products per
