@@ -151,9 +151,11 @@ __global__ void k_to_f32(int64_t cnt, const double *a, float *b)
 // blocks of 16 targets (TB = 2 for up to 32 columns: one source step then
 // feeds two kernel values per lane into two matrix products that share the
 // weight operand), or, with fewer than four units, a phase of the 4-source
-// steps of one unit.
+// steps of one unit.  With one column block the kernel fits six waves per
+// SIMD in 80 registers (the matrix products then accumulate in ordinary
+// vector registers).
 template <int KIND, int NCB>
-__global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 1))) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                  const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                  const int32_t *ilsum, const float *pc, int64_t npiv,
                                                  const int32_t *coord, const float *hc, float h0, int d,
@@ -254,47 +256,44 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma(int64_t nc, int P, const int32_
                     for (int q = 0; q < RP / 4; q++) wd[q] = 4 * q < R ? wr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 __syncthreads();
-                if (wact) {
-                    int steps = 0;
-                    for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
-                        const int32_t src = s4 + (lane >> 4);
-                        const int32_t srcc = src < ns ? src : ns - 1;
-                        const float4 q = sx[srcc];
-                        float kvv[TB];
+                // groups of four steps: the FP32 accumulators stay in the
+                // matrix-core registers across a group and are added into
+                // the FP64 sums once per group (steps past the tile add zero)
+                if (wact)
+                    for (int32_t g0 = ph * 4; g0 < ns; g0 += 16 * nph) {
 #pragma unroll
-                        for (int j = 0; j < TB; j++) {
-                            float r2 = tn[j] + q.w;
-                            r2 = fmaf(tz[j], q.z, r2);
-                            r2 = fmaf(ty[j], q.y, r2);
-                            r2 = fmaf(tx[j], q.x, r2);
-                            kvv[j] = src < ns ? kv32<KIND>(r2, prm) : 0.f;
+                        for (int k = 0; k < 4; k++) {
+                            const int32_t src = g0 + k * 4 * nph + (lane >> 4);
+                            const int32_t srcc = src < ns ? src : ns - 1;
+                            const float4 q = sx[srcc];
+                            float kvv[TB];
+#pragma unroll
+                            for (int j = 0; j < TB; j++) {
+                                float r2 = tn[j] + q.w;
+                                r2 = fmaf(tz[j], q.z, r2);
+                                r2 = fmaf(ty[j], q.y, r2);
+                                r2 = fmaf(tx[j], q.x, r2);
+                                kvv[j] = src < ns ? kv32<KIND>(r2, prm) : 0.f;
+                            }
+#pragma unroll
+                            for (int b = 0; b < NCB; b++) {
+                                const float bw = swt[srcc * SW + b * 16 + (lane & 15)];
+#pragma unroll
+                                for (int j = 0; j < TB; j++)
+                                    accf[j][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv[j], bw, accf[j][b], 0, 0, 0);
+                            }
                         }
 #pragma unroll
-                        for (int b = 0; b < NCB; b++) {
-                            const float bw = swt[srcc * SW + b * 16 + (lane & 15)];
+                        for (int j = 0; j < TB; j++)
 #pragma unroll
-                            for (int j = 0; j < TB; j++)
-                                accf[j][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv[j], bw, accf[j][b], 0, 0, 0);
-                        }
-                        if (++steps == 4) {
-                            steps = 0;
+                            for (int b = 0; b < NCB; b++) {
 #pragma unroll
-                            for (int j = 0; j < TB; j++)
-#pragma unroll
-                                for (int b = 0; b < NCB; b++) {
-                                    for (int i = 0; i < 4; i++) accd[j][b][i] += (double)accf[j][b][i];
-                                    accf[j][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-                                }
-                        }
+                                for (int i = 0; i < 4; i++) accd[j][b][i] += (double)accf[j][b][i];
+                                accf[j][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                            }
                     }
-                }
             }
         }
-#pragma unroll
-        for (int j = 0; j < TB; j++)
-#pragma unroll
-            for (int b = 0; b < NCB; b++)
-                for (int i = 0; i < 4; i++) accd[j][b][i] += (double)accf[j][b][i];
         // phases of the same unit are added in order ph = 0, 1, ...
         __syncthreads();
         if (nph > 1 && wact)
