@@ -155,7 +155,7 @@ __global__ void k_to_f32(int64_t cnt, const double *a, float *b)
 // SIMD in 80 registers (the matrix products then accumulate in ordinary
 // vector registers).
 template <int KIND, int NCB>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 1))) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 2))) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                  const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                  const int32_t *ilsum, const float *pc, int64_t npiv,
                                                  const int32_t *coord, const float *hc, float h0, int d,
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
 // row 4 i + l / 16, column l % 16.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 template <int KIND, int MODE, int NCB>
-__global__ __launch_bounds__(NT) void k_m2l_mfma64(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_m2l_mfma64(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                    const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                    const int32_t *ilsum, const double *pc, int64_t npiv, int d,
                                                    const double *w, int R, double *u, double *part_out, double prm)
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_m2l_mfma64(int64_t nc, int P, const int3
 // v_mfma_f32_16x16x4f32 (partial sums folded into FP64 every 16 sources);
 // T = double uses v_mfma_f64_16x16x4f64.
 template <typename T, int KIND, int NCB>
-__global__ __launch_bounds__(NT) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
                                                  const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
                                                  const int32_t *nbsum, const double *pts, int64_t n, int d,
                                                  const T *xw, const T *xw2, const double *far,
@@ -481,49 +481,50 @@ __global__ __launch_bounds__(NT) void k_p2p_mfma(int64_t nc, const int32_t *firs
                 }
             }
             __syncthreads();
-            if (wact) {
-                int steps = 0;
-                for (int32_t s4 = ph * 4; s4 < ns; s4 += 4 * nph) {
-                    int32_t src = s4 + (lane >> 4);
-                    T kvv = T(0);
-                    int32_t srcc = src < ns ? src : ns - 1;
-                    if (src < ns) {
-                        double4 q = sx[src];
-                        T dx = (T)(tx - q.x), dy = (T)(ty - q.y), dz = (T)(tz - q.z);
-                        kvv = kv_self<KIND, T>(dx * dx + dy * dy + dz * dz, prm);
+            // groups of four steps; the FP32 form adds its partial sums
+            // into FP64 once per group (steps past the tile add zero)
+            if (wact)
+                for (int32_t g0 = ph * 4; g0 < ns; g0 += 16 * nph) {
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const int32_t src = g0 + k * 4 * nph + (lane >> 4);
+                        T kvv = T(0);
+                        const int32_t srcc = src < ns ? src : ns - 1;
+                        if (src < ns) {
+                            double4 q = sx[src];
+                            T dx = (T)(tx - q.x), dy = (T)(ty - q.y), dz = (T)(tz - q.z);
+                            kvv = kv_self<KIND, T>(dx * dx + dy * dy + dz * dz, prm);
+                        }
+#pragma unroll
+                        for (int b = 0; b < NCB; b++) {
+                            if constexpr (mixed) {
+                                af[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt[srcc * SW + b * 16 + (lane & 15)],
+                                                                             af[b], 0, 0, 0);
+                                af2[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt2[srcc * SW + b * 16 + (lane & 15)],
+                                                                              af2[b], 0, 0, 0);
+                            } else {
+                                ad[b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kvv,
+                                                                             (double)swt[srcc * SW + b * 16 + (lane & 15)],
+                                                                             ad[b], 0, 0, 0);
+                            }
+                        }
                     }
                     if constexpr (mixed) {
 #pragma unroll
                         for (int b = 0; b < NCB; b++) {
-                            af[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt[srcc * SW + b * 16 + (lane & 15)],
-                                                                         af[b], 0, 0, 0);
-                            af2[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt2[srcc * SW + b * 16 + (lane & 15)],
-                                                                          af2[b], 0, 0, 0);
-                        }
-                        if (++steps == 4) {
-                            steps = 0;
 #pragma unroll
-                            for (int b = 0; b < NCB; b++) {
-                                for (int i = 0; i < 4; i++) accd[b][i] += (double)af[b][i] + (double)af2[b][i];
-                                af[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-                                af2[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-                            }
+                            for (int i = 0; i < 4; i++) accd[b][i] += (double)af[b][i] + (double)af2[b][i];
+                            af[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                            af2[b] = floatx4{0.f, 0.f, 0.f, 0.f};
                         }
-                    } else {
-#pragma unroll
-                        for (int b = 0; b < NCB; b++)
-                            ad[b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kvv,
-                                                                         (double)swt[srcc * SW + b * 16 + (lane & 15)],
-                                                                         ad[b], 0, 0, 0);
                     }
                 }
-            }
         }
         // result rows of this lane: FP32 layout row 4 (l/16) + i, FP64 layout row 4 i + l/16
+        if constexpr (!mixed)
 #pragma unroll
-        for (int b = 0; b < NCB; b++)
-            for (int i = 0; i < 4; i++)
-                accd[b][i] += mixed ? (double)af[b][i] + (double)af2[b][i] : (double)ad[b][i];
+            for (int b = 0; b < NCB; b++)
+                for (int i = 0; i < 4; i++) accd[b][i] = ad[b][i];
         __syncthreads();
         if (nph > 1 && wact)
             for (int b = 0; b < NCB; b++)
