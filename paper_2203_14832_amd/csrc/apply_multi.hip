@@ -164,6 +164,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
     constexpr int RP = NCB * 16;
     constexpr int TB = NCB <= 2 ? 2 : 1;             // target blocks per wavefront
     constexpr int TS = NCB == 1 ? 256 : 128;         // sources per LDS tile
+    static_assert(TS % 64 == 0 && TS <= NT, "the tile pads to a multiple of 64 sources, one per thread");
     constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
     constexpr int RED = NT * NCB * 4 * TB;           // doubles of the phase reduction
     __shared__ float4 sx[TS];
@@ -254,18 +255,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
                     float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
 #pragma unroll
                     for (int q = 0; q < RP / 4; q++) wd[q] = 4 * q < R ? wr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                } else if (t < ((ns + 63) & ~63)) {
+                    // padding up to a multiple of 64 sources (TS is one): far
+                    // from every target, zero weights, so it adds exact zeros
+                    sx[t] = make_float4(1e15f, 1e15f, 1e15f, 3e30f);
+                    float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
+#pragma unroll
+                    for (int q = 0; q < RP / 4; q++) wd[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 __syncthreads();
                 // groups of four steps: the FP32 accumulators stay in the
                 // matrix-core registers across a group and are added into
-                // the FP64 sums once per group (steps past the tile add zero)
+                // the FP64 sums once per group.  A group of phase ph reads
+                // sources below (g0 / (16 nph) + 1) 16 nph <= the padded
+                // tile end, since 16 nph divides 64.
                 if (wact)
                     for (int32_t g0 = ph * 4; g0 < ns; g0 += 16 * nph) {
 #pragma unroll
                         for (int k = 0; k < 4; k++) {
                             const int32_t src = g0 + k * 4 * nph + (lane >> 4);
-                            const int32_t srcc = src < ns ? src : ns - 1;
-                            const float4 q = sx[srcc];
+                            const float4 q = sx[src];
                             float kvv[TB];
 #pragma unroll
                             for (int j = 0; j < TB; j++) {
@@ -273,11 +282,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
                                 r2 = fmaf(tz[j], q.z, r2);
                                 r2 = fmaf(ty[j], q.y, r2);
                                 r2 = fmaf(tx[j], q.x, r2);
-                                kvv[j] = src < ns ? kv32<KIND>(r2, prm) : 0.f;
+                                kvv[j] = kv32<KIND>(r2, prm);
                             }
 #pragma unroll
                             for (int b = 0; b < NCB; b++) {
-                                const float bw = swt[srcc * SW + b * 16 + (lane & 15)];
+                                const float bw = swt[src * SW + b * 16 + (lane & 15)];
 #pragma unroll
                                 for (int j = 0; j < TB; j++)
                                     accf[j][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv[j], bw, accf[j][b], 0, 0, 0);
@@ -416,7 +425,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // v_mfma_f32_16x16x4f32 (partial sums folded into FP64 every 16 sources);
 // T = double uses v_mfma_f64_16x16x4f64.
 template <typename T, int KIND, int NCB>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 2))) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
                                                  const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
                                                  const int32_t *nbsum, const double *pts, int64_t n, int d,
                                                  const T *xw, const T *xw2, const double *far,
@@ -425,6 +434,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     constexpr int RP = NCB * 16;
     constexpr int TS = 64;
     constexpr bool mixed = sizeof(T) == 4;
+    static_assert(TS == 64 && TS <= NT, "every step index stays inside one 64-source tile");
     constexpr int SW = (mixed && !(NCB & 1)) ? RP + 16 : RP;   // LDS row stride (bank spread)
     __shared__ double4 sx[TS];
     __shared__ __align__(16) T swt[TS * SW];
@@ -479,32 +489,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
                     for (int q = 0; q < RP / 2; q++) da[q] = 2 * q < R ? a[q] : make_double2(0.0, 0.0);
                 }
+            } else if (t < TS) {
+                // padding of the tile: far from every target, zero weights
+                sx[t] = make_double4(1e15, 1e15, 1e15, 0.0);
+#pragma unroll
+                for (int q = 0; q < RP; q++) {
+                    swt[t * SW + q] = T(0);
+                    if constexpr (mixed) swt2[t * SW + q] = T(0);
+                }
             }
             __syncthreads();
             // groups of four steps; the FP32 form adds its partial sums
-            // into FP64 once per group (steps past the tile add zero)
+            // into FP64 once per group.  Every source index stays below TS
+            // (a multiple of 16 nph); the padding adds exact zeros.
             if (wact)
                 for (int32_t g0 = ph * 4; g0 < ns; g0 += 16 * nph) {
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
                         const int32_t src = g0 + k * 4 * nph + (lane >> 4);
-                        T kvv = T(0);
-                        const int32_t srcc = src < ns ? src : ns - 1;
-                        if (src < ns) {
-                            double4 q = sx[src];
-                            T dx = (T)(tx - q.x), dy = (T)(ty - q.y), dz = (T)(tz - q.z);
-                            kvv = kv_self<KIND, T>(dx * dx + dy * dy + dz * dz, prm);
-                        }
+                        const double4 q = sx[src];
+                        const T dx = (T)(tx - q.x), dy = (T)(ty - q.y), dz = (T)(tz - q.z);
+                        const T kvv = kv_self<KIND, T>(dx * dx + dy * dy + dz * dz, prm);
 #pragma unroll
                         for (int b = 0; b < NCB; b++) {
                             if constexpr (mixed) {
-                                af[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt[srcc * SW + b * 16 + (lane & 15)],
+                                af[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt[src * SW + b * 16 + (lane & 15)],
                                                                              af[b], 0, 0, 0);
-                                af2[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt2[srcc * SW + b * 16 + (lane & 15)],
+                                af2[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(kvv, swt2[src * SW + b * 16 + (lane & 15)],
                                                                               af2[b], 0, 0, 0);
                             } else {
                                 ad[b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kvv,
-                                                                             (double)swt[srcc * SW + b * 16 + (lane & 15)],
+                                                                             (double)swt[src * SW + b * 16 + (lane & 15)],
                                                                              ad[b], 0, 0, 0);
                             }
                         }
