@@ -42,87 +42,112 @@ __global__ void k_gather_multi(int64_t n, int R, int RP, const int32_t *order, c
     }
 }
 
-// upward pass for RP columns: w = C_B^T x~, one workgroup per cell; the rows
-// of x~ that are not pivots are staged in LDS 32 at a time
-constexpr int XT = 32;
-__global__ __launch_bounds__(NT) void k_up_multi(int RP, const int32_t *piv_ptr, const int32_t *tt_off,
+// Transfer passes for RP columns (Sec. 4).  One wavefront per (cell, 64 rows,
+// 16 columns): every lane keeps the 16 sums of its row in registers, the
+// matrix entries of the wave's 64 rows are contiguous in memory, and the
+// vector entry each step multiplies is the same for the whole wave (one
+// address).  The flat grid numbers the items of a cell consecutively, so the
+// column blocks of one cell re-read its matrix block from the cache.
+
+// upward pass: w_q = x~(ipos_q) + sum_r C(r, q) x~(rem_pos_r) over the rows of
+// t~ that are not pivots (C holds those rows of C_B, (m - k) x k row-major)
+__global__ __launch_bounds__(64) void k_up_multi(int ipc, int RP, const int32_t *piv_ptr, const int32_t *tt_off,
                                                  const int32_t *ipos, const int32_t *rem_ptr, const int32_t *rem_pos,
-                                                 const int64_t *crem_off, const double *crem, const double *xin,
-                                                 double *w)
+                                                 const int64_t *crem_off, const double *__restrict__ crem,
+                                                 const double *__restrict__ xin, double *__restrict__ w)
 {
-    __shared__ double xr[XT * 64];
-    const int64_t c = blockIdx.x;
-    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
-    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
-    const double *C = crem + crem_off[c];
-    for (int32_t e0 = blockIdx.y * NT; e0 < kk * RP; e0 += NT * gridDim.y) {
-        const int32_t e = e0 + threadIdx.x;
-        const bool act = e < kk * RP;
-        const int32_t q = act ? e / RP : 0, col = e % RP;
-        double acc = act ? xin[(int64_t)(to + ipos[po + q]) * RP + col] : 0.0;
-        double a1 = 0.0;
-        for (int32_t r0 = 0; r0 < nr; r0 += XT) {
-            const int32_t rn = nr - r0 < XT ? nr - r0 : XT;
-            __syncthreads();
-            for (int32_t i = threadIdx.x; i < rn * RP; i += NT)
-                xr[i] = xin[(int64_t)(to + rem_pos[ro + r0 + i / RP]) * RP + i % RP];
-            __syncthreads();
-            if (act) {
-                const double *Cq = C + (int64_t)r0 * kk + q;
-                int32_t r = 0;
-                for (; r + 1 < rn; r += 2) {
-                    acc += Cq[(int64_t)r * kk] * xr[r * RP + col];
-                    a1 += Cq[(int64_t)(r + 1) * kk] * xr[(r + 1) * RP + col];
-                }
-                if (r < rn) acc += Cq[(int64_t)r * kk] * xr[r * RP + col];
-            }
+    const int64_t c = blockIdx.x / ipc;
+    const int item = (int)(blockIdx.x % ipc), ncb = RP / 16;
+    const int32_t qc = item / ncb, cb = item % ncb;
+    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po;
+    if (qc * 64 >= kk) return;   // uniform for the wavefront
+    const int32_t to = tt_off[c], ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    const int32_t q = qc * 64 + (int32_t)threadIdx.x, qs = q < kk ? q : kk - 1;
+    const double *xb = xin + cb * 16;
+    double acc[16];
+    {
+        const double2 *xp = reinterpret_cast<const double2 *>(xb + (int64_t)(to + ipos[po + qs]) * RP);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const double2 v = xp[j];
+            acc[2 * j] = v.x;
+            acc[2 * j + 1] = v.y;
         }
-        if (act) w[(int64_t)(po + q) * RP + col] = acc + a1;
+    }
+    const double *Cq = crem + crem_off[c] + qs;
+#pragma unroll 2
+    for (int32_t r = 0; r < nr; r++) {
+        const double cv = Cq[(int64_t)r * kk];
+        const double *xr = xb + (int64_t)(to + rem_pos[ro + r]) * RP;
+#pragma unroll
+        for (int j = 0; j < 16; j++) acc[j] = fma(cv, xr[j], acc[j]);
+    }
+    if (q < kk) {
+        double2 *wp = reinterpret_cast<double2 *>(w + (int64_t)(po + q) * RP + cb * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) wp[j] = make_double2(acc[2 * j], acc[2 * j + 1]);
     }
 }
 
-// downward pass for RP columns: the stacked C_B u added to the children (L2L)
-// or written as the far field of the leaf's points (L2P); u staged in LDS
-__global__ __launch_bounds__(NT) void k_down_multi(int RP, const int32_t *piv_ptr, const int32_t *tt_off,
-                                                   const int32_t *ipos, const int32_t *rem_ptr,
+// downward pass: the stacked C_B u added to the children (L2L) or written as
+// the far field of the leaf's points (L2P).  Items [0, nqc * ncb) of a cell
+// copy u to the pivot rows of t~; the others form sum_q C(r, q) u_q for the
+// other rows from the transposed blocks (crem_t, k x (m - k) row-major).
+__global__ __launch_bounds__(64) void k_down_multi(int ipc, int nqc, int RP, const int32_t *piv_ptr,
+                                                   const int32_t *tt_off, const int32_t *ipos, const int32_t *rem_ptr,
                                                    const int32_t *rem_pos, const int64_t *crem_off,
-                                                   const double *crem, const double *u, double *out, int accumulate)
+                                                   const double *__restrict__ crem_t, const double *__restrict__ u,
+                                                   double *__restrict__ out, int accumulate)
 {
-    __shared__ double ur[XT * 64];
-    const int64_t c = blockIdx.x;
+    const int64_t c = blockIdx.x / ipc;
+    int item = (int)(blockIdx.x % ipc);
+    const int ncb = RP / 16, lane = threadIdx.x;
     const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
-    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
-    const double *C = crem + crem_off[c];
-    for (int32_t e = blockIdx.y * NT + threadIdx.x; e < kk * RP; e += NT * gridDim.y) {
-        int32_t q = e / RP, col = e % RP;
-        int64_t dst = (int64_t)(to + ipos[po + q]) * RP + col;
-        double v = u[(int64_t)(po + q) * RP + col];
-        out[dst] = accumulate ? out[dst] + v : v;
-    }
-    for (int32_t e0 = blockIdx.y * NT; e0 < nr * RP; e0 += NT * gridDim.y) {
-        const int32_t e = e0 + threadIdx.x;
-        const bool act = e < nr * RP;
-        const int32_t r = act ? e / RP : 0, col = e % RP;
-        const double *row = C + (int64_t)r * kk;
-        double acc = 0.0, a1 = 0.0;
-        for (int32_t q0 = 0; q0 < kk; q0 += XT) {
-            const int32_t qn = kk - q0 < XT ? kk - q0 : XT;
-            __syncthreads();
-            for (int32_t i = threadIdx.x; i < qn * RP; i += NT) ur[i] = u[(int64_t)(po + q0) * RP + i];
-            __syncthreads();
-            if (act) {
-                int32_t q = 0;
-                for (; q + 1 < qn; q += 2) {
-                    acc += row[q0 + q] * ur[q * RP + col];
-                    a1 += row[q0 + q + 1] * ur[(q + 1) * RP + col];
-                }
-                if (q < qn) acc += row[q0 + q] * ur[q * RP + col];
+    if (item < nqc * ncb) {
+        const int32_t qc = item / ncb, cb = item % ncb, q = qc * 64 + lane;
+        if (q >= kk) return;
+        const double2 *up = reinterpret_cast<const double2 *>(u + (int64_t)(po + q) * RP + cb * 16);
+        double2 *op = reinterpret_cast<double2 *>(out + (int64_t)(to + ipos[po + q]) * RP + cb * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            double2 v = up[j];
+            if (accumulate) {
+                const double2 o = op[j];
+                v.x += o.x;
+                v.y += o.y;
             }
+            op[j] = v;
         }
-        if (act) {
-            acc += a1;
-            int64_t dst = (int64_t)(to + rem_pos[ro + r]) * RP + col;
-            out[dst] = accumulate ? out[dst] + acc : acc;
+        return;
+    }
+    item -= nqc * ncb;
+    const int32_t rc = item / ncb, cb = item % ncb;
+    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    if (rc * 64 >= nr) return;   // uniform for the wavefront
+    const int32_t r = rc * 64 + lane, rs = r < nr ? r : nr - 1;
+    const double *Ct = crem_t + crem_off[c] + rs;
+    const double *ub = u + (int64_t)po * RP + cb * 16;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = 0.0;
+#pragma unroll 2
+    for (int32_t q = 0; q < kk; q++) {
+        const double cv = Ct[(int64_t)q * nr];
+        const double *uq = ub + (int64_t)q * RP;
+#pragma unroll
+        for (int j = 0; j < 16; j++) acc[j] = fma(cv, uq[j], acc[j]);
+    }
+    if (r < nr) {
+        double2 *op = reinterpret_cast<double2 *>(out + (int64_t)(to + rem_pos[ro + r]) * RP + cb * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            double2 v = make_double2(acc[2 * j], acc[2 * j + 1]);
+            if (accumulate) {
+                const double2 o = op[j];
+                v.x += o.x;
+                v.y += o.y;
+            }
+            op[j] = v;
         }
     }
 }
@@ -704,11 +729,6 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     const bool mixed = precision == NNCA_PREC_MIXED;
     const int kind = H->kind;
     auto &W = H->multi;
-    // 256-element output chunks of the widest cell, at most 64
-    auto chunks = [](int32_t rows) {
-        int64_t ch = ((int64_t)rows * RP + NT - 1) / NT;
-        return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ch, 64));
-    };
     k_gather_multi<<<grid_for(n * RP, 256), 256, 0, s>>>(n, R, RP, H->order, X, ldx, W.xs, mixed ? W.xhi : nullptr,
                                                          mixed ? W.xlo : nullptr);
     HIPCHECK(hipGetLastError());
@@ -719,8 +739,9 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
         for (int l = kap; l >= lmin; l--) {
             Level &L = H->lev[l];
             const double *src = l == kap ? W.xs : W.w[l + 1];
-            k_up_multi<<<dim3((unsigned)L.ncell, chunks(L.max_k)), NT, 0, s>>>(RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off,
-                                                  L.crem64, src, W.w[l]);
+            const int ipc = (int)((L.max_k + 63) / 64) * NCB;
+            k_up_multi<<<(unsigned)(L.ncell * ipc), 64, 0, s>>>(ipc, RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr,
+                                                                L.rem_pos, L.crem_off, L.crem64, src, W.w[l]);
             HIPCHECK(hipGetLastError());
         }
         // FP32 copies of the multipole vectors the FP32 transverse pass reads
@@ -744,8 +765,11 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
         for (int l = lmin; l <= kap; l++) {
             Level &L = H->lev[l];
             double *out = l == kap ? far : W.u[l + 1];
-            k_down_multi<<<dim3((unsigned)L.ncell, chunks(std::max(L.max_k, L.max_nrem))), NT, 0, s>>>(RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
-                                                    L.crem_off, L.crem64, W.u[l], out, l == kap ? 0 : 1);
+            const int nqc = (int)((L.max_k + 63) / 64);
+            const int ipc = (nqc + (int)((L.max_nrem + 63) / 64)) * NCB;
+            k_down_multi<<<(unsigned)(L.ncell * ipc), 64, 0, s>>>(ipc, nqc, RP, L.piv_ptr, L.tt_off, L.ipos,
+                                                                  L.rem_ptr, L.rem_pos, L.crem_off, L.crem_t, W.u[l],
+                                                                  out, l == kap ? 0 : 1);
             HIPCHECK(hipGetLastError());
         }
     }
