@@ -26,20 +26,43 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int NT = 256;
 
-__global__ void k_gather_multi(int64_t n, int R, int RP, const int32_t *order, const double *X, int64_t ldx,
-                               double *xs, float *hi, float *lo)
+// Input gather for RP columns: X (original order, column-major, leading
+// dimension ldx) to row-major tree order, zero columns past R, and the
+// x_hi / x_lo split of the mixed form.  A workgroup takes 64 consecutive
+// original indices: it reads each column's 64 entries (contiguous) into LDS,
+// then writes each point's row of RP values at its tree position.
+__global__ __launch_bounds__(256) void k_gather_multi(int64_t n, int R, int RP, const int32_t *rank, const double *X,
+                                                      int64_t ldx, double *xs, float *hi, float *lo)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n * RP) return;
-    int64_t p = i / RP;
-    int c = (int)(i % RP);
-    double v = c < R ? X[(int64_t)c * ldx + order[p]] : 0.0;
-    xs[i] = v;
-    if (hi) {
-        float h = (float)v;
-        hi[i] = h;
-        lo[i] = (float)(v - (double)h);
+    __shared__ double tile[64 * 65];   // [point][column], rows padded against bank conflicts
+    const int t = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int jn = n - j0 < 64 ? (int)(n - j0) : 64;
+    {
+        const int jj = t & 63;
+        for (int c = t >> 6; c < RP; c += 4)
+            tile[jj * 65 + c] = (c < R && jj < jn) ? X[(int64_t)c * ldx + j0 + jj] : 0.0;
     }
+    __syncthreads();
+    const int ppr = 256 / RP;   // rows written per round
+    if (t >= ppr * RP) return;
+    const int c = t % RP;
+    for (int jj = t / RP; jj < jn; jj += ppr) {
+        const double v = tile[jj * 65 + c];
+        const int64_t i = (int64_t)rank[j0 + jj] * RP + c;
+        xs[i] = v;
+        if (hi) {
+            const float h = (float)v;
+            hi[i] = h;
+            lo[i] = (float)(v - (double)h);
+        }
+    }
+}
+
+__global__ void k_rank(int64_t n, const int32_t *order, int32_t *rank)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n) rank[order[p]] = (int32_t)p;
 }
 
 // Transfer passes for RP columns (Sec. 4).  One wavefront per (cell, 64 rows,
@@ -729,8 +752,8 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     const bool mixed = precision == NNCA_PREC_MIXED;
     const int kind = H->kind;
     auto &W = H->multi;
-    k_gather_multi<<<grid_for(n * RP, 256), 256, 0, s>>>(n, R, RP, H->order, X, ldx, W.xs, mixed ? W.xhi : nullptr,
-                                                         mixed ? W.xlo : nullptr);
+    k_gather_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, W.rank, X, ldx, W.xs, mixed ? W.xhi : nullptr,
+                                                             mixed ? W.xlo : nullptr);
     HIPCHECK(hipGetLastError());
     const double prm64 = 1.0 / (H->hparam * H->hparam);
     const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
@@ -788,12 +811,15 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     HIPCHECK(hipGetLastError());
 }
 
-void ensure_multi(nnca_h2 *H, int RP)
+void ensure_multi(nnca_h2 *H, int RP, hipStream_t s)
 {
     auto &W = H->multi;
     if (W.rp >= RP) return;
     free_multi(H);
     const int64_t n = H->n;
+    W.rank = dalloc<int32_t>(n);
+    k_rank<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, W.rank);
+    HIPCHECK(hipGetLastError());
     W.xs = dalloc<double>(n * RP);
     W.far = dalloc<double>(n * RP);
     W.xhi = dalloc<float>(n * RP);
@@ -819,7 +845,7 @@ void ensure_multi(nnca_h2 *H, int RP)
 void free_multi(nnca_h2 *H)
 {
     auto &W = H->multi;
-    dfree(W.xs); dfree(W.far); dfree(W.xhi); dfree(W.xlo); dfree(W.part);
+    dfree(W.xs); dfree(W.far); dfree(W.xhi); dfree(W.xlo); dfree(W.part); dfree(W.rank);
     for (auto p : W.w) dfree(p);
     for (auto p : W.u) dfree(p);
     for (auto p : W.w32) dfree(p);
@@ -832,7 +858,7 @@ void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int6
     for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
         const int R = (int)std::min<int64_t>(64, nrhs - c0);
         const int NCB = (R + 15) / 16;
-        ensure_multi(H, NCB * 16);
+        ensure_multi(H, NCB * 16, s);
         const double *Xb = X + c0 * ldx;
         double *Yb = Y + c0 * ldy;
         switch (NCB) {

@@ -157,6 +157,7 @@ struct nnca_h2 {
         double *xs = nullptr, *far = nullptr, *part = nullptr;
         int64_t part_cap = 0;
         float *xhi = nullptr, *xlo = nullptr;
+        int32_t *rank = nullptr;      // original index -> tree position (inverse of order)
         std::vector<double *> w, u;   // per level
         std::vector<float *> w32;     // per level: FP32 copy of w for the FP32 transverse pass
         int R = 0;                    // columns of the block in flight
