@@ -59,6 +59,29 @@ __global__ __launch_bounds__(256) void k_gather_multi(int64_t n, int R, int RP, 
     }
 }
 
+// Output scatter for RP columns, the converse of the gather: the row-major
+// tree-order result to Y (original order, column-major, leading dimension
+// ldy), columns below R.  A workgroup reads the rows of 64 consecutive
+// original indices (contiguous) into LDS and writes each column's 64 entries
+// (contiguous).
+__global__ __launch_bounds__(256) void k_scatter_multi(int64_t n, int R, int RP, const int32_t *rank, const double *yt,
+                                                       double *Y, int64_t ldy)
+{
+    __shared__ double tile[64 * 65];
+    const int t = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int jn = n - j0 < 64 ? (int)(n - j0) : 64;
+    const int ppr = 256 / RP;
+    if (t < ppr * RP) {
+        const int c = t % RP;
+        for (int jj = t / RP; jj < jn; jj += ppr) tile[jj * 65 + c] = yt[(int64_t)rank[j0 + jj] * RP + c];
+    }
+    __syncthreads();
+    const int jj = t & 63;
+    if (jj < jn)
+        for (int c = t >> 6; c < R; c += 4) Y[(int64_t)c * ldy + j0 + jj] = tile[jj * 65 + c];
+}
+
 __global__ void k_rank(int64_t n, const int32_t *order, int32_t *rank)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -467,7 +490,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
-// Near field for RP columns on the matrix cores plus the combine into Y.
+// Near field for RP columns on the matrix cores plus the far field, written
+// back in tree order (k_scatter_multi then forms Y).
 // Coordinates FP64; the mixed form (T = float) rounds the differences to FP32,
 // generates K in FP32 and multiplies it by the x_hi and x_lo tiles with
 // v_mfma_f32_16x16x4f32 (partial sums folded into FP64 every 16 sources);
@@ -476,8 +500,8 @@ template <typename T, int KIND, int NCB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 2))) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
                                                  const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
                                                  const int32_t *nbsum, const double *pts, int64_t n, int d,
-                                                 const T *xw, const T *xw2, const double *far,
-                                                 const int32_t *order, double *Y, int64_t ldy, int R, T prm)
+                                                 const T *xw, const T *xw2, const double *far, double *yt, int R,
+                                                 T prm)
 {
     constexpr int RP = NCB * 16;
     constexpr int TS = 64;
@@ -604,9 +628,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
                     int32_t r = tb * 16 + (mixed ? 4 * (lane >> 4) + i : 4 * i + (lane >> 4));
                     int col = b * 16 + (lane & 15);
                     if (r < kk && col < R) {
-                        int64_t p = po + r;
-                        double f = far ? far[p * RP + col] : 0.0;
-                        Y[(int64_t)col * ldy + order[p]] = f + accd[b][i];
+                        const int64_t p = po + r;
+                        const double f = far ? far[p * RP + col] : 0.0;
+                        yt[p * RP + col] = f + accd[b][i];
                     }
                 }
         }
@@ -797,7 +821,7 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
         }
     }
     const Level &F = H->lev[kap];
-#define PP(T, K, A, B, PRM) k_p2p_mfma<T, K, NCB><<<(int)F.ncell, NT, 0, s>>>(F.ncell, F.first, F.count, F.nb_ptr, F.nb, H->nbpre, H->nbsum, H->pts64, n, H->dim, A, B, far, H->order, Y, ldy, R, PRM)
+#define PP(T, K, A, B, PRM) k_p2p_mfma<T, K, NCB><<<(int)F.ncell, NT, 0, s>>>(F.ncell, F.first, F.count, F.nb_ptr, F.nb, H->nbpre, H->nbsum, H->pts64, n, H->dim, A, B, far, W.far, R, PRM)
     if (mixed) {
         if (kind == NNCA_K_INV_R) PP(float, NNCA_K_INV_R, W.xhi, W.xlo, prm32);
         else if (kind == NNCA_K_LOG_R) PP(float, NNCA_K_LOG_R, W.xhi, W.xlo, prm32);
@@ -808,6 +832,8 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
         else PP(double, NNCA_K_GAUSS, W.xs, (const double *)nullptr, prm64);
     }
 #undef PP
+    HIPCHECK(hipGetLastError());
+    k_scatter_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, W.rank, W.far, Y, ldy);
     HIPCHECK(hipGetLastError());
 }
 
