@@ -85,7 +85,7 @@ void nnca::destroy_handle(nnca_h2 *H)
     void *ps[] = {H->pts64,    H->order,    H->keys,     H->nbpre,    H->nbsum,     H->xs64,
                   H->far64,    H->xhi,      H->xlo,      H->m2l_part, H->pown_ptr,  H->pown_nb,
                   H->pown_pre, H->pown_sum, H->pown_slot, H->pnon_ptr, H->pnon_slot, H->pcell,
-                  H->pcol_hi,  H->pcol_lo,  H->prow};
+                  H->pcol_hi,  H->pcol_lo,  H->prow,     H->near64,   H->rank};
     for (void *p : ps) dfree(p);
     delete H;
 }

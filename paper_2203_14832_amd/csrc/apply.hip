@@ -130,6 +130,23 @@ __global__ __launch_bounds__(256) void k_up_cell(const int32_t *piv_ptr, const i
     }
 }
 
+// y_j = near + far of the point whose tree position is rank_j: random reads,
+// contiguous writes (the same sum, in the same order, as adding the far field
+// to the near-field sums in place)
+__global__ void k_near_far_out(int64_t n, const int32_t *rank, const double *near, const double *far, double *y)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t p = rank[j];
+    y[j] = near[p] + far[p];
+}
+
+__global__ void k_invert_order(int64_t n, const int32_t *order, int32_t *rank)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n) rank[order[p]] = (int32_t)p;
+}
+
 // downward pass: the stacked C_B u^{B,i} added to the children's u (L2L) or
 // written as the far field of the leaf's points (L2P).  crem_t holds every
 // cell's block transposed (k x (m-k)) so that neighbouring rows read
@@ -503,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t c0, const int32_t *first, co
             }
             int32_t p = po + tb + i;
             double f = far ? far[p] : 0.0;
-            y[order[p]] = (f + s1) + s2;
+            y[order ? order[p] : p] = (f + s1) + s2;
         }
         __syncthreads();
     }
@@ -1314,19 +1331,20 @@ __global__ void k_p2p_gather(int64_t n, const int32_t *pcell, const int32_t *fir
         s1 += (double)col_hi[sl];
         s2 += (double)col_lo[sl];
     }
-    y[order[p]] = s1 + s2;
+    y[order ? order[p] : p] = s1 + s2;
 }
 
 // the near field of leaf cells [c0, c1)
 template <typename T>
 void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *far, double *y, T prm,
-                hipStream_t s, int64_t c0 = 0, int64_t c1 = -1)
+                hipStream_t s, int64_t c0 = 0, int64_t c1 = -1, bool tree_order = false)
 {
+    const int32_t *order = tree_order ? nullptr : H->order;
     const nnca::Level &L = H->lev[H->kappa];
     if (c1 < 0) c1 = L.ncell;
     const int64_t nc = c1 - c0;
     if (nc <= 0) return;
-#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(c0, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, H->order, y, prm)
+#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(c0, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, order, y, prm)
     if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
     else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
@@ -1374,8 +1392,8 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
     double *far = nullptr;
     // With a far field, the near field runs on the handle's second stream
     // while the far-field passes run here (it reads only x and the points);
-    // it writes the near-field sums to y, and the leaf-level L2P adds the far
-    // field to y after the join.  It runs in two parts of equal work, both
+    // both write their sums in tree order, and after the join one kernel
+    // forms y (original order) from them through the inverse permutation.  It runs in two parts of equal work, both
     // beside memory-bound passes: the first beside the upward pass, the
     // second after the leaf level's transverse kernel, beside its combine
     // step and the downward pass (the transverse kernels, bound by VALU
@@ -1389,14 +1407,15 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
     auto near_part = [&](int64_t c0, int64_t c1) {
         Span sp(H, H->aux, PASS_P2P, kap);
         if (psym) launch_p2p_sym(kind, H, (const float *)xhi, (const float *)xlo, (float)prm, H->aux, c0, c1);
-        else if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, y, prm, H->aux, c0, c1);
-        else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, y, prm, H->aux, c0, c1);
+        else if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, H->near64, prm, H->aux, c0, c1, true);
+        else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, H->near64, prm, H->aux, c0, c1, true);
     };
     auto near_gather = [&]() {
         Span sp(H, H->aux, PASS_P2P, kap);
         const nnca::Level &F = H->lev[kap];
         k_p2p_gather<<<grid_for(H->n, 256), 256, 0, H->aux>>>(H->n, H->pcell, F.first, H->pnon_ptr, H->pnon_slot,
-                                                              H->pcol_hi, H->pcol_lo, H->prow, H->order, y);
+                                                              H->pcol_hi, H->pcol_lo, H->prow, nullptr,
+                                                              H->near64);
         HIPCHECK(hipGetLastError());
     };
     if (overlap) {
@@ -1454,18 +1473,22 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             near_part(csplit, ncl);
             HIPCHECK(hipEventRecord(H->ev_join, H->aux));
         }
-        // downward pass; with the near field overlapped, the leaf level adds
-        // the far field to y (original order) after the join
+        // downward pass; the leaf level writes the far field in tree order
         far = H->far64;
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
             const bool leaf = l == kap;
-            double *out = leaf ? (overlap ? y : far) : H->lev[l + 1].u64;
-            if (leaf && overlap) HIPCHECK(hipStreamWaitEvent(s, H->ev_join, 0));
+            double *out = leaf ? far : H->lev[l + 1].u64;
             Span sp(H, s, PASS_DOWN, l);
             k_down<<<grid_for(L.npiv + L.nrem, 256), 256, 0, s>>>(
                 L.npiv, L.nrem, L.piv_cell, L.rem_cell, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
-                L.crem_off, L.crem_t, L.u64, out, leaf ? (overlap ? 1 : 0) : 1, leaf && overlap ? H->order : nullptr);
+                L.crem_off, L.crem_t, L.u64, out, leaf ? 0 : 1, nullptr);
+            HIPCHECK(hipGetLastError());
+        }
+        if (overlap) {
+            HIPCHECK(hipStreamWaitEvent(s, H->ev_join, 0));
+            Span sp(H, s, PASS_DOWN, kap);
+            k_near_far_out<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->rank, H->near64, far, y);
             HIPCHECK(hipGetLastError());
         }
     }
@@ -1628,6 +1651,16 @@ static void prepare_p2p_sym(nnca_h2 *H, const std::vector<int32_t> &hc)
     H->p2p_sym = true;
 }
 
+// tree-order near-field buffer and the inverse permutation of the points
+// (order is a permutation of [0, n))
+void prepare_output(nnca_h2 *H, hipStream_t s)
+{
+    H->near64 = dalloc<double>(H->n);
+    H->rank = dalloc<int32_t>(H->n);
+    k_invert_order<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->order, H->rank);
+    HIPCHECK(hipGetLastError());
+}
+
 void prepare_apply(nnca_h2 *H)
 {
     hipStream_t s = H->stream;
@@ -1714,6 +1747,7 @@ void prepare_apply(nnca_h2 *H)
     HIPCHECK(hipEventCreateWithFlags(&H->ev_leafk, hipEventDisableTiming));
     H->xs64 = dalloc<double>(H->n);
     H->far64 = dalloc<double>(H->n);
+    prepare_output(H, s);
     H->xhi = dalloc<float>(H->n);
     H->xlo = dalloc<float>(H->n);
 }

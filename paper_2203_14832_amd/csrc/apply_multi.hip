@@ -82,12 +82,6 @@ __global__ __launch_bounds__(256) void k_scatter_multi(int64_t n, int R, int RP,
         for (int c = t >> 6; c < R; c += 4) Y[(int64_t)c * ldy + j0 + jj] = tile[jj * 65 + c];
 }
 
-__global__ void k_rank(int64_t n, const int32_t *order, int32_t *rank)
-{
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < n) rank[order[p]] = (int32_t)p;
-}
-
 // Transfer passes for RP columns (Sec. 4).  One wavefront per (cell, 64 rows,
 // 16 columns): every lane keeps the 16 sums of its row in registers, the
 // matrix entries of the wave's 64 rows are contiguous in memory, and the
@@ -776,7 +770,7 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     const bool mixed = precision == NNCA_PREC_MIXED;
     const int kind = H->kind;
     auto &W = H->multi;
-    k_gather_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, W.rank, X, ldx, W.xs, mixed ? W.xhi : nullptr,
+    k_gather_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, X, ldx, W.xs, mixed ? W.xhi : nullptr,
                                                              mixed ? W.xlo : nullptr);
     HIPCHECK(hipGetLastError());
     const double prm64 = 1.0 / (H->hparam * H->hparam);
@@ -833,19 +827,16 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     }
 #undef PP
     HIPCHECK(hipGetLastError());
-    k_scatter_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, W.rank, W.far, Y, ldy);
+    k_scatter_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, W.far, Y, ldy);
     HIPCHECK(hipGetLastError());
 }
 
-void ensure_multi(nnca_h2 *H, int RP, hipStream_t s)
+void ensure_multi(nnca_h2 *H, int RP)
 {
     auto &W = H->multi;
     if (W.rp >= RP) return;
     free_multi(H);
     const int64_t n = H->n;
-    W.rank = dalloc<int32_t>(n);
-    k_rank<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, W.rank);
-    HIPCHECK(hipGetLastError());
     W.xs = dalloc<double>(n * RP);
     W.far = dalloc<double>(n * RP);
     W.xhi = dalloc<float>(n * RP);
@@ -871,7 +862,7 @@ void ensure_multi(nnca_h2 *H, int RP, hipStream_t s)
 void free_multi(nnca_h2 *H)
 {
     auto &W = H->multi;
-    dfree(W.xs); dfree(W.far); dfree(W.xhi); dfree(W.xlo); dfree(W.part); dfree(W.rank);
+    dfree(W.xs); dfree(W.far); dfree(W.xhi); dfree(W.xlo); dfree(W.part);
     for (auto p : W.w) dfree(p);
     for (auto p : W.u) dfree(p);
     for (auto p : W.w32) dfree(p);
@@ -884,7 +875,7 @@ void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int6
     for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
         const int R = (int)std::min<int64_t>(64, nrhs - c0);
         const int NCB = (R + 15) / 16;
-        ensure_multi(H, NCB * 16, s);
+        ensure_multi(H, NCB * 16);
         const double *Xb = X + c0 * ldx;
         double *Yb = Y + c0 * ldy;
         switch (NCB) {

@@ -282,6 +282,7 @@ nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags)
         HIPCHECK(hipEventCreateWithFlags(&M->ev_leafk, hipEventDisableTiming));
         M->xs64 = dalloc<double>(N);
         M->far64 = dalloc<double>(N);
+        prepare_output(M, s);
         M->xhi = dalloc<float>(N);
         M->xlo = dalloc<float>(N);
         HIPCHECK(hipStreamSynchronize(s));

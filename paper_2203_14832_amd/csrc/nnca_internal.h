@@ -136,6 +136,8 @@ struct nnca_h2 {
 
     // matvec workspace
     double *xs64 = nullptr, *far64 = nullptr;
+    double *near64 = nullptr;     // near-field sums in tree order (overlapped schedule)
+    int32_t *rank = nullptr;      // original index -> tree position (inverse of order)
     float *xhi = nullptr, *xlo = nullptr;
     // symmetric near field of the mixed matvec (leaf level): per cell the
     // owned neighbour entries (cell, first source, column slot of source 0),
@@ -157,7 +159,6 @@ struct nnca_h2 {
         double *xs = nullptr, *far = nullptr, *part = nullptr;
         int64_t part_cap = 0;
         float *xhi = nullptr, *xlo = nullptr;
-        int32_t *rank = nullptr;      // original index -> tree position (inverse of order)
         std::vector<double *> w, u;   // per level
         std::vector<float *> w32;     // per level: FP32 copy of w for the FP32 transverse pass
         int R = 0;                    // columns of the block in flight
@@ -211,6 +212,7 @@ void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int6
 void free_multi(nnca_h2 *H);
 void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s);
 void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots);
+void prepare_output(nnca_h2 *H, hipStream_t s);
 int mixed_fp32_levels(int kind);
 void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, double *y, hipStream_t s);
 // grad.hip
