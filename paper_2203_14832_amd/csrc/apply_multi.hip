@@ -502,10 +502,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
     constexpr bool mixed = sizeof(T) == 4;
     static_assert(TS == 64 && TS <= NT, "every step index stays inside one 64-source tile");
     constexpr int SW = (mixed && !(NCB & 1)) ? RP + 16 : RP;   // LDS row stride (bank spread)
+    // the weight tiles and, after the tile loop, the phase reduction share
+    // one LDS buffer
+    constexpr int WBYTES = (int)sizeof(T) * TS * SW * (mixed ? 2 : 1);
+    constexpr int RBYTES = (int)sizeof(double) * NT * NCB * 4;
     __shared__ double4 sx[TS];
-    __shared__ __align__(16) T swt[TS * SW];
-    __shared__ __align__(16) T swt2[mixed ? TS * SW : 1];
-    __shared__ double red[NT * NCB * 4];
+    __shared__ __align__(16) double sraw[(WBYTES > RBYTES ? WBYTES : RBYTES) / 8];
+    T *swt = reinterpret_cast<T *>(sraw);
+    T *swt2 = mixed ? swt + TS * SW : swt;   // used by the mixed form only
+    double *red = sraw;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int64_t c = blockIdx.x;
     const int32_t kk = count[c], po = first[c], S = nbsum[c];
