@@ -1,0 +1,63 @@
+"""GPU: the mixed near field carries the low part of x.
+
+The mixed form splits x = x_hi + x_lo (x_hi = fl32(x)) and multiplies both
+parts by the FP32 kernel block, so that the near field keeps x to FP64
+precision.  The low part is at most 2^-24 of x, far below the 1e-6 bound of
+the other parity tests, so a path that lost it would still pass them.  Here
+every step is exact, so the mixed product must equal the exact sum bit for
+bit:
+
+* two clusters of 30 coincident points, 100 apart, Gaussian kernel with
+  h = 1: every kernel value is exactly 1 (same cluster, r = 0) or exactly 0
+  (exp(-10^4) underflows in FP32 and FP64);
+* x = x_hi + x_lo with x_hi = k 2^-10 (512 < |k| <= 1024, so fl32(x) = x_hi)
+  and x_lo = m 2^-40 (|m| < 2^15, below half an ulp of x_hi): every FP32
+  partial sum of at most 16 such terms is exact, and so is every FP64 sum.
+
+Dropping x_lo would change each row by the cluster's sum of x_lo (~2^-25).
+The 60 points form a single leaf (near field only); one column takes the
+one-column kernel, 20 and 64 columns the matrix-core kernel.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_14832_amd import nnca  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(R, seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros((60, 3))
+    p[30:, 0] = 100.0
+    k = rng.integers(513, 1025, (60, R)) * rng.choice([-1, 1], (60, R))
+    m = rng.integers(-(2 ** 15) + 1, 2 ** 15, (60, R))
+    m[m == 0] = 1
+    x = k * 2.0 ** -10 + m * 2.0 ** -40
+    assert np.array_equal(x.astype(np.float32).astype(np.float64), k * 2.0 ** -10)
+    exact = np.empty_like(x)
+    exact[:30] = x[:30].sum(0)
+    exact[30:] = x[30:].sum(0)
+    lo_only = np.empty_like(x)
+    lo_only[:30] = (m[:30] * 2.0 ** -40).sum(0)
+    lo_only[30:] = (m[30:] * 2.0 ** -40).sum(0)
+    return p, x, exact, lo_only
+
+
+@pytest.mark.parametrize("R", [1, 20, 64])
+def test_mixed_near_field_keeps_x_lo(R):
+    p, x, exact, lo_only = _problem(R, 40 + R)
+    G = nnca.H2Matrix(p, "gauss", 1e-6, 64, length_scale=1.0)
+    X = torch.tensor(x[:, 0] if R == 1 else x, device="cuda")
+    for prec in ("fp64", "mixed"):
+        y = G.matvec(X, prec).cpu().numpy().reshape(60, R)
+        np.testing.assert_array_equal(y, exact, err_msg=prec)
+    # the low parts matter at this precision: without them every row is off
+    assert (np.abs(lo_only) > 0).all()
