@@ -233,6 +233,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
     constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
     constexpr int RED = NT * NCB * 4 * TB;           // doubles of the phase reduction
     __shared__ float4 sx[TS];
+    __shared__ int32_t sidx[TS];
     __shared__ __align__(16) double swt_raw[TS * SW / 2 > RED ? TS * SW / 2 : RED];
     __shared__ int32_t est[MET + 1], ebase[MET];
     __shared__ float esh[3][MET];
@@ -314,21 +315,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
                     v.z = d == 3 ? pc[2 * npiv + idx] + esh[2][lo] : 0.f;
                     v.w = v.x * v.x + v.y * v.y + v.z * v.z;
                     sx[t] = v;
-                    // this source's FP32 weights, four columns at a time: the
-                    // columns up to R (padding columns of w are zero), then zeros
-                    const float4 *wr = reinterpret_cast<const float4 *>(w32 + (int64_t)idx * RP);
-                    float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
+                    sidx[t] = idx;
+                    if constexpr (TS == NT) {
+                        // one source per thread: it loads its own weight row
+                        const float4 *wr = reinterpret_cast<const float4 *>(w32 + (int64_t)idx * RP);
+                        float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
 #pragma unroll
-                    for (int q = 0; q < RP / 4; q++) wd[q] = 4 * q < R ? wr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                        for (int q = 0; q < RP / 4; q++)
+                            wd[q] = 4 * q < R ? wr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 } else if (t < ((ns + 63) & ~63)) {
                     // padding up to a multiple of 64 sources (TS is one): far
                     // from every target, zero weights, so it adds exact zeros
                     sx[t] = make_float4(1e15f, 1e15f, 1e15f, 3e30f);
-                    float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
+                    sidx[t] = -1;
+                    if constexpr (TS == NT) {
+                        float4 *wd = reinterpret_cast<float4 *>(swt + t * SW);
 #pragma unroll
-                    for (int q = 0; q < RP / 4; q++) wd[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        for (int q = 0; q < RP / 4; q++) wd[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 }
                 __syncthreads();
+                // with fewer sources than threads per tile, the FP32 weight
+                // rows are loaded by the whole workgroup, four columns per
+                // thread and step: the columns up to R (padding columns of w
+                // are zero), then zeros
+                if constexpr (TS != NT) {
+                    constexpr int NV = RP / 4;
+                    const int rows = (ns + 63) & ~63;
+                    for (int i = t; i < rows * NV; i += NT) {
+                        const int row = i / NV, q = i % NV;
+                        const int32_t idx = sidx[row];
+                        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (idx >= 0 && 4 * q < R) v = reinterpret_cast<const float4 *>(w32 + (int64_t)idx * RP)[q];
+                        reinterpret_cast<float4 *>(swt + row * SW)[q] = v;
+                    }
+                    __syncthreads();
+                }
                 // groups of four steps: the FP32 accumulators stay in the
                 // matrix-core registers across a group and are added into
                 // the FP64 sums once per group.  A group of phase ph reads
@@ -409,6 +432,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     constexpr int RP = NCB * 16;
     constexpr int TS = 64;
     __shared__ double4 sx[TS];
+    __shared__ int32_t sidx[TS];
     __shared__ __align__(16) double swt[TS * RP > NT * NCB * 4 ? TS * RP : NT * NCB * 4];
     double *red = swt;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -435,15 +459,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const int32_t ns = se - s0 < TS ? se - s0 : TS;
             __syncthreads();
             if (t < ns) {
-                int32_t s = s0 + t;
-                int32_t e = list_entry(ilpre, e0, e1, s);
-                int32_t idx = piv_ptr[il[e]] + (s - ilpre[e]);
+                const int32_t s = s0 + t;
+                const int32_t e = list_entry(ilpre, e0, e1, s);
+                const int32_t idx = piv_ptr[il[e]] + (s - ilpre[e]);
                 sx[t] = make_double4(pc[idx], pc[npiv + idx], d == 3 ? pc[2 * npiv + idx] : 0.0, 0.0);
-                // this source's weights, two columns at a time (padding columns are zero)
-                const double2 *wr = reinterpret_cast<const double2 *>(w + (int64_t)idx * RP);
-                double2 *wd = reinterpret_cast<double2 *>(swt + t * RP);
-#pragma unroll
-                for (int q = 0; q < RP / 2; q++) wd[q] = 2 * q < R ? wr[q] : make_double2(0.0, 0.0);
+                sidx[t] = idx;
+            }
+            __syncthreads();
+            // the tile's weight rows, two columns per thread and step over the
+            // whole workgroup (padding columns are zero)
+            for (int i = t; i < ns * (RP / 2); i += NT) {
+                const int row = i / (RP / 2), q = i % (RP / 2);
+                double2 v = make_double2(0.0, 0.0);
+                if (2 * q < R) v = reinterpret_cast<const double2 *>(w + (int64_t)sidx[row] * RP)[q];
+                reinterpret_cast<double2 *>(swt + row * RP)[q] = v;
             }
             __syncthreads();
             if (wact)
@@ -507,6 +536,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
     constexpr int WBYTES = (int)sizeof(T) * TS * SW * (mixed ? 2 : 1);
     constexpr int RBYTES = (int)sizeof(double) * NT * NCB * 4;
     __shared__ double4 sx[TS];
+    __shared__ int32_t sidx[TS];
     __shared__ __align__(16) double sraw[(WBYTES > RBYTES ? WBYTES : RBYTES) / 8];
     T *swt = reinterpret_cast<T *>(sraw);
     T *swt2 = mixed ? swt + TS * SW : swt;   // used by the mixed form only
@@ -539,34 +569,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
             const int32_t ns = S - s0 < TS ? S - s0 : TS;
             __syncthreads();
             if (t < ns) {
-                int32_t s = s0 + t;
-                int32_t e = list_entry(nbpre, e0, e1, s);
-                int32_t idx = first[nb[e]] + (s - nbpre[e]);
+                const int32_t s = s0 + t;
+                const int32_t e = list_entry(nbpre, e0, e1, s);
+                const int32_t idx = first[nb[e]] + (s - nbpre[e]);
                 sx[t] = make_double4(pts[idx], pts[n + idx], d == 3 ? pts[2 * n + idx] : 0.0, 0.0);
-                // this source's weights, 16 bytes at a time (padding columns are zero)
-                if constexpr (mixed) {
-                    const float4 *a = reinterpret_cast<const float4 *>(xw + (int64_t)idx * RP);
-                    const float4 *b = reinterpret_cast<const float4 *>(xw2 + (int64_t)idx * RP);
-                    float4 *da = reinterpret_cast<float4 *>(swt + t * SW);
-                    float4 *db = reinterpret_cast<float4 *>(swt2 + t * SW);
-#pragma unroll
-                    for (int q = 0; q < RP / 4; q++) {
-                        da[q] = 4 * q < R ? a[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                        db[q] = 4 * q < R ? b[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                } else {
-                    const double2 *a = reinterpret_cast<const double2 *>(xw + (int64_t)idx * RP);
-                    double2 *da = reinterpret_cast<double2 *>(swt + t * SW);
-#pragma unroll
-                    for (int q = 0; q < RP / 2; q++) da[q] = 2 * q < R ? a[q] : make_double2(0.0, 0.0);
-                }
+                sidx[t] = idx;
             } else if (t < TS) {
                 // padding of the tile: far from every target, zero weights
                 sx[t] = make_double4(1e15, 1e15, 1e15, 0.0);
-#pragma unroll
-                for (int q = 0; q < RP; q++) {
-                    swt[t * SW + q] = T(0);
-                    if constexpr (mixed) swt2[t * SW + q] = T(0);
+                sidx[t] = -1;
+            }
+            __syncthreads();
+            // the tile's weight rows, 16 bytes per thread and step over the
+            // whole workgroup (columns from R on and padding rows are zero)
+            {
+                constexpr int V = 16 / (int)sizeof(T);   // values per 16 bytes
+                constexpr int NV = RP / V;                // 16-byte pieces per row
+                for (int i = t; i < TS * NV; i += NT) {
+                    const int row = i / NV, q = i % NV;
+                    const int32_t idx = sidx[row];
+                    const bool live = idx >= 0 && V * q < R;
+                    if constexpr (mixed) {
+                        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+                        if (live) {
+                            a = reinterpret_cast<const float4 *>(xw + (int64_t)idx * RP)[q];
+                            b = reinterpret_cast<const float4 *>(xw2 + (int64_t)idx * RP)[q];
+                        }
+                        reinterpret_cast<float4 *>(swt + row * SW)[q] = a;
+                        reinterpret_cast<float4 *>(swt2 + row * SW)[q] = b;
+                    } else {
+                        double2 a = make_double2(0.0, 0.0);
+                        if (live) a = reinterpret_cast<const double2 *>(xw + (int64_t)idx * RP)[q];
+                        reinterpret_cast<double2 *>(swt + row * SW)[q] = a;
+                    }
                 }
             }
             __syncthreads();
