@@ -192,6 +192,121 @@ __global__ __launch_bounds__(64) void k_down_multi(int ipc, int nqc, int RP, con
     }
 }
 
+// The same passes for levels with few items: four wavefronts per item, each
+// taking every fourth term of the sum; the partial sums are added in order
+// through LDS.
+constexpr int SPLIT_WAVES = 4;
+
+__device__ inline void add_split_partials(double (&acc)[16], int wv, int lane, double *red)
+{
+    if (wv > 0)
+#pragma unroll
+        for (int j = 0; j < 16; j++) red[((wv - 1) * 16 + j) * 64 + lane] = acc[j];
+    __syncthreads();
+    if (wv == 0)
+        for (int w2 = 1; w2 < SPLIT_WAVES; w2++)
+#pragma unroll
+            for (int j = 0; j < 16; j++) acc[j] += red[((w2 - 1) * 16 + j) * 64 + lane];
+}
+
+__global__ __launch_bounds__(64 * SPLIT_WAVES) void k_up_multi_split(
+    int ipc, int RP, const int32_t *piv_ptr, const int32_t *tt_off, const int32_t *ipos, const int32_t *rem_ptr,
+    const int32_t *rem_pos, const int64_t *crem_off, const double *__restrict__ crem,
+    const double *__restrict__ xin, double *__restrict__ w)
+{
+    __shared__ double red[(SPLIT_WAVES - 1) * 16 * 64];
+    const int64_t c = blockIdx.x / ipc;
+    const int item = (int)(blockIdx.x % ipc), ncb = RP / 16;
+    const int32_t qc = item / ncb, cb = item % ncb;
+    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po;
+    if (qc * 64 >= kk) return;   // uniform for the workgroup
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t to = tt_off[c], ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    const int32_t q = qc * 64 + lane, qs = q < kk ? q : kk - 1;
+    const double *xb = xin + cb * 16;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = 0.0;
+    const double *Cq = crem + crem_off[c] + qs;
+#pragma unroll 2
+    for (int32_t r = wv; r < nr; r += SPLIT_WAVES) {
+        const double cv = Cq[(int64_t)r * kk];
+        const double *xr = xb + (int64_t)(to + rem_pos[ro + r]) * RP;
+#pragma unroll
+        for (int j = 0; j < 16; j++) acc[j] = fma(cv, xr[j], acc[j]);
+    }
+    add_split_partials(acc, wv, lane, red);
+    if (wv == 0 && q < kk) {
+        const double2 *xp = reinterpret_cast<const double2 *>(xb + (int64_t)(to + ipos[po + q]) * RP);
+        double2 *wp = reinterpret_cast<double2 *>(w + (int64_t)(po + q) * RP + cb * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const double2 v = xp[j];
+            wp[j] = make_double2(v.x + acc[2 * j], v.y + acc[2 * j + 1]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * SPLIT_WAVES) void k_down_multi_split(
+    int ipc, int nqc, int RP, const int32_t *piv_ptr, const int32_t *tt_off, const int32_t *ipos,
+    const int32_t *rem_ptr, const int32_t *rem_pos, const int64_t *crem_off, const double *__restrict__ crem_t,
+    const double *__restrict__ u, double *__restrict__ out, int accumulate)
+{
+    __shared__ double red[(SPLIT_WAVES - 1) * 16 * 64];
+    const int64_t c = blockIdx.x / ipc;
+    int item = (int)(blockIdx.x % ipc);
+    const int ncb = RP / 16, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t po = piv_ptr[c], kk = piv_ptr[c + 1] - po, to = tt_off[c];
+    if (item < nqc * ncb) {
+        const int32_t qc = item / ncb, cb = item % ncb, q = qc * 64 + lane;
+        if (wv > 0 || q >= kk) return;
+        const double2 *up = reinterpret_cast<const double2 *>(u + (int64_t)(po + q) * RP + cb * 16);
+        double2 *op = reinterpret_cast<double2 *>(out + (int64_t)(to + ipos[po + q]) * RP + cb * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            double2 v = up[j];
+            if (accumulate) {
+                const double2 o = op[j];
+                v.x += o.x;
+                v.y += o.y;
+            }
+            op[j] = v;
+        }
+        return;
+    }
+    item -= nqc * ncb;
+    const int32_t rc = item / ncb, cb = item % ncb;
+    const int32_t ro = rem_ptr[c], nr = rem_ptr[c + 1] - ro;
+    if (rc * 64 >= nr) return;   // uniform for the workgroup
+    const int32_t r = rc * 64 + lane, rs = r < nr ? r : nr - 1;
+    const double *Ct = crem_t + crem_off[c] + rs;
+    const double *ub = u + (int64_t)po * RP + cb * 16;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = 0.0;
+#pragma unroll 2
+    for (int32_t q = wv; q < kk; q += SPLIT_WAVES) {
+        const double cv = Ct[(int64_t)q * nr];
+        const double *uq = ub + (int64_t)q * RP;
+#pragma unroll
+        for (int j = 0; j < 16; j++) acc[j] = fma(cv, uq[j], acc[j]);
+    }
+    add_split_partials(acc, wv, lane, red);
+    if (wv == 0 && r < nr) {
+        double2 *op = reinterpret_cast<double2 *>(out + (int64_t)(to + rem_pos[ro + r]) * RP + cb * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            double2 v = make_double2(acc[2 * j], acc[2 * j + 1]);
+            if (accumulate) {
+                const double2 o = op[j];
+                v.x += o.x;
+                v.y += o.y;
+            }
+            op[j] = v;
+        }
+    }
+}
+
 // index of the interaction-list entry holding source s of the cell (the
 // largest e in [e0, e1) with pre[e] <= s)
 __device__ inline int32_t list_entry(const int32_t *pre, int32_t e0, int32_t e1, int32_t s)
@@ -204,6 +319,9 @@ __device__ inline int32_t list_entry(const int32_t *pre, int32_t e0, int32_t e1,
     return lo;
 }
 
+// transfer-pass launches with fewer items than this take the four-wavefront
+// kernels
+constexpr unsigned SPLIT_BELOW = 2048;
 constexpr int MET = 256;   // interaction-list entries staged in LDS at a time
 
 __global__ void k_to_f32(int64_t cnt, const double *a, float *b)
@@ -821,8 +939,13 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
             Level &L = H->lev[l];
             const double *src = l == kap ? W.xs : W.w[l + 1];
             const int ipc = (int)((L.max_k + 63) / 64) * NCB;
-            k_up_multi<<<(unsigned)(L.ncell * ipc), 64, 0, s>>>(ipc, RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr,
-                                                                L.rem_pos, L.crem_off, L.crem64, src, W.w[l]);
+            const unsigned nb = (unsigned)(L.ncell * ipc);
+            if (nb < SPLIT_BELOW)
+                k_up_multi_split<<<nb, 64 * SPLIT_WAVES, 0, s>>>(ipc, RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr,
+                                                                 L.rem_pos, L.crem_off, L.crem64, src, W.w[l]);
+            else
+                k_up_multi<<<nb, 64, 0, s>>>(ipc, RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
+                                             L.crem_off, L.crem64, src, W.w[l]);
             HIPCHECK(hipGetLastError());
         }
         // FP32 copies of the multipole vectors the FP32 transverse pass reads
@@ -848,9 +971,14 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
             double *out = l == kap ? far : W.u[l + 1];
             const int nqc = (int)((L.max_k + 63) / 64);
             const int ipc = (nqc + (int)((L.max_nrem + 63) / 64)) * NCB;
-            k_down_multi<<<(unsigned)(L.ncell * ipc), 64, 0, s>>>(ipc, nqc, RP, L.piv_ptr, L.tt_off, L.ipos,
-                                                                  L.rem_ptr, L.rem_pos, L.crem_off, L.crem_t, W.u[l],
-                                                                  out, l == kap ? 0 : 1);
+            const unsigned nb = (unsigned)(L.ncell * ipc);
+            if (nb < SPLIT_BELOW)
+                k_down_multi_split<<<nb, 64 * SPLIT_WAVES, 0, s>>>(ipc, nqc, RP, L.piv_ptr, L.tt_off, L.ipos,
+                                                                   L.rem_ptr, L.rem_pos, L.crem_off, L.crem_t,
+                                                                   W.u[l], out, l == kap ? 0 : 1);
+            else
+                k_down_multi<<<nb, 64, 0, s>>>(ipc, nqc, RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
+                                               L.crem_off, L.crem_t, W.u[l], out, l == kap ? 0 : 1);
             HIPCHECK(hipGetLastError());
         }
     }
