@@ -41,7 +41,7 @@ PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
 # runs of `bench.py --probe` (profiles/h2_matvec_c2_hbm_bytes.md), scaled by
 # the counters' reading of a 256 MiB copy: fetch + write MiB at kappa and
 # kappa-1.  Valid for one version of k_m2l_sym; None once the kernel changes.
-M2L_SYM_HBM_MIB = ((276.9, 339.8), (94.0, 117.0))
+M2L_SYM_HBM_MIB = ((277.0, 339.9), (94.1, 117.0))
 
 
 def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3):
