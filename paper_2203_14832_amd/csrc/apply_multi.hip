@@ -15,6 +15,7 @@
 // scheme as for one column.
 #include <cstring>
 #include <algorithm>
+#include <type_traits>
 
 #include "nnca_internal.h"
 #include "kernel_values.h"
@@ -475,11 +476,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
                 // the FP64 sums once per group.  A group of phase ph reads
                 // sources below (g0 / (16 nph) + 1) 16 nph <= the padded
                 // tile end, since 16 nph divides 64.
-                if (wact)
-                    for (int32_t g0 = ph * 4; g0 < ns; g0 += 16 * nph) {
+                // (the phase count is a template constant of the loop, so the
+                // four steps' LDS addresses differ by immediate offsets)
+                auto groups = [&](auto nph_c) {
+                    constexpr int NPH = decltype(nph_c)::value;
+                    for (int32_t g0 = ph * 4; g0 < ns; g0 += 16 * NPH) {
 #pragma unroll
                         for (int k = 0; k < 4; k++) {
-                            const int32_t src = g0 + k * 4 * nph + (lane >> 4);
+                            const int32_t src = g0 + k * 4 * NPH + (lane >> 4);
                             const float4 q = sx[src];
                             float kvv[TB];
 #pragma unroll
@@ -507,6 +511,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
                                 accf[j][b] = floatx4{0.f, 0.f, 0.f, 0.f};
                             }
                     }
+                };
+                if (wact) {
+                    if (nph == 1) groups(std::integral_constant<int, 1>{});
+                    else if (nph == 2) groups(std::integral_constant<int, 2>{});
+                    else groups(std::integral_constant<int, 4>{});
+                }
             }
         }
         // phases of the same unit are added in order ph = 0, 1, ...
