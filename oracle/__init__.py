@@ -248,9 +248,16 @@ class H2:
         return Y[0] if vec else Y.T.copy()
 
     def interactions(self):
-        out = np.zeros(2, np.int64)
+        """(transverse, near-field) kernel interactions of one matvec column."""
+        out = np.zeros(2 + self.tree.kappa + 1, np.int64)
         lib().orc_h2_interactions(self._h, _p(out))
         return int(out[0]), int(out[1])
+
+    def interactions_by_level(self):
+        """Transverse interactions of each level 0..kappa (one column)."""
+        out = np.zeros(2 + self.tree.kappa + 1, np.int64)
+        lib().orc_h2_interactions(self._h, _p(out))
+        return [int(v) for v in out[2:]]
 
     def frozen(self, h: float) -> "H2":
         """The same pivots with every operator re-evaluated at length scale h

@@ -984,17 +984,23 @@ void orc_h2_matvec(const orc_h2 *H, const double *x, double *y, int64_t nrhs, in
     free(w); free(u); free(off); free(xs); free(ys);
 }
 
-/* Number of kernel interactions one matvec evaluates per right-hand side:
- * out[0] = transverse (sum over IL pairs of k_B k_B'), out[1] = near field. */
+/* Number of kernel interactions one matvec evaluates per right-hand side
+ * (Sec. 4: the transverse pass applies S_{B,B'} = K(t^{B,i}, t^{B',i}), a
+ * k_B x k_B' block, for every B' in IL(B); the near field a |t^B| x |t^B'|
+ * block for every B' in N(B) of a leaf):
+ *   out[0] = transverse total, out[1] = near field,
+ *   out[2 + l] = transverse pairs of level l for l = 0..kappa (0 above lmin). */
 void orc_h2_interactions(const orc_h2 *H, int64_t *out)
 {
     const orc_tree *T = H->T;
     out[0] = out[1] = 0;
+    for (int l = 0; l <= T->kappa; l++) out[2 + l] = 0;
     for (int l = H->lmin; l <= T->kappa; l++) {
         const olevel *lv = &T->lev[l];
         for (int64_t b = 0; b < lv->ncell; b++)
             for (int64_t e = lv->il_ptr[b]; e < lv->il_ptr[b + 1]; e++)
-                out[0] += H->cell[l][b].k * H->cell[l][lv->il[e]].k;
+                out[2 + l] += H->cell[l][b].k * H->cell[l][lv->il[e]].k;
+        out[0] += out[2 + l];
     }
     const olevel *lf = &T->lev[T->kappa];
     for (int64_t b = 0; b < lf->ncell; b++)

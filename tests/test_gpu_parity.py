@@ -4,8 +4,11 @@
 * tree order, cells and lists are identical;
 * pivot sets t^{B,i} and s^{B,i} are identical at every level (FP64 build);
 * transfer operators agree to 1e-12 (in practice bit for bit);
-* the FP64 matvec agrees with the oracle's to 1e-12, the mixed one with the
-  FP64 one to 1e-6 (the tolerance the mixed form is specified to);
+* the FP64 matvec agrees with the oracle's to 1e-12 (relative 2-norm and
+  every entry against the column's largest), the mixed one with the FP64 one
+  and with the oracle's to 1e-6 (the tolerance the mixed form is specified
+  to), also with the plain (every ordered pair) FP32 passes;
+* the interaction counts per level equal the oracle's;
 * the FP64 direct sum agrees with the oracle's compensated sum to 1e-13.
 Sizes span several levels, partially filled tiles and ragged cells.
 """
@@ -45,7 +48,30 @@ CASES = {
     "mixture": (lambda: workload("c4", n=12000)[0], "gauss", 1e-6, 128, 0.5, None),
     "literal_sqrt2": (lambda: np.random.default_rng(7).uniform(-1, 1, (6000, 3)), "inv_r", 1e-6, 24, 1.0, (2, 1)),
     "cube2d_inv": (lambda: np.random.default_rng(8).uniform(-1, 1, (9000, 2)), "inv_r", 1e-9, 20, 1.0, None),
+    # the headline distribution at N = 2^16 (kappa = 4): level kappa-1 has
+    # ranks above 80, so the FP32 symmetric transverse pass runs its second
+    # shape set there (ranks 81-224: 4-32 lane groups of up to seven
+    # registers), as it does at level kappa-1 of the N = 2^20 problem
+    "c2_64k": (lambda: workload("c2", n=65536)[0], "inv_r", 1e-6, 64, 1.0, None),
 }
+
+
+def close_elementwise(Y, Yo, tol):
+    """max_i |Y_ic - Yo_ic| <= tol * max_i |Yo_ic| for every column c."""
+    Y, Yo = Y.reshape(Y.shape[0], -1), Yo.reshape(Yo.shape[0], -1)
+    for c in range(Yo.shape[1]):
+        err = np.abs(Y[:, c] - Yo[:, c]).max()
+        assert err <= tol * np.abs(Yo[:, c]).max(), (c, err, np.abs(Yo[:, c]).max())
+
+
+def mixed_vs_oracle(name, Ym, Yo):
+    """The mixed product against the oracle's FP64 product: the relative
+    2-norm within the mixed bound per column, and every entry within ten
+    times that bound of the column's largest entry."""
+    tol = MIXED_TOL.get(name, 1e-6)
+    for c in range(Yo.shape[1]):
+        assert rel(Ym[:, c], Yo[:, c]) <= tol, (name, c, rel(Ym[:, c], Yo[:, c]))
+    close_elementwise(Ym, Yo, 10 * tol)
 
 
 @pytest.fixture(scope="module")
@@ -94,6 +120,29 @@ def test_tree_parity(built, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_interaction_counts(built, name):
+    # the counts that the throughput figures divide by: transverse pairs per
+    # level and near-field pairs, equal to the oracle's
+    p, G, T, O, kind, h = built(name)
+    inf = G.info()
+    far, near = O.interactions()
+    assert inf["m2l_level"] == O.interactions_by_level()
+    assert inf["m2l_interactions"] == far
+    assert inf["p2p_interactions"] == near
+
+
+def test_headline_shape_sets(built):
+    # c2_64k reaches the transverse-pass shape set for level ranks 81-224 at
+    # level kappa-1, which runs in FP32 in the mixed form
+    p, G, T, O, kind, h = built("c2_64k")
+    inf = G.info()
+    k = inf["kappa"]
+    assert k == 4
+    assert 80 < inf["max_rank"][k - 1] <= 224, inf["max_rank"]
+    assert inf["mixed_fp32_levels"] == 2
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_pivot_parity(built, name):
     p, G, T, O, kind, h = built(name)
     for l in range(O.lmin, T.kappa + 1):
@@ -123,8 +172,11 @@ def test_matvec_parity(built, name):
     Y64 = np.stack([G.matvec(Xt[:, c], "fp64").cpu().numpy() for c in range(3)], 1)
     Yo = O.matvec(X)
     assert rel(Y64, Yo) <= 1e-12
+    close_elementwise(Y64, Yo, 1e-12)
     Ym = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
-    print(name, "mixed vs fp64:", [rel(Ym[:, c], Y64[:, c]) for c in range(3)])
+    print(name, "mixed vs fp64:", [rel(Ym[:, c], Y64[:, c]) for c in range(3)],
+          "vs oracle:", [rel(Ym[:, c], Yo[:, c]) for c in range(3)])
+    mixed_vs_oracle(name, Ym, Yo)
     # FP32 transverse pass at the two finest levels for 1/r, the leaf level
     # only for the kernels whose interpolation operators amplify more; the
     # symmetric near field where near pairs exceed 1/12 of the transverse
@@ -144,6 +196,7 @@ def test_matvec_parity(built, name):
     for c in range(3):
         assert rel(Yp[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c)
         assert rel(Yp[:, c], Ym[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c)
+    mixed_vs_oracle(name, Yp, Yo)
     # adjoint: <A x, y> = <x, A^T y>
     Ya = G.rmatvec(Xt, "fp64").cpu().numpy()
     lhs, rhs = X[:, 0] @ Ya[:, 1], Y64[:, 0] @ X[:, 1]
@@ -239,7 +292,7 @@ def test_rank_cap_retry_and_chunking(orc):
 
 
 @pytest.mark.parametrize("name,R", [("cube3d", 5), ("cube3d", 37), ("sphere", 64), ("mixture", 16), ("c1", 20),
-                                    ("literal_sqrt2", 33)])
+                                    ("literal_sqrt2", 33), ("c2_64k", 16)])
 def test_many_rhs_parity(built, name, R):
     # The block path (columns innermost, MFMA for the FP32 transverse pass)
     # against the oracle and against one column at a time.
@@ -250,9 +303,11 @@ def test_many_rhs_parity(built, name, R):
     Y64 = G.matvec(Xt, "fp64").cpu().numpy()
     Yo = O.matvec(X[:, :3])
     assert rel(Y64[:, :3], Yo) <= 1e-12
+    close_elementwise(Y64[:, :3], Yo, 1e-12)
     one = np.stack([G.matvec(Xt[:, c], "fp64").cpu().numpy() for c in (0, R - 1)], 1)
     assert rel(Y64[:, [0, R - 1]], one) <= 1e-13
     Ym = G.matvec(Xt, "mixed").cpu().numpy()
     errs = [rel(Ym[:, c], Y64[:, c]) for c in range(R)]
     print(name, R, "block mixed vs fp64: max", max(errs))
     assert max(errs) <= MIXED_TOL.get(name, 1e-6)
+    mixed_vs_oracle(name, Ym[:, :3], Yo)

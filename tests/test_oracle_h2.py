@@ -156,3 +156,64 @@ def test_degenerate_inputs(orc):
     T, H = build(orc, p, "inv_r", 1e-8, leaf=16)
     assert T.kappa == 20
     assert rel(H.matvec(x), orc.direct(p, x, "inv_r")) <= 1e-6
+
+
+def _brute_interactions(T, H, eta2=None):
+    """Interaction counts recomputed without the oracle's lists: every pair of
+    same-level cells is classified from its integer cell coordinates by the
+    admissibility test of Sec. 2.2 (adjacency for eta^2 = d); a pair of
+    level l >= lmin is a transverse block iff it is admissible and its
+    parents are not (Table 1); a pair of leaves is a near-field block iff it
+    is not admissible."""
+    d = T.d
+    num, den = (d, 1) if eta2 is None else eta2
+
+    def adm(coord):
+        g = np.maximum(np.abs(coord[:, None, :] - coord[None, :, :]) - 1, 0)
+        return d * den <= num * (g * g).sum(-1)
+
+    far = [0] * (T.kappa + 1)
+    for l in range(H.lmin, T.kappa + 1):
+        cl = T.cells(l)
+        k = np.array([H.cell(l, b)["k"] for b in range(T.ncell(l))], np.int64)
+        a = adm(cl["coord"])
+        if l > 0:
+            pa = adm(T.cells(l - 1)["coord"])
+            par = cl["parent"]
+            a &= ~pa[par[:, None], par[None, :]]
+        far[l] = int((np.outer(k, k) * a).sum())
+    leaf = T.cells(T.kappa)
+    cnt = leaf["count"].astype(np.int64)
+    near = int((np.outer(cnt, cnt) * ~adm(leaf["coord"])).sum())
+    return far, near
+
+
+@pytest.mark.parametrize("kind,d,n,leaf,tol,eta2", [("inv_r", 3, 4000, 16, 1e-4, None),
+                                                    ("log_r", 2, 3000, 12, 1e-6, None),
+                                                    ("inv_r", 3, 2500, 12, 1e-5, (2, 1))])
+def test_interaction_counts_brute_force(orc, kind, d, n, leaf, tol, eta2):
+    # the counts behind the throughput figures, per level, against a
+    # recount from cell coordinates and the oracle's ranks
+    rng = np.random.default_rng(40)
+    p = rng.uniform(-1, 1, (n, d))
+    T, H = build(orc, p, kind, tol, leaf, eta2=eta2)
+    far, near = _brute_interactions(T, H, eta2)
+    assert H.interactions_by_level() == far
+    assert H.interactions() == (sum(far), near)
+    assert sum(far) > 0 and near > 0
+
+
+def test_interaction_counts_cover_all_pairs(orc):
+    # tol = 0 keeps every cell at full rank (k_B = |B|), so the transverse and
+    # near-field blocks together cover every ordered pair exactly once (Sec. 3):
+    # their interaction counts add up to N^2
+    rng = np.random.default_rng(41)
+    n = 3000
+    p = rng.uniform(-1, 1, (n, 3))
+    T, H = build(orc, p, "inv_r", 0.0, leaf=16)
+    for l in range(H.lmin, T.kappa + 1):
+        cl = T.cells(l)
+        for b in range(T.ncell(l)):
+            assert H.cell(l, b)["k"] == cl["count"][b]
+    far, near = H.interactions()
+    assert far + near == n * n
