@@ -44,27 +44,63 @@ PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
 M2L_SYM_HBM_MIB = ((277.0, 339.9), (94.1, 117.0))
 
 
-def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3):
-    """Oracle (plain FP64 C, OpenMP over cells) on a sample of the workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_full_inter: int, sample_n: int = 1 << 16, reps: int = 3, points=None, x=None, yd_gpu=None,
+                 direct_rows: int = 16384):
+    """Oracle (plain FP64 C, OpenMP over cells) on a sample of the workload,
+    on all host threads and on one; with the full problem's points, its
+    compensated direct sum on `direct_rows` sampled rows, which also checks
+    the GPU direct sum `yd_gpu` behind the error figures."""
     import oracle
     from paper_2203_14832_amd.workloads import workload
-    p, x = workload("c2", n=sample_n)
+    p, xs = workload("c2", n=sample_n)
     T = oracle.Tree(p, 64)
     H = oracle.H2(T, "inv_r", 1e-6)
-    H.matvec(x[:, 0])
+    H.matvec(xs[:, 0])
     t0 = time.perf_counter()
     for _ in range(reps):
-        H.matvec(x[:, 0])
+        H.matvec(xs[:, 0])
     dt = (time.perf_counter() - t0) / reps
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        H.matvec(xs[:, 0])
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
     far, near = H.interactions()
     rate = (far + near) / dt
-    return {
-        "value": rate / n_full_inter, "unit": "matvecs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    out = {
+        "value": rate / n_full_inter, "unit": "matvecs/s", "cores": threads, "kind": "oracle",
         "sample": f"oracle FP64 matvec on N={sample_n} points of the same distribution (leaf 64, tol 1e-6), "
                   f"{reps} timed matvecs, {far + near} interactions each, scaled by interaction count to "
                   f"the N=2^20 problem ({n_full_inter} interactions)",
-        "sample_seconds_per_matvec": dt,
+        "sample_seconds_per_matvec": dt, "one_thread_seconds_per_matvec": dt1,
+        "one_thread_matvecs_per_s": (far + near) / dt1 / n_full_inter, "cpu_model": cpu_model(),
     }
+    if points is not None and yd_gpu is not None:
+        n = points.shape[0]
+        rows = np.sort(np.random.default_rng(2024).choice(n, min(direct_rows, n), replace=False))
+        t0 = time.perf_counter()
+        yo = oracle.direct(points, x, "inv_r", rows=rows)
+        dtd = time.perf_counter() - t0
+        out["direct_sample"] = {
+            "rows": int(rows.size), "seconds": dtd,
+            "gpu_direct_rel_err": float(np.linalg.norm(yd_gpu[rows] - yo) / np.linalg.norm(yo)),
+            "gpu_direct_max_abs_err_over_max": float(np.abs(yd_gpu[rows] - yo).max() / np.abs(yo).max()),
+        }
+    return out
 
 
 def main():
@@ -120,14 +156,23 @@ def main():
         for _ in range(k):
             H.matvec_raw(X, Y, 1, prec)
 
-    # FP64 matvec (reference arithmetic on the same pivots)
-    run("fp64", Y64, 2)
-    torch.cuda.synchronize()
-    k64 = max(3, args.steps // 4)
-    t0 = time.perf_counter()
-    run("fp64", Y64, k64)
-    torch.cuda.synchronize()
-    fp64_ms = (time.perf_counter() - t0) / k64 * 1e3
+    # FP64 matvec (reference arithmetic on the same pivots), with the same
+    # schedule as the mixed one (symmetric transverse pass) and with the plain
+    # (every ordered pair) pass
+    def time_fp64(sym):
+        H.set_symmetric(sym)
+        run("fp64", Y64, 2)
+        torch.cuda.synchronize()
+        k64 = max(3, args.steps // 4)
+        t0 = time.perf_counter()
+        run("fp64", Y64, k64)
+        torch.cuda.synchronize()
+        H.set_symmetric(True)
+        return (time.perf_counter() - t0) / k64 * 1e3
+
+    fp64_plain_ms = time_fp64(False)
+    fp64_ms = time_fp64(True)
+    run("fp64", Y64, 1)
 
     # timed mixed-precision steps; HIP events on the library stream bracket
     # the launches of the transverse-pass kernel only
@@ -205,18 +250,24 @@ def main():
                      "peak_derivation": "7.864e13 FP32 lane-instr/s / 10 slots per pair "
                                         "(r^2: add + 3 fma; 1/r: v_rsq_f32 = 4; 2 fma)"},
         "m2l_coarse_fp64_ms_per_step": coarse_ms, "m2l_level_interactions": info["m2l_level"],
+        # both forms with the symmetric transverse pass (the same schedule)
         "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
+        # both forms with the plain pass, and the mixed default against it
+        "fp64_plain_pass_ms_per_step": fp64_plain_ms, "mixed_plain_pass_ms_per_step": ms_nosym,
+        "speedup_vs_fp64_plain_pass": fp64_plain_ms / ms_nosym,
+        "speedup_mixed_vs_fp64_plain_pass": fp64_plain_ms / ms_step,
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,
         "interactions_per_step": inter, "ms_per_step_without_events": ms_plain,
-        "mixed_plain_pass_ms_per_step": ms_nosym, "speedup_vs_fp64_plain_pass": fp64_ms / ms_nosym,
     }
+    yd = None
     if not args.no_direct:
         yd = nnca.direct(p, X.reshape(n), "inv_r", device=dev)
         torch.cuda.synchronize()
         out["err_fp64_vs_direct"] = float(torch.linalg.norm(Y64.reshape(n) - yd) / torch.linalg.norm(yd))
         out["err_mixed_vs_direct"] = float(torch.linalg.norm(Ym.reshape(n) - yd) / torch.linalg.norm(yd))
+        yd = yd.cpu().numpy()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inter)
+        out["cpu_baseline"] = cpu_baseline(inter, points=p, x=x[:, 0], yd_gpu=yd)
     print(json.dumps(out), flush=True)
 
 

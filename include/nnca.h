@@ -128,16 +128,16 @@ nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G
                                  void *stream);
 
 /* Apply options of a handle, for the matvecs issued after the call.
- *   NNCA_APPLY_NO_SYMMETRIC: the mixed form evaluates the FP32 transverse
- *     blocks of its finest levels, and the near-field blocks, for every
- *     ordered pair of cells.  By default (flags = 0) it uses the symmetric
- *     case of Sec. 5: K(x, y) = K(y, x) and B' in IL(B) <=> B in IL(B')
- *     (likewise for N(B)) make the block of (B', B) the transpose of that of
- *     (B, B'), so each unordered pair is evaluated once and used for both
- *     directions (the near field so only where near pairs exceed 1/12 of
- *     the transverse interactions).  The FP64 form always evaluates every
- *     ordered pair.  Either choice gives the product to the accuracy of the
- *     mixed form; summation orders differ.
+ *   NNCA_APPLY_NO_SYMMETRIC: both forms evaluate the transverse blocks, and
+ *     the mixed form the near-field blocks, for every ordered pair of cells.
+ *     By default (flags = 0) they use the symmetric case of Sec. 5:
+ *     K(x, y) = K(y, x) and B' in IL(B) <=> B in IL(B') (likewise for N(B))
+ *     make the block of (B', B) the transpose of that of (B, B'), so each
+ *     unordered pair is evaluated once and used for both directions (the
+ *     transverse pass of every level whose ranks are at most 256; the mixed
+ *     near field only where near pairs exceed 1/12 of the transverse
+ *     interactions).  Either choice gives the product to the accuracy of its
+ *     form; summation orders differ.
  * Errors: INVALID_ARG (NULL handle, unknown bits).                        */
 enum { NNCA_APPLY_NO_SYMMETRIC = 1 };
 nnca_status nnca_set_apply_flags(nnca_handle h, int32_t flags);

@@ -71,6 +71,7 @@ def lib():
         L.orc_h2_matvec.argtypes = [P, P, P, i64, i32]
         L.orc_h2_interactions.argtypes = [P, P]
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
         L.orc_h2_frozen.restype = P; L.orc_h2_frozen.argtypes = [P, f64]
         L.orc_h2_grad_h.restype = f64; L.orc_h2_grad_h.argtypes = [P, P, P, i32]
         L.orc_dense_grad_h.restype = f64; L.orc_dense_grad_h.argtypes = [P, i64, i32, f64, P, P]
@@ -84,6 +85,11 @@ def _p(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops (timing runs)."""
+    lib().orc_set_num_threads(int(k))
 
 
 def log(x: float) -> float:

@@ -1017,6 +1017,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Derivative with respect to the Gaussian length scale, pivots frozen        */
 /* ------------------------------------------------------------------------- */

@@ -43,6 +43,7 @@ int orc_h2_cell(const orc_h2 *H, int l, int64_t b, int64_t *mnk, int64_t *piv, i
                 int64_t *tt, double *C);
 void orc_h2_matvec(const orc_h2 *H, const double *x, double *y, int64_t nrhs, int adjoint);
 void orc_h2_interactions(const orc_h2 *H, int64_t *out);
+void orc_set_num_threads(int k);
 orc_h2 *orc_h2_frozen(const orc_h2 *H, double hnew);
 double orc_h2_grad_h(const orc_h2 *H, const double *x, const double *g, int parts);
 double orc_dense_grad_h(const double *pts, int64_t n, int d, double h, const double *x, const double *g);

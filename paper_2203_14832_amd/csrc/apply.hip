@@ -632,7 +632,11 @@ __global__ void k_transpose_blocks(int64_t nc, const int32_t *piv_ptr, const int
 //           in FP32 chunks folded into FP64, FP32 column slots;
 //   M_F64R  FP64 coordinates and products, 1/r from an FP32 seed and one
 //           FP64 Newton step, FP64 column slots (the coarse levels of the
-//           mixed matvec).
+//           mixed matvec);
+//   M_F64   FP64 throughout: coordinate differences, K = 1/sqrt(r^2)
+//           correctly rounded, FP64 products and column slots (the FP64
+//           matvec: the same schedule as the mixed one, only the arithmetic
+//           differs).
 // Levels with few cells split each cell's owned sources over P workgroups;
 // their row sums go to P partial vectors added in order by k_sum_parts.
 
@@ -700,6 +704,7 @@ struct SymArgs {
 template <int MODE> struct SymT;
 template <> struct SymT<M_F32> { using T = float; using T4 = float4; };
 template <> struct SymT<M_F64R> { using T = double; using T4 = double4; };
+template <> struct SymT<M_F64> { using T = double; using T4 = double4; };
 
 template <int MODE>
 struct SymShared {
@@ -734,13 +739,15 @@ struct SymShared {
 // the cancellation costs a few units in the last place of r^2.  FP64-refined
 // form: absolute coordinates, (|t|^2 + |s|^2) / r^2 at most a few thousand
 // (a relative error of r^2 below 1e-12, far under the FP32 rounding of the
-// finer levels).
+// finer levels).  FP64 form: r^2 from the coordinate differences, as in the
+// plain pass.
 template <int KIND, int MODE, int TPG, int R>
 __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int pp, int32_t kk)
 {
     using T = typename SymT<MODE>::T;
     using T4 = typename SymT<MODE>::T4;
     constexpr bool F32 = MODE == M_F32;
+    constexpr bool DIFF = MODE == M_F64;   // r^2 from coordinate differences
     constexpr int G = NT / TPG;
     constexpr int SPT = SYM_TS / NT;
     const int t = threadIdx.x, g = t / TPG, ti = t % TPG;
@@ -766,10 +773,12 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
         tz[r] = d == 3 ? pc[2 * npiv + q] : T(0);
         tw[r] = ok ? (T)A.w[q] : T(0);   // padding targets add nothing to column sums
         acc[r] = 0.0;
-        tn[r] = tx[r] * tx[r] + ty[r] * ty[r] + tz[r] * tz[r];
-        tx[r] *= T(-2);
-        ty[r] *= T(-2);
-        tz[r] *= T(-2);
+        if constexpr (!DIFF) {
+            tn[r] = tx[r] * tx[r] + ty[r] * ty[r] + tz[r] * tz[r];
+            tx[r] *= T(-2);
+            ty[r] *= T(-2);
+            tz[r] *= T(-2);
+        }
     }
     const T prm = (T)A.prm;
     // first owned entry holding source sb
@@ -836,7 +845,8 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
                         v[q].y += sh.esh[1][lo];
                         v[q].z += sh.esh[2][lo];
                     }
-                    sn[q] = v[q].x * v[q].x + v[q].y * v[q].y + v[q].z * v[q].z;
+                    if constexpr (!DIFF) sn[q] = v[q].x * v[q].x + v[q].y * v[q].y + v[q].z * v[q].z;
+                    else sn[q] = T(0);
                     sl[q] = sh.eslot[lo] + s;
                 }
             }
@@ -862,11 +872,18 @@ __device__ void sym_cell(const SymArgs &A, SymShared<MODE> &sh, int64_t c, int p
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     T kv_;
-                    T r2 = tn[r] + qn;
-                    r2 = fma(tz[r], q.z, r2);
-                    r2 = fma(ty[r], q.y, r2);
-                    r2 = fma(tx[r], q.x, r2);
+                    T r2;
+                    if constexpr (DIFF) {
+                        const T dx = tx[r] - q.x, dy = ty[r] - q.y, dz = tz[r] - q.z;
+                        r2 = (dx * dx + dy * dy) + dz * dz;
+                    } else {
+                        r2 = tn[r] + qn;
+                        r2 = fma(tz[r], q.z, r2);
+                        r2 = fma(ty[r], q.y, r2);
+                        r2 = fma(tx[r], q.x, r2);
+                    }
                     if constexpr (F32) kv_ = kv32<KIND>(r2, prm);
+                    else if constexpr (DIFF) kv_ = kv64<KIND>(r2, prm);
                     else kv_ = kv_refined<KIND, MODE>(r2, prm);
                     a[r] += kv_ * q.w;
                     cp += kv_ * tw[r];
@@ -1059,7 +1076,7 @@ static int sym_parts(const nnca::Level &L)
 template <int KIND, int MODE>
 static void sym_launch(int32_t max_k, int g, const SymArgs &A, hipStream_t s)
 {
-    if constexpr (MODE == M_F64R)
+    if constexpr (MODE != M_F32)
         if (max_k > 80 && max_k <= 160) {
             k_m2l_sym<KIND, MODE, 3><<<g, NT, 0, s>>>(A);
             return;
@@ -1458,8 +1475,9 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
             nnca::Level &L = H->lev[l];
             const bool sym = L.sym && !(H->apply_flags & NNCA_APPLY_NO_SYMMETRIC);
             hipEvent_t after = overlap && l == kap ? H->ev_leafk : nullptr;
-            if (f32 && sym) {   // the launcher times its kernel and its combine step apart
-                if (l <= lf64) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s, after);
+            if (sym) {   // the launcher times its kernel and its combine step apart
+                if (!f32) launch_m2l_sym<M_F64>(kind, H, L, l, prm64, s, after);
+                else if (l <= lf64) launch_m2l_sym<M_F64R>(kind, H, L, l, prm64, s, after);
                 else launch_m2l_sym<M_F32>(kind, H, L, l, (double)prm, s, after);
                 continue;
             }
@@ -1523,9 +1541,10 @@ void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p,
 // to the larger one otherwise (about half of every list each); pairs with an
 // empty cell carry nothing and are left out.  Levels whose ranks exceed
 // SYM_MAXK or whose slot count exceeds 32-bit offsets keep the plain pass.
-// fp64_slots: FP64 column slots (levels the mixed matvec runs in the
-// FP64-refined form), else FP32.
-void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots)
+// The column slots are one FP64 buffer: the FP64 and FP64-refined forms use
+// it as FP64 slots, the FP32 form (levels of the mixed matvec that run in
+// FP32) as FP32 slots.
+void prepare_symmetric(nnca_h2 *H, Level &L, bool)
 {
     if (L.sym || L.ncell < 1 || L.max_k > SYM_MAXK) return;
     const int64_t nc = L.ncell;
@@ -1579,8 +1598,8 @@ void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots)
     L.own_slot = up(oslot);
     L.non_ptr = up(nptr);
     L.non_slot = up(nslot);
-    if (fp64_slots) L.col64 = dalloc<double>(col);
-    else L.col32 = dalloc<float>(col);
+    L.col64 = dalloc<double>(col);
+    L.col32 = reinterpret_cast<float *>(L.col64);
     L.ncol = col;
     L.max_own = max_own;
     L.sym = true;

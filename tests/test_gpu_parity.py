@@ -188,11 +188,16 @@ def test_matvec_parity(built, name):
         assert rel(Ym[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c, rel(Ym[:, c], Y64[:, c]))
     # the plain (every ordered pair) FP32 transverse pass and near field give
     # the same product to the same bound; the symmetric ones are the default
+    # FP64 too: the plain transverse pass, against the oracle like the
+    # symmetric one (the default of both forms)
     G.set_symmetric(False)
     try:
         Yp = np.stack([G.matvec(Xt[:, c], "mixed").cpu().numpy() for c in range(3)], 1)
+        Y64p = np.stack([G.matvec(Xt[:, c], "fp64").cpu().numpy() for c in range(3)], 1)
     finally:
         G.set_symmetric(True)
+    assert rel(Y64p, Yo) <= 1e-12
+    close_elementwise(Y64p, Yo, 1e-12)
     for c in range(3):
         assert rel(Yp[:, c], Y64[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c)
         assert rel(Yp[:, c], Ym[:, c]) <= MIXED_TOL.get(name, 1e-6), (name, c)
