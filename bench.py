@@ -306,7 +306,7 @@ def bench_many_rhs(args):
     p, x = workload("c3")
     n, R = p.shape[0], x.shape[1]
     t0 = time.perf_counter()
-    H = nnca.H2Matrix(p, c["kernel"], c["tol"], c["leaf"], device=dev)
+    H = nnca.H2Matrix(p, c["kernel"], c["tol"], c["leaf"], device=dev, max_rhs=R)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = H.info()

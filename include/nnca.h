@@ -23,10 +23,16 @@
  *   - `stream` is a hipStream_t (NULL = the default stream).  nnca_build and
  *     the export/query functions are blocking; nnca_matvec,
  *     nnca_matvec_adjoint and nnca_direct are asynchronous on `stream`.
+ *     Successive calls on one handle are ordered even when they name
+ *     different streams (each call waits for the handle's previous one).
  *   - A handle may be used from one thread at a time.
+ *   - Device memory of a handle comes from the allocator given at build time
+ *     (default: hipMalloc / hipFree).  nnca_matvec and nnca_matvec_adjoint
+ *     allocate nothing: their workspace is sized at build time.
  */
 #ifndef NNCA_H
 #define NNCA_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -62,6 +68,19 @@ typedef enum {
  *     operators always come from the FP64 build.                           */
 typedef enum { NNCA_PREC_FP64 = 0, NNCA_PREC_MIXED = 1 } nnca_precision;
 
+/* Element type of the caller's X and Y.  The arithmetic is set by the
+ * precision alone: FP32 vectors are widened on input and rounded on
+ * output.                                                                 */
+typedef enum { NNCA_F32 = 0, NNCA_F64 = 1 } nnca_dtype;
+
+/* Caller-supplied device allocator: alloc returns `bytes` of device memory on
+ * the current device (NULL on failure), free releases a pointer alloc
+ * returned.  Both receive `ctx`.  The library frees only after the device
+ * work that uses the memory has finished (it synchronizes the device first).
+ * Every device buffer of the handle, at build and later, comes from it.    */
+typedef void *(*nnca_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*nnca_free_fn)(void *ptr, void *ctx);
+
 typedef struct {
     uint32_t struct_size;    /* sizeof(nnca_build_options)                    */
     int32_t eta2_num;        /* admissibility eta^2 = eta2_num / eta2_den;     */
@@ -74,6 +93,16 @@ typedef struct {
                                 cell that needs more is re-run with min(m, n);
                                 0 = 256.  Affects memory and speed only.      */
     int32_t reserved;
+    /* fields below: struct_size >= their end (older callers get defaults)  */
+    int32_t max_rhs;         /* columns of the many-column workspace sized at
+                                build time: 0 = 16, 1 = none (matvecs with
+                                several columns run one column at a time),
+                                else rounded up to a multiple of 16, at most
+                                64; wider X run in blocks of that width       */
+    int32_t reserved2;
+    nnca_alloc_fn alloc;     /* NULL: hipMalloc / hipFree                     */
+    nnca_free_fn free;       /*   (both or neither)                           */
+    void *alloc_ctx;
 } nnca_build_options;
 
 /* Build the H2 representation (Sec. 3 steps 1; steps 2-3 are evaluated on
@@ -92,16 +121,22 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
                        double tol, int32_t leaf_size, const nnca_build_options *opts,
                        void *stream, nnca_handle *out);
 
-/* Y = A~ X (Sec. 4) for nrhs columns.  X, Y: device FP64, original point
- * order, column-major with leading dimensions ldx, ldy >= n; X and Y must not
- * overlap.  precision is an nnca_precision.  Asynchronous on `stream`.     */
-nnca_status nnca_matvec(nnca_handle h, const double *X, double *Y, int64_t nrhs,
-                        int64_t ldx, int64_t ldy, int32_t precision, void *stream);
+/* Y = A~ X (Sec. 4) for nrhs columns.  X, Y: device memory of element type
+ * dtype (an nnca_dtype), original point order, column-major with leading
+ * dimensions ldx, ldy >= n (elements); X and Y must not overlap.  precision
+ * is an nnca_precision.  Asynchronous on `stream`; allocates nothing.
+ * Errors: INVALID_ARG (NULL handle or vectors, nrhs < 1, leading dimension
+ * < n, unknown dtype or precision, X and Y overlapping); HIP.              */
+nnca_status nnca_matvec(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                        int32_t dtype, int32_t precision, void *stream);
 
-/* Y = A~^T X: the same passes transposed (P2M <-> L2P, M2M <-> L2L, every
- * M2L and near-field block transposed).  Arguments as nnca_matvec.        */
-nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64_t nrhs,
-                                int64_t ldx, int64_t ldy, int32_t precision, void *stream);
+/* Y = A~^T X.  The library covers the symmetric case of Sec. 5 only (P = Q,
+ * K(x, y) = K(y, x)): there V_B = U_B and T_{B B_c} = C_{B_c B}^T, so the
+ * transposed passes (P2M <-> L2P, M2M <-> L2L, S_{B,B'}^T = S_{B',B}, near
+ * blocks likewise) are the forward ones and A~^T = A~; this entry point runs
+ * the forward passes.  Arguments and errors as nnca_matvec.               */
+nnca_status nnca_matvec_adjoint(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                int32_t dtype, int32_t precision, void *stream);
 
 /* Backward of Y = A~ X for a scalar loss L with G = dL/dY (device FP64,
  * column-major, original point order, like X):

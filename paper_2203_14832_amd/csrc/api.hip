@@ -2,6 +2,7 @@
 // translation, handle lifetime, parity exports.
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -25,9 +26,43 @@ void hip_check(hipError_t e, const char *what)
     }
 }
 
+static thread_local const Allocator *tl_alloc = nullptr;
+
+const Allocator *current_allocator() { return tl_alloc; }
+
+AllocScope::AllocScope(const Allocator &a) : prev(tl_alloc) { tl_alloc = &a; }
+AllocScope::~AllocScope() { tl_alloc = prev; }
+
+void *dalloc_bytes(size_t bytes)
+{
+    void *p = nullptr;
+    const Allocator *a = tl_alloc;
+    if (a && a->alloc) {
+        p = a->alloc(bytes, a->ctx);
+        if (!p) fail(NNCA_ERR_OUT_OF_MEMORY, "the caller's allocator returned NULL for " + std::to_string(bytes) +
+                                                 " bytes");
+        return p;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(NNCA_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+// A caller's allocator may hand the memory to other work at once (a caching
+// allocator), so the device is drained first, as hipFree does by itself.
 void dfree(void *p)
 {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    const Allocator *a = tl_alloc;
+    if (a && a->free) {
+        (void)hipDeviceSynchronize();
+        a->free(p, a->ctx);
+        return;
+    }
+    (void)hipFree(p);
 }
 
 }  // namespace nnca
@@ -74,6 +109,7 @@ void nnca::destroy_handle(nnca_h2 *H)
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->ev_leafk) (void)hipEventDestroy(H->ev_leafk);
+    if (H->ev_done) (void)hipEventDestroy(H->ev_done);
     for (auto &L : H->lev) {
         void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
                       L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
@@ -114,6 +150,28 @@ static void d2h_convert(const S *dev, int64_t cnt, D *host)
     for (int64_t i = 0; i < cnt; i++) host[i] = (D)tmp[i];
 }
 
+// Checks shared by the matvec entry points (nnca_matvec, its adjoint and the
+// allocation-free variant).
+void nnca::check_matvec_args(nnca_handle h, const void *X, const void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                             int32_t dtype, int32_t precision)
+{
+    if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+    if (!X || !Y) fail(NNCA_ERR_INVALID_ARG, "X or Y is NULL");
+    if (nrhs < 1) fail(NNCA_ERR_INVALID_ARG, "nrhs < 1");
+    if (ldx < h->n || ldy < h->n) fail(NNCA_ERR_INVALID_ARG, "leading dimension < n");
+    if (dtype != NNCA_F32 && dtype != NNCA_F64) fail(NNCA_ERR_INVALID_ARG, "bad dtype");
+    if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+    const int64_t es = dtype == NNCA_F32 ? 4 : 8;
+    const char *xb = (const char *)X, *xe = xb + ((nrhs - 1) * ldx + h->n) * es;
+    const char *yb = (const char *)Y, *ye = yb + ((nrhs - 1) * ldy + h->n) * es;
+    if (xb < ye && yb < xe) fail(NNCA_ERR_INVALID_ARG, "X and Y overlap");
+}
+
+// Calls on one handle share its workspace: each waits for the end of the
+// previous one (recorded on that call's stream), whatever stream it names.
+void nnca::order_call_begin(nnca_handle h, hipStream_t s) { HIPCHECK(hipStreamWaitEvent(s, h->ev_done, 0)); }
+void nnca::order_call_end(nnca_handle h, hipStream_t s) { HIPCHECK(hipEventRecord(h->ev_done, s)); }
+
 extern "C" {
 
 nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t points_on_device,
@@ -133,9 +191,17 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
         o.struct_size = sizeof(o);
         o.exhausted_policy = 1;
         if (opts) {
-            if (opts->struct_size < sizeof(nnca_build_options)) fail(NNCA_ERR_INVALID_ARG, "bad struct_size");
-            o = *opts;
+            // callers built against the first version of the struct end at
+            // `reserved`; the fields after it keep their defaults
+            const size_t v1 = offsetof(nnca_build_options, max_rhs);
+            if (opts->struct_size != v1 && opts->struct_size < sizeof(nnca_build_options))
+                fail(NNCA_ERR_INVALID_ARG, "bad struct_size");
+            std::memcpy(&o, opts, opts->struct_size < sizeof(o) ? opts->struct_size : sizeof(o));
+            o.struct_size = sizeof(o);
         }
+        if ((o.alloc == nullptr) != (o.free == nullptr))
+            fail(NNCA_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+        if (o.max_rhs < 0) fail(NNCA_ERR_INVALID_ARG, "max_rhs < 0");
         if ((o.eta2_num == 0) != (o.eta2_den == 0) || o.eta2_num < 0 || o.eta2_den < 0)
             fail(NNCA_ERR_INVALID_ARG, "eta2 must be a positive fraction or 0/0");
         if (o.exhausted_policy != 0 && o.exhausted_policy != 1) fail(NNCA_ERR_INVALID_ARG, "bad exhausted_policy");
@@ -155,6 +221,11 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
         if (o.rank_reserve < 0) fail(NNCA_ERR_INVALID_ARG, "rank_reserve < 0");
         H->rank_reserve = o.rank_reserve > 0 ? o.rank_reserve : 256;
         H->stream = (hipStream_t)stream;
+        H->alloc.alloc = o.alloc;
+        H->alloc.free = o.free;
+        H->alloc.ctx = o.alloc_ctx;
+        H->max_rhs = o.max_rhs == 0 ? 16 : (o.max_rhs > 64 ? 64 : o.max_rhs);
+        AllocScope as(H->alloc);
         try {
             double *pin = nullptr;
             int64_t pld = ld;
@@ -178,6 +249,7 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
             }
             build_pivots(H);
             prepare_apply(H);
+            HIPCHECK(hipEventCreateWithFlags(&H->ev_done, hipEventDisableTiming));
             HIPCHECK(hipStreamSynchronize(H->stream));
         } catch (...) {
             (void)hipStreamSynchronize(H->stream);
@@ -189,26 +261,23 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
     });
 }
 
-static nnca_status matvec_common(nnca_handle h, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                                 int32_t precision, void *stream)
+static nnca_status matvec_common(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                 int32_t dtype, int32_t precision, void *stream)
 {
     return guarded([&] {
-        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
-        if (!X || !Y) fail(NNCA_ERR_INVALID_ARG, "X or Y is NULL");
-        if (nrhs < 1) fail(NNCA_ERR_INVALID_ARG, "nrhs < 1");
-        if (ldx < h->n || ldy < h->n) fail(NNCA_ERR_INVALID_ARG, "leading dimension < n");
-        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
-        const char *xb = (const char *)X, *xe = (const char *)(X + (nrhs - 1) * ldx + h->n);
-        const char *yb = (const char *)Y, *ye = (const char *)(Y + (nrhs - 1) * ldy + h->n);
-        if (xb < ye && yb < xe) fail(NNCA_ERR_INVALID_ARG, "X and Y overlap");
-        run_matvec(h, X, Y, nrhs, ldx, ldy, precision, (hipStream_t)stream);
+        check_matvec_args(h, X, Y, nrhs, ldx, ldy, dtype, precision);
+        AllocScope as(h->alloc);
+        const hipStream_t s = (hipStream_t)stream;
+        order_call_begin(h, s);
+        run_matvec(h, X, Y, nrhs, ldx, ldy, dtype, precision, s);
+        order_call_end(h, s);
     });
 }
 
-nnca_status nnca_matvec(nnca_handle h, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                        int32_t precision, void *stream)
+nnca_status nnca_matvec(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                        int32_t dtype, int32_t precision, void *stream)
 {
-    return matvec_common(h, X, Y, nrhs, ldx, ldy, precision, stream);
+    return matvec_common(h, X, Y, nrhs, ldx, ldy, dtype, precision, stream);
 }
 
 // In the symmetric case of Sec. 5 (P = Q, K(x,y) = K(y,x), V_B = U_B,
@@ -216,10 +285,10 @@ nnca_status nnca_matvec(nnca_handle h, const double *X, double *Y, int64_t nrhs,
 // ones: P2M^T = L2P, M2M^T = L2L, and every block S_{B,B'}^T = S_{B',B} with
 // B' in IL(B) <=> B in IL(B'), near blocks likewise.  The adjoint therefore
 // runs the same kernels.
-nnca_status nnca_matvec_adjoint(nnca_handle h, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                                int32_t precision, void *stream)
+nnca_status nnca_matvec_adjoint(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                int32_t dtype, int32_t precision, void *stream)
 {
-    return matvec_common(h, X, Y, nrhs, ldx, ldy, precision, stream);
+    return matvec_common(h, X, Y, nrhs, ldx, ldy, dtype, precision, stream);
 }
 
 nnca_status nnca_set_apply_flags(nnca_handle h, int32_t flags)
@@ -261,7 +330,11 @@ nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G
                 if (d.first < q + sizeof(double) && q < d.second) fail(NNCA_ERR_INVALID_ARG, "DX and dLdh overlap");
             }
         }
-        run_backward(h, X, G, nrhs, ldx, ldg, precision, DX, lddx, dLdh, (hipStream_t)stream);
+        AllocScope as(h->alloc);
+        const hipStream_t s = (hipStream_t)stream;
+        order_call_begin(h, s);
+        run_backward(h, X, G, nrhs, ldx, ldg, precision, DX, lddx, dLdh, s);
+        order_call_end(h, s);
     });
 }
 
@@ -273,6 +346,7 @@ nnca_status nnca_batch_create(const nnca_handle *handles, int32_t count, int32_t
         if (flags & ~(NNCA_BATCH_GRAPH | NNCA_BATCH_AUTOTUNE)) fail(NNCA_ERR_INVALID_ARG, "unknown flags");
         for (int32_t b = 0; b < count; b++)
             if (!handles[b]) fail(NNCA_ERR_INVALID_ARG, "a handle is NULL");
+        AllocScope as(handles[0]->alloc);
         *out = create_batch(handles, count, flags);
     });
 }
@@ -300,13 +374,19 @@ nnca_status nnca_batch_matvec(nnca_batch_handle b, const double *X, double *Y, i
         const char *xb = (const char *)X, *xe = (const char *)(X + (nrhs - 1) * ldx + n);
         const char *yb = (const char *)Y, *ye = (const char *)(Y + (nrhs - 1) * ldy + n);
         if (xb < ye && yb < xe) fail(NNCA_ERR_INVALID_ARG, "X and Y overlap");
+        AllocScope as(*batch_allocator(b));
         run_batch(b, X, Y, nrhs, ldx, ldy, precision, (hipStream_t)stream);
     });
 }
 
 nnca_status nnca_batch_destroy(nnca_batch_handle b)
 {
-    return guarded([&] { destroy_batch(b); });
+    return guarded([&] {
+        if (!b) return;
+        const Allocator a = *batch_allocator(b);
+        AllocScope as(a);
+        destroy_batch(b);
+    });
 }
 
 nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t kernel_kind,
@@ -481,6 +561,9 @@ nnca_status nnca_destroy(nnca_handle h)
     return guarded([&] {
         if (h) {
             (void)hipStreamSynchronize(h->stream);
+            if (h->ev_done) (void)hipEventSynchronize(h->ev_done);
+            const Allocator a = h->alloc;
+            AllocScope as(a);
             destroy_handle(h);
         }
     });

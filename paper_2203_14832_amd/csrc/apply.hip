@@ -35,17 +35,20 @@ template <> struct V4<double> { using type = double4; };
 // ---------------------------------------------------------------------------
 // input gather (original -> tree order) and split
 
-__global__ void k_gather64(int64_t n, const int32_t *order, const double *x, double *xs)
+// TI: element type of the caller's vector (FP32 input is widened exactly)
+template <typename TI>
+__global__ void k_gather64(int64_t n, const int32_t *order, const TI *x, double *xs)
 {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < n) xs[p] = x[order[p]];
+    if (p < n) xs[p] = (double)x[order[p]];
 }
 
-__global__ void k_gather_split(int64_t n, const int32_t *order, const double *x, double *xs, float *hi, float *lo)
+template <typename TI>
+__global__ void k_gather_split(int64_t n, const int32_t *order, const TI *x, double *xs, float *hi, float *lo)
 {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
-    double v = x[order[p]];
+    double v = (double)x[order[p]];
     xs[p] = v;
     float h = (float)v;
     hi[p] = h;
@@ -132,13 +135,15 @@ __global__ __launch_bounds__(256) void k_up_cell(const int32_t *piv_ptr, const i
 
 // y_j = near + far of the point whose tree position is rank_j: random reads,
 // contiguous writes (the same sum, in the same order, as adding the far field
-// to the near-field sums in place)
-__global__ void k_near_far_out(int64_t n, const int32_t *rank, const double *near, const double *far, double *y)
+// to the near-field sums in place).  far may be NULL (no far field).  TO: the
+// caller's element type (FP32 output is the rounded FP64 sum).
+template <typename TO>
+__global__ void k_near_far_out(int64_t n, const int32_t *rank, const double *near, const double *far, TO *y)
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int32_t p = rank[j];
-    y[j] = near[p] + far[p];
+    y[j] = (TO)(far ? near[p] + far[p] : near[p]);
 }
 
 __global__ void k_invert_order(int64_t n, const int32_t *order, int32_t *rank)
@@ -1013,12 +1018,7 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
     const int P = m2l_parts(L);
     double *part = nullptr;
     if (P > 1) {
-        if (H->m2l_part_cap < (int64_t)P * L.npiv) {
-            dfree(H->m2l_part);
-            H->m2l_part = nullptr;
-            H->m2l_part = dalloc<double>((int64_t)P * L.npiv);
-            H->m2l_part_cap = (int64_t)P * L.npiv;
-        }
+        if (H->m2l_part_cap < (int64_t)P * L.npiv) fail(NNCA_ERR_INTERNAL, "split workspace not sized");
         part = H->m2l_part;
     }
     const int g = (int)(nc * P);
@@ -1096,12 +1096,7 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
     const int P = sym_parts(L);
     double *part = nullptr;
     if (P > 1) {
-        if (H->m2l_part_cap < (int64_t)P * L.npiv) {
-            dfree(H->m2l_part);
-            H->m2l_part = nullptr;
-            H->m2l_part = dalloc<double>((int64_t)P * L.npiv);
-            H->m2l_part_cap = (int64_t)P * L.npiv;
-        }
+        if (H->m2l_part_cap < (int64_t)P * L.npiv) fail(NNCA_ERR_INTERNAL, "split workspace not sized");
         part = H->m2l_part;
     }
     SymArgs A{L.k, L.piv_ptr, L.own_ptr, L.own_il, L.own_pre, L.own_sum, L.own_slot, L.pc32, L.pc64, L.npiv, nc,
@@ -1397,8 +1392,8 @@ static void launch_p2p_sym(int kind, nnca_h2 *H, const float *xhi, const float *
 // levels then hold every multipole vector and every local vector, the latter
 // with all contributions of the coarser levels added).
 template <typename T>
-void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, double *y, hipStream_t s, int kind,
-                bool do_up, bool do_p2p)
+void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, void *y, bool y32, hipStream_t s,
+                int kind, bool do_up, bool do_p2p)
 {
     const bool f32 = sizeof(T) == 4;
     const int kap = H->kappa, lmin = H->lmin;
@@ -1506,34 +1501,52 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, doub
         if (overlap) {
             HIPCHECK(hipStreamWaitEvent(s, H->ev_join, 0));
             Span sp(H, s, PASS_DOWN, kap);
-            k_near_far_out<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->rank, H->near64, far, y);
+            if (y32)
+                k_near_far_out<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->rank, H->near64, far, (float *)y);
+            else
+                k_near_far_out<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->rank, H->near64, far, (double *)y);
             HIPCHECK(hipGetLastError());
         }
     }
     if (!do_p2p || overlap) return;
-    // near field alone (no far field)
+    // near field alone (no far field): in tree order, then y
     Span sp(H, s, PASS_P2P, kap);
-    if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, y, prm, s);
-    else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, y, prm, s);
+    if (f32) launch_p2p<T>(kind, H, xhi, xlo, nullptr, H->near64, prm, s, 0, -1, true);
+    else launch_p2p<T>(kind, H, (const T *)xs64, nullptr, nullptr, H->near64, prm, s, 0, -1, true);
+    if (y32)
+        k_near_far_out<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->rank, H->near64, nullptr, (float *)y);
+    else
+        k_near_far_out<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->rank, H->near64, nullptr, (double *)y);
+    HIPCHECK(hipGetLastError());
 }
 
 }  // namespace
 
-void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s)
+template <typename TI>
+static void gather_typed(nnca_h2 *H, const TI *x, int precision, hipStream_t s)
 {
     const int64_t n = H->n;
     Span sp(H, s, PASS_GATHER, -1);
     if (precision == NNCA_PREC_MIXED)
-        k_gather_split<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64, H->xhi, H->xlo);
+        k_gather_split<TI><<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64, H->xhi, H->xlo);
     else
-        k_gather64<<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64);
+        k_gather64<TI><<<grid_for(n, 256), 256, 0, s>>>(n, H->order, x, H->xs64);
     HIPCHECK(hipGetLastError());
+}
+
+void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s) { gather_typed(H, x, precision, s); }
+
+static void column_passes_io(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, void *y, bool y32,
+                             hipStream_t s)
+{
+    if (precision == NNCA_PREC_MIXED)
+        one_column<float>(H, H->xs64, H->xhi, H->xlo, y, y32, s, kind, do_up, do_p2p);
+    else one_column<double>(H, H->xs64, nullptr, nullptr, y, y32, s, kind, do_up, do_p2p);
 }
 
 void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p, double *y, hipStream_t s)
 {
-    if (precision == NNCA_PREC_MIXED) one_column<float>(H, H->xs64, H->xhi, H->xlo, y, s, kind, do_up, do_p2p);
-    else one_column<double>(H, H->xs64, nullptr, nullptr, y, s, kind, do_up, do_p2p);
+    column_passes_io(H, precision, kind, do_up, do_p2p, y, false, s);
 }
 
 // Ownership of the interacting pairs of a level for the symmetric transverse
@@ -1664,8 +1677,9 @@ static void prepare_p2p_sym(nnca_h2 *H, const std::vector<int32_t> &hc)
     H->pnon_ptr = up(nptr);
     H->pnon_slot = up(nslot);
     H->pcell = up(pc);
-    H->pcol_hi = dalloc<float>(col > 0 ? col : 1);
-    H->pcol_lo = dalloc<float>(col > 0 ? col : 1);
+    H->pcol_n = col > 0 ? col : 1;
+    H->pcol_hi = dalloc<float>(H->pcol_n);
+    H->pcol_lo = dalloc<float>(H->pcol_n);
     H->prow = dalloc<double>(2 * n);
     H->p2p_sym = true;
 }
@@ -1769,6 +1783,7 @@ void prepare_apply(nnca_h2 *H)
     prepare_output(H, s);
     H->xhi = dalloc<float>(H->n);
     H->xlo = dalloc<float>(H->n);
+    prepare_workspace(H);
 }
 
 // Levels of the mixed matvec whose transverse pass runs in FP32, counted
@@ -1780,17 +1795,47 @@ void prepare_apply(nnca_h2 *H)
 // operators have the largest entries.
 int mixed_fp32_levels(int kind) { return kind == NNCA_K_INV_R ? 2 : 1; }
 
-void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
-                hipStream_t s)
+void run_matvec(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
+                int precision, hipStream_t s)
 {
-    if (nrhs > 1) {
-        run_matvec_multi(H, X, Y, nrhs, ldx, ldy, precision, s);
+    // several columns: the many-column path where its workspace exists
+    if (nrhs > 1 && H->multi.rp > 0) {
+        run_matvec_multi(H, X, Y, nrhs, ldx, ldy, dtype, precision, s);
         return;
     }
+    run_matvec_columns(H, X, Y, nrhs, ldx, ldy, dtype, precision, s);
+}
+
+void run_matvec_columns(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
+                        int precision, hipStream_t s)
+{
+    const bool f32 = dtype == NNCA_F32;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
     for (int64_t col = 0; col < nrhs; col++) {
-        gather_input(H, X + col * ldx, precision, s);
-        column_passes(H, precision, H->kind, true, true, Y + col * ldy, s);
+        const char *x = (const char *)X + col * ldx * es;
+        char *y = (char *)Y + col * ldy * es;
+        if (f32) gather_typed(H, (const float *)x, precision, s);
+        else gather_typed(H, (const double *)x, precision, s);
+        column_passes_io(H, precision, H->kind, true, true, y, f32, s);
     }
+}
+
+void prepare_workspace(nnca_h2 *H)
+{
+    // partial vectors of the split one-column transverse launches: the larger
+    // split of the plain and the symmetric pass on every level
+    int64_t part = 0;
+    for (int l = H->lmin; l <= H->kappa; l++) {
+        const Level &L = H->lev[l];
+        if (!L.has_piv) continue;
+        const int P = std::max(m2l_parts(L), sym_parts(L));
+        if (P > 1) part = std::max(part, (int64_t)P * L.npiv);
+    }
+    if (part > 0) {
+        H->m2l_part = dalloc<double>(part);
+        H->m2l_part_cap = part;
+    }
+    if (H->max_rhs > 1) alloc_multi(H, (std::min(H->max_rhs, 64) + 15) / 16 * 16);
 }
 
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam, const double *X,

@@ -32,7 +32,8 @@ constexpr int NT = 256;
 // x_hi / x_lo split of the mixed form.  A workgroup takes 64 consecutive
 // original indices: it reads each column's 64 entries (contiguous) into LDS,
 // then writes each point's row of RP values at its tree position.
-__global__ __launch_bounds__(256) void k_gather_multi(int64_t n, int R, int RP, const int32_t *rank, const double *X,
+template <typename TI>
+__global__ __launch_bounds__(256) void k_gather_multi(int64_t n, int R, int RP, const int32_t *rank, const TI *X,
                                                       int64_t ldx, double *xs, float *hi, float *lo)
 {
     __shared__ double tile[64 * 65];   // [point][column], rows padded against bank conflicts
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(256) void k_gather_multi(int64_t n, int R, int RP, 
     {
         const int jj = t & 63;
         for (int c = t >> 6; c < RP; c += 4)
-            tile[jj * 65 + c] = (c < R && jj < jn) ? X[(int64_t)c * ldx + j0 + jj] : 0.0;
+            tile[jj * 65 + c] = (c < R && jj < jn) ? (double)X[(int64_t)c * ldx + j0 + jj] : 0.0;
     }
     __syncthreads();
     const int ppr = 256 / RP;   // rows written per round
@@ -65,8 +66,9 @@ __global__ __launch_bounds__(256) void k_gather_multi(int64_t n, int R, int RP, 
 // ldy), columns below R.  A workgroup reads the rows of 64 consecutive
 // original indices (contiguous) into LDS and writes each column's 64 entries
 // (contiguous).
+template <typename TO>
 __global__ __launch_bounds__(256) void k_scatter_multi(int64_t n, int R, int RP, const int32_t *rank, const double *yt,
-                                                       double *Y, int64_t ldy)
+                                                       TO *Y, int64_t ldy)
 {
     __shared__ double tile[64 * 65];
     const int t = threadIdx.x;
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(256) void k_scatter_multi(int64_t n, int R, int RP,
     __syncthreads();
     const int jj = t & 63;
     if (jj < jn)
-        for (int c = t >> 6; c < R; c += 4) Y[(int64_t)c * ldy + j0 + jj] = tile[jj * 65 + c];
+        for (int c = t >> 6; c < R; c += 4) Y[(int64_t)c * ldy + j0 + jj] = (TO)tile[jj * 65 + c];
 }
 
 // Transfer passes for RP columns (Sec. 4).  One wavefront per (cell, 64 rows,
@@ -858,30 +860,24 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
     }
 }
 
-// partial-result workspace for the split factors in use (never inside a
-// captured region: the first call with a new table allocates)
-void ensure_part(nnca_h2 *H, int RP, const std::vector<int32_t> *tab)
+// the partial-result workspace (sized once, for the default split factors
+// at the workspace width) holds the split factors in use
+void check_part(nnca_h2 *H, int RP, const std::vector<int32_t> *tab)
 {
     auto &W = H->multi;
-    int64_t need = 1;
     for (int l = H->lmin; l <= H->kappa; l++) {
         const Level &L = H->lev[l];
         const int P = tab ? (*tab)[l] : parts_for(L);
-        if (P > 1) need = std::max(need, (int64_t)P * L.npiv * RP);
+        if (P > 1 && (int64_t)P * L.npiv * RP > W.part_cap) fail(NNCA_ERR_INTERNAL, "split workspace not sized");
     }
-    if (W.part_cap >= need) return;
-    dfree(W.part);
-    W.part = nullptr;
-    W.part = dalloc<double>(need);
-    W.part_cap = need;
 }
 
 // Autotuner of the transverse pass: for every level, time the launch (and the
 // ordered sum of the partial vectors) for split factors P = 1, 2, 4, ..., 64
 // on the multipole vectors already in place, and keep the fastest.  Factors
 // that leave a part without a full source tile, put more than 2^18
-// workgroups in flight or need more than 1 GiB of partial vectors are not
-// tried.
+// workgroups in flight or need more partial vectors than the workspace holds
+// are not tried.
 template <int NCB>
 std::vector<int32_t> tune_m2l_multi(nnca_h2 *H, bool mixed, hipStream_t s)
 {
@@ -897,14 +893,11 @@ std::vector<int32_t> tune_m2l_multi(nnca_h2 *H, bool mixed, hipStream_t s)
             for (int P = 1; P <= 64; P *= 2) {
                 if (P > 1 && (int64_t)P * 128 > L.max_ilsum) break;
                 if ((int64_t)P * L.ncell > (1 << 18)) break;
-                if ((int64_t)P * L.npiv * RP * 8 > ((int64_t)1 << 30)) break;
+                if (P > 1 && (int64_t)P * L.npiv * RP > H->multi.part_cap) break;
                 cand.push_back(P);
             }
             float tbest = 0.f;
             for (int32_t P : cand) {
-                std::vector<int32_t> one(H->kappa + 1, 1);
-                one[l] = P;
-                ensure_part(H, RP, &one);
                 m2l_level_multi<NCB>(H, l, P, mixed, s);   // warm
                 HIPCHECK(hipEventRecord(a, s));
                 for (int rep = 0; rep < 3; rep++) m2l_level_multi<NCB>(H, l, P, mixed, s);
@@ -928,9 +921,8 @@ std::vector<int32_t> tune_m2l_multi(nnca_h2 *H, bool mixed, hipStream_t s)
     return best;
 }
 
-template <int NCB>
-void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int64_t ldy, int precision,
-                 hipStream_t s)
+template <int NCB, typename TI, typename TO>
+void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy, int precision, hipStream_t s)
 {
     constexpr int RP = NCB * 16;
     const int64_t n = H->n;
@@ -938,8 +930,8 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     const bool mixed = precision == NNCA_PREC_MIXED;
     const int kind = H->kind;
     auto &W = H->multi;
-    k_gather_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, X, ldx, W.xs, mixed ? W.xhi : nullptr,
-                                                             mixed ? W.xlo : nullptr);
+    k_gather_multi<TI><<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, X, ldx, W.xs,
+                                                                 mixed ? W.xhi : nullptr, mixed ? W.xlo : nullptr);
     HIPCHECK(hipGetLastError());
     const double prm64 = 1.0 / (H->hparam * H->hparam);
     const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
@@ -973,7 +965,7 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
             if (it == H->m2l_tuned.end()) it = H->m2l_tuned.emplace(key, tune_m2l_multi<NCB>(H, mixed, s)).first;
             tab = &it->second;
         }
-        ensure_part(H, RP, tab);
+        check_part(H, RP, tab);
         for (int l = lmin; l <= kap; l++) m2l_level_multi<NCB>(H, l, tab ? (*tab)[l] : parts_for(H->lev[l]), mixed, s);
         far = W.far;
         for (int l = lmin; l <= kap; l++) {
@@ -1005,14 +997,19 @@ void multi_block(nnca_h2 *H, const double *X, double *Y, int R, int64_t ldx, int
     }
 #undef PP
     HIPCHECK(hipGetLastError());
-    k_scatter_multi<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, W.far, Y, ldy);
+    k_scatter_multi<TO><<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, W.far, Y, ldy);
     HIPCHECK(hipGetLastError());
 }
 
-void ensure_multi(nnca_h2 *H, int RP)
+}  // namespace
+
+// many-column workspace for blocks of up to RP (a multiple of 16, <= 64)
+// columns: tree-order inputs and outputs, the multipole and local vectors of
+// every level, FP32 copies of the multipole vectors of the FP32 levels, and
+// the partial vectors of the default split factors
+void alloc_multi(nnca_h2 *H, int RP)
 {
     auto &W = H->multi;
-    if (W.rp >= RP) return;
     free_multi(H);
     const int64_t n = H->n;
     W.xs = dalloc<double>(n * RP);
@@ -1035,8 +1032,6 @@ void ensure_multi(nnca_h2 *H, int RP)
     W.rp = RP;
 }
 
-}  // namespace
-
 void free_multi(nnca_h2 *H)
 {
     auto &W = H->multi;
@@ -1047,15 +1042,16 @@ void free_multi(nnca_h2 *H)
     W = nnca_h2::Multi();
 }
 
-void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                      int precision, hipStream_t s)
+template <typename TI, typename TO>
+static void multi_typed(nnca_h2 *H, const TI *X, TO *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
+                        hipStream_t s)
 {
-    for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
-        const int R = (int)std::min<int64_t>(64, nrhs - c0);
+    const int width = H->multi.rp;   // blocks of the workspace's width
+    for (int64_t c0 = 0; c0 < nrhs; c0 += width) {
+        const int R = (int)std::min<int64_t>(width, nrhs - c0);
         const int NCB = (R + 15) / 16;
-        ensure_multi(H, NCB * 16);
-        const double *Xb = X + c0 * ldx;
-        double *Yb = Y + c0 * ldy;
+        const TI *Xb = X + c0 * ldx;
+        TO *Yb = Y + c0 * ldy;
         switch (NCB) {
         case 1: multi_block<1>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
         case 2: multi_block<2>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
@@ -1063,6 +1059,14 @@ void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int6
         default: multi_block<4>(H, Xb, Yb, R, ldx, ldy, precision, s); break;
         }
     }
+}
+
+void run_matvec_multi(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
+                      int precision, hipStream_t s)
+{
+    if (H->multi.rp < 16) fail(NNCA_ERR_INTERNAL, "many-column workspace missing");
+    if (dtype == NNCA_F32) multi_typed(H, (const float *)X, (float *)Y, nrhs, ldx, ldy, precision, s);
+    else multi_typed(H, (const double *)X, (double *)Y, nrhs, ldx, ldy, precision, s);
 }
 
 }  // namespace nnca

@@ -136,6 +136,9 @@ nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags)
         M->hparam = H0.hparam;
         M->stream = s;
         M->autotune = (flags & NNCA_BATCH_AUTOTUNE) != 0;
+        M->alloc = H0.alloc;   // the batch's memory comes from the first handle's allocator
+        M->max_rhs = 1;
+        for (int32_t b = 0; b < count; b++) M->max_rhs = std::max(M->max_rhs, hs[b]->max_rhs);
         B->off.assign(count + 1, 0);
         int S = 0;
         for (int32_t b = 0; b < count; b++) {
@@ -285,6 +288,7 @@ nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags)
         prepare_output(M, s);
         M->xhi = dalloc<float>(N);
         M->xlo = dalloc<float>(N);
+        prepare_workspace(M);
         HIPCHECK(hipStreamSynchronize(s));
     } catch (...) {
         destroy_batch(B);
@@ -299,7 +303,7 @@ void run_batch(nnca_batch *B, const double *X, double *Y, int64_t nrhs, int64_t 
     HIPCHECK(hipEventRecord(B->ev_in, cs));
     HIPCHECK(hipStreamWaitEvent(B->gs, B->ev_in, 0));
     if (!B->use_graph) {
-        run_matvec(B->M, X, Y, nrhs, ldx, ldy, precision, B->gs);
+        run_matvec(B->M, X, Y, nrhs, ldx, ldy, NNCA_F64, precision, B->gs);
     } else {
         nnca_batch::Key k;
         k.X = X;
@@ -315,11 +319,11 @@ void run_batch(nnca_batch *B, const double *X, double *Y, int64_t nrhs, int64_t 
             B->graph = nullptr;
             B->have_graph = false;
             // eager run: workspaces and tuned split factors exist before capture
-            run_matvec(B->M, X, Y, nrhs, ldx, ldy, precision, B->gs);
+            run_matvec(B->M, X, Y, nrhs, ldx, ldy, NNCA_F64, precision, B->gs);
             HIPCHECK(hipStreamSynchronize(B->gs));
             HIPCHECK(hipStreamBeginCapture(B->gs, hipStreamCaptureModeThreadLocal));
             try {
-                run_matvec(B->M, X, Y, nrhs, ldx, ldy, precision, B->gs);
+                run_matvec(B->M, X, Y, nrhs, ldx, ldy, NNCA_F64, precision, B->gs);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(B->gs, &g);
@@ -338,6 +342,7 @@ void run_batch(nnca_batch *B, const double *X, double *Y, int64_t nrhs, int64_t 
 }
 
 int64_t batch_rows(const nnca_batch *B) { return B->off[B->count]; }
+const Allocator *batch_allocator(const nnca_batch *B) { return &B->M->alloc; }
 int32_t batch_count(const nnca_batch *B) { return B->count; }
 const int64_t *batch_offsets(const nnca_batch *B) { return B->off.data(); }
 

@@ -321,7 +321,7 @@ void run_backward(nnca_h2 *H, const double *X, const double *Gv, int64_t nrhs, i
                   int precision, double *DX, int64_t lddx, double *dldh, hipStream_t s)
 {
     if (!dldh) {   // the gradient with respect to x alone: A~^T G = A~ G
-        run_matvec(H, Gv, DX, nrhs, ldg, lddx, precision, s);
+        run_matvec(H, Gv, DX, nrhs, ldg, lddx, NNCA_F64, precision, s);
         return;
     }
     if (H->kind != NNCA_K_GAUSS) fail(NNCA_ERR_NOT_SUPPORTED, "length-scale derivative needs the Gaussian kernel");

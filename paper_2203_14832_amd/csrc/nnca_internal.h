@@ -22,18 +22,29 @@ void set_error(const std::string &msg);
 void hip_check(hipError_t e, const char *what);
 #define HIPCHECK(x) ::nnca::hip_check((x), #x)
 
+// Device allocator of a handle (the caller's, or hipMalloc / hipFree when
+// both functions are NULL).  Every ABI call that may allocate or free
+// installs its handle's allocator for the calling thread (AllocScope); dalloc
+// and dfree use the installed one.
+struct Allocator {
+    nnca_alloc_fn alloc = nullptr;
+    nnca_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+const Allocator *current_allocator();
+struct AllocScope {
+    const Allocator *prev;
+    explicit AllocScope(const Allocator &a);
+    ~AllocScope();
+};
+void *dalloc_bytes(size_t bytes);
+
 // Device allocation owned by the library (freed with the handle).
 template <typename T>
 T *dalloc(size_t count)
 {
-    void *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(NNCA_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
-    return static_cast<T *>(p);
+    return static_cast<T *>(dalloc_bytes(count * sizeof(T)));
 }
 void dfree(void *p);
 
@@ -115,6 +126,9 @@ struct nnca_h2 {
     int64_t ws_budget = 0;
     int32_t rank_reserve = 256;
     int32_t apply_flags = 0;      // NNCA_APPLY_* bits
+    nnca::Allocator alloc;        // device memory of the handle
+    int32_t max_rhs = 16;         // columns of the many-column workspace (1: none)
+    hipEvent_t ev_done = nullptr; // end of the last matvec (orders calls across streams)
     int32_t fp32_levels = 2;      // mixed matvec: finest levels whose transverse pass runs in FP32
     int32_t kmax = 20, kappa = 0, lmin = 1;
     double lo[3] = {0, 0, 0}, L = 0.0;
@@ -149,6 +163,7 @@ struct nnca_h2 {
     int32_t *pown_slot = nullptr, *pnon_ptr = nullptr, *pnon_slot = nullptr, *pcell = nullptr;
     float *pcol_hi = nullptr, *pcol_lo = nullptr;
     double *prow = nullptr;
+    int64_t pcol_n = 0;           // entries of pcol_hi and of pcol_lo
     double *m2l_part = nullptr;   // partial M2L vectors of split launches
     int64_t m2l_part_cap = 0;
 
@@ -205,10 +220,19 @@ void debug_kernel_eval(int kind, double hparam, int dim, const double *a, const 
                        int64_t count, double *out, hipStream_t s);
 // apply.hip
 void prepare_apply(nnca_h2 *H);
-void run_matvec(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+// X, Y of element type dtype (NNCA_F32 / NNCA_F64)
+void run_matvec(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
                 int precision, hipStream_t s);
-void run_matvec_multi(nnca_h2 *H, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+void run_matvec_multi(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
                       int precision, hipStream_t s);
+// one column at a time (the one-column passes), whatever nrhs
+void run_matvec_columns(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
+                        int precision, hipStream_t s);
+// workspace of the matvec, allocated once (build, batch creation): split
+// partial vectors of the one-column transverse pass and the many-column
+// buffers for H->max_rhs columns
+void prepare_workspace(nnca_h2 *H);
+void alloc_multi(nnca_h2 *H, int RP);
 void free_multi(nnca_h2 *H);
 void gather_input(nnca_h2 *H, const double *x, int precision, hipStream_t s);
 void prepare_symmetric(nnca_h2 *H, Level &L, bool fp64_slots);
@@ -221,12 +245,17 @@ void run_backward(nnca_h2 *H, const double *X, const double *G, int64_t nrhs, in
 void free_grad(nnca_h2 *H);
 // api.hip
 void destroy_handle(nnca_h2 *H);
+void check_matvec_args(nnca_h2 *h, const void *X, const void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                       int32_t dtype, int32_t precision);
+void order_call_begin(nnca_h2 *h, hipStream_t s);
+void order_call_end(nnca_h2 *h, hipStream_t s);
 // batch.hip
 nnca_batch *create_batch(nnca_h2 *const *hs, int32_t count, int32_t flags);
 void destroy_batch(nnca_batch *B);
 void run_batch(nnca_batch *B, const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int precision,
                hipStream_t cs);
 int64_t batch_rows(const nnca_batch *B);
+const Allocator *batch_allocator(const nnca_batch *B);
 int32_t batch_count(const nnca_batch *B);
 const int64_t *batch_offsets(const nnca_batch *B);
 enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4, PASS_M2L_COMBINE = 5 };

@@ -19,7 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libnnca.so")
 
 KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
+DTYPE_F32, DTYPE_F64 = 0, 1
 MAX_LEVELS = 64
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class NncaError(RuntimeError):
@@ -31,7 +35,48 @@ class NncaError(RuntimeError):
 class BuildOptions(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("eta2_num", C.c_int32), ("eta2_den", C.c_int32),
                 ("exhausted_policy", C.c_int32), ("workspace_bytes", C.c_int64), ("rank_reserve", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("max_rhs", C.c_int32), ("reserved2", C.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+# Device memory of the handles built with allocator="torch": the torch
+# caching allocator, through the C ABI's allocator hooks.  Each handle gets a
+# context number; its record counts the calls (a batch made from handles
+# keeps using the first handle's record, so records are never dropped).
+_alloc_records = {}
+
+
+class AllocRecord:
+    def __init__(self, device):
+        self.device = device
+        self.allocs = 0
+        self.frees = 0
+        self.bytes = 0
+
+
+def _torch_alloc(nbytes, ctx):
+    try:
+        import torch
+        rec = _alloc_records[ctx]
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device=rec.device)
+        rec.allocs += 1
+        rec.bytes += int(nbytes)
+        return ptr
+    except Exception:   # the library reports NULL as out of memory
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+        _alloc_records[ctx].frees += 1
+    except Exception:
+        pass
+
+
+_TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+_TORCH_FREE = FREE_FN(_torch_free)
 
 
 class Info(C.Structure):
@@ -67,8 +112,8 @@ def lib():
         P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
             "nnca_build": [P, i64, i32, i64, i32, i32, f64, f64, i32, P, P, P],
-            "nnca_matvec": [P, P, P, i64, i64, i64, i32, P],
-            "nnca_matvec_adjoint": [P, P, P, i64, i64, i64, i32, P],
+            "nnca_matvec": [P, P, P, i64, i64, i64, i32, i32, P],
+            "nnca_matvec_adjoint": [P, P, P, i64, i64, i64, i32, i32, P],
             "nnca_matvec_backward": [P, P, P, i64, i64, i64, i32, P, i64, P, P],
             "nnca_direct": [P, i64, i32, i64, i32, f64, P, P, i64, i64, i64, P],
             "nnca_query": [P, P],
@@ -111,9 +156,12 @@ def _stream(torch):
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _as_columns(torch, X, n, device):
-    """(n,) or (n, r) -> column-major FP64 device buffer (r, n) and r."""
-    X = torch.as_tensor(X, dtype=torch.float64, device=device)
+def _as_columns(torch, X, n, device, keep_f32=False):
+    """(n,) or (n, r) -> column-major device buffer (r, n) and r: FP64, or
+    FP32 when keep_f32 and X is FP32."""
+    X = torch.as_tensor(X, device=device)
+    dt = torch.float32 if (keep_f32 and X.dtype == torch.float32) else torch.float64
+    X = X.to(dtype=dt)
     if X.dim() == 1:
         return X.contiguous().reshape(1, n), 1, True
     return X.t().contiguous(), X.shape[1], False
@@ -124,7 +172,10 @@ class H2Matrix:
 
     def __init__(self, points, kernel: str = "inv_r", tol: float = 1e-6, leaf_size: int = 64,
                  length_scale: float = 1.0, eta2=None, policy: int = 1, workspace_bytes: int = 0,
-                 rank_reserve: int = 0, device="cuda:0"):
+                 rank_reserve: int = 0, device="cuda:0", max_rhs: int = 0, allocator: str | None = "torch"):
+        """``max_rhs``: columns of the many-column workspace (0: 16; 1: none);
+        ``allocator``: "torch" (the caching allocator, through the C ABI's
+        hooks) or None (the library's hipMalloc)."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -133,9 +184,17 @@ class H2Matrix:
         self.n, self.dim, self.kernel = n, d, kernel
         self.length_scale = float(length_scale)
         soa = pts.t().contiguous().to(self.device)
-        opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes), int(rank_reserve), 0)
+        opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes), int(rank_reserve), 0,
+                            int(max_rhs), 0)
         if eta2 is not None:
             opts.eta2_num, opts.eta2_den = int(eta2[0]), int(eta2[1])
+        self.alloc_record = None
+        if allocator == "torch":
+            ctx = len(_alloc_records) + 1
+            self.alloc_record = _alloc_records[ctx] = AllocRecord(self.device)
+            opts.alloc, opts.free, opts.alloc_ctx = _TORCH_ALLOC, _TORCH_FREE, ctx
+        elif allocator is not None:
+            raise ValueError("allocator must be 'torch' or None")
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().nnca_build(C.c_void_p(soa.data_ptr()), n, d, n, 1, KINDS[kernel], float(length_scale),
@@ -155,18 +214,21 @@ class H2Matrix:
         if not _finalizing():
             self.close()
 
-    def _apply(self, X, precision: str, adjoint: bool, out=None):
+    def _apply(self, X, precision: str, adjoint: bool, out=None, fn=None):
         torch = self.torch
-        Xc, r, vec = _as_columns(torch, X, self.n, self.device)
-        Y = torch.empty((r, self.n), dtype=torch.float64, device=self.device) if out is None else out
-        fn = lib().nnca_matvec_adjoint if adjoint else lib().nnca_matvec
+        Xc, r, vec = _as_columns(torch, X, self.n, self.device, keep_f32=True)
+        Y = torch.empty((r, self.n), dtype=Xc.dtype, device=self.device) if out is None else out
+        dt = DTYPE_F32 if Xc.dtype == torch.float32 else DTYPE_F64
+        if fn is None:
+            fn = lib().nnca_matvec_adjoint if adjoint else lib().nnca_matvec
         with torch.cuda.device(self.device):
-            _check(fn(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), r, self.n, self.n,
+            _check(fn(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), r, self.n, self.n, dt,
                       PRECISION[precision], _stream(torch)))
         return Y.reshape(self.n) if vec else Y.t()
 
     def matvec(self, X, precision: str = "fp64"):
-        """Y = A~ X (FP64 device tensor, (n,) or (n, r))."""
+        """Y = A~ X for a device tensor (n,) or (n, r), FP64 or FP32 (the
+        result has X's type; the arithmetic is set by ``precision``)."""
         return self._apply(X, precision, False)
 
     def rmatvec(self, X, precision: str = "fp64"):
@@ -212,9 +274,11 @@ class H2Matrix:
         return fn.apply(X, length_scale, self, precision)
 
     def matvec_raw(self, Xc, Y, nrhs: int, precision: str = "fp64"):
-        """Column-major device buffers (nrhs, n) in, (nrhs, n) out; no copies."""
+        """Column-major device buffers (nrhs, n) in, (nrhs, n) out, both FP64
+        or both FP32; no copies."""
+        dt = DTYPE_F32 if Xc.dtype == self.torch.float32 else DTYPE_F64
         _check(lib().nnca_matvec(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs, self.n,
-                                 self.n, PRECISION[precision], _stream(self.torch)))
+                                 self.n, dt, PRECISION[precision], _stream(self.torch)))
 
     def profile(self, enable: bool = True, passes=None):
         """Start (and clear) or stop per-launch event timing of matvec passes

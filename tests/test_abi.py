@@ -54,8 +54,34 @@ def test_invalid_arguments(lib):
     assert _build(lib, P, 10, 3, 10, kind=3, h=0.0)[0] == 1
     assert _build(lib, P, 10, 3, 10, kind=1)[0] == 4   # log only in 2D
     assert b"dim" in lib.nnca_last_error() or lib.nnca_last_error()
-    assert lib.nnca_matvec(None, None, None, 1, 1, 1, 0, None) == 1
+    assert lib.nnca_matvec(None, None, None, 1, 1, 1, 1, 0, None) == 1
+    assert lib.nnca_matvec_adjoint(None, None, None, 1, 1, 1, 1, 0, None) == 1
     assert lib.nnca_query(None, None) == 1
     assert lib.nnca_destroy(None) == 0
     assert lib.nnca_direct(None, 10, 3, 10, 2, 1.0, None, None, 1, 10, 10, None) == 1
     assert lib.nnca_matvec_backward(None, None, None, 1, 1, 1, 0, None, 1, None, None) == 1
+
+
+def test_build_options_layout(lib):
+    # the struct grew at its end: the first version ends at `reserved` (32
+    # bytes); the allocator fields follow the column-workspace size
+    from paper_2203_14832_amd import nnca
+    O = nnca.BuildOptions
+    assert O.max_rhs.offset == 32 and O.alloc.offset == 40 and O.free.offset == 48 and O.alloc_ctx.offset == 56
+    assert C.sizeof(O) == 64
+
+
+def test_build_rejects_bad_options(lib):
+    from paper_2203_14832_amd import nnca
+    p = np.zeros((3, 10))
+    P = p.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+    o = nnca.BuildOptions(C.sizeof(nnca.BuildOptions))
+    o.alloc = nnca._TORCH_ALLOC          # alloc without free
+    assert lib.nnca_build(P, 10, 3, 10, 0, 2, 1.0, 1e-6, 64, C.byref(o), None, C.byref(h)) == 1
+    o = nnca.BuildOptions(C.sizeof(nnca.BuildOptions))
+    o.max_rhs = -1
+    assert lib.nnca_build(P, 10, 3, 10, 0, 2, 1.0, 1e-6, 64, C.byref(o), None, C.byref(h)) == 1
+    o = nnca.BuildOptions(20)             # neither version's size
+    assert lib.nnca_build(P, 10, 3, 10, 0, 2, 1.0, 1e-6, 64, C.byref(o), None, C.byref(h)) == 1
+    assert not h.value

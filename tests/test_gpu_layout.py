@@ -34,7 +34,8 @@ def op():
 
 
 def _raw(h, X, Y, nrhs, ldx, ldy, precision):
-    st = nnca.lib().nnca_matvec(h._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs, ldx, ldy,
+    dt = nnca.DTYPE_F32 if X.dtype == torch.float32 else nnca.DTYPE_F64
+    st = nnca.lib().nnca_matvec(h._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs, ldx, ldy, dt,
                                 nnca.PRECISION[precision], nnca._stream(torch))
     torch.cuda.synchronize()
     return st

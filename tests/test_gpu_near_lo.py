@@ -54,7 +54,7 @@ def _problem(R, seed):
 @pytest.mark.parametrize("R", [1, 20, 64])
 def test_mixed_near_field_keeps_x_lo(R):
     p, x, exact, lo_only = _problem(R, 40 + R)
-    G = nnca.H2Matrix(p, "gauss", 1e-6, 64, length_scale=1.0)
+    G = nnca.H2Matrix(p, "gauss", 1e-6, 64, length_scale=1.0, max_rhs=64)
     X = torch.tensor(x[:, 0] if R == 1 else x, device="cuda")
     for prec in ("fp64", "mixed"):
         y = G.matvec(X, prec).cpu().numpy().reshape(60, R)

@@ -82,7 +82,8 @@ def built(orc):
         if name not in cache:
             gen, kind, tol, leaf, h, eta2 = CASES[name]
             p = gen()
-            G = nnca.H2Matrix(p, kind, tol, leaf, length_scale=h, eta2=eta2)
+            # the many-column workspace at its widest: blocks of 16-64 columns
+            G = nnca.H2Matrix(p, kind, tol, leaf, length_scale=h, eta2=eta2, max_rhs=64)
             T = orc.Tree(p, leaf, eta2=eta2)
             O = orc.H2(T, kind, tol, h=h)
             cache[name] = (p, G, T, O, kind, h)
