@@ -138,6 +138,26 @@ nnca_status nnca_matvec(nnca_handle h, const void *X, void *Y, int64_t nrhs, int
 nnca_status nnca_matvec_adjoint(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                                 int32_t dtype, int32_t precision, void *stream);
 
+/* Y = A~ X like nnca_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Every per-call buffer of the one-column passes (input in tree
+ * order and its FP32 split, multipole and local vectors, column slots, split
+ * partial vectors, near- and far-field sums) lives in one static device
+ * array of NNCA_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from
+ * its first use on that GPU until the process ends; nothing is allocated,
+ * on the device or the host.  nrhs > 1 runs the columns one at a time.
+ * The handle's own workspace is not touched.  Results equal nnca_matvec's
+ * with nrhs = 1 bit for bit.  Every call on one GPU, from any handle, uses
+ * the same array and leaves its contents behind: calls that can overlap on
+ * one GPU (different streams, different threads) race and must be ordered
+ * by the caller.  Arguments as nnca_matvec.
+ * Errors: as nnca_matvec; NOT_SUPPORTED when the handle's per-call buffers
+ * exceed the array (the message states both sizes; use nnca_matvec); HIP
+ * when the array's device address cannot be obtained.                     */
+#define NNCA_NOALLOC_SCRATCH_BYTES (64u << 20)
+nnca_status nnca_matvec_noalloc(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                int32_t dtype, int32_t precision, void *stream);
+
 /* Backward of Y = A~ X for a scalar loss L with G = dL/dY (device FP64,
  * column-major, original point order, like X):
  *   DX    = A~^T G  (the gradient with respect to X; Sec. 5's symmetric case

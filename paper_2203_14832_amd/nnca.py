@@ -21,6 +21,7 @@ KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 DTYPE_F32, DTYPE_F64 = 0, 1
 MAX_LEVELS = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -114,6 +115,7 @@ def lib():
             "nnca_build": [P, i64, i32, i64, i32, i32, f64, f64, i32, P, P, P],
             "nnca_matvec": [P, P, P, i64, i64, i64, i32, i32, P],
             "nnca_matvec_adjoint": [P, P, P, i64, i64, i64, i32, i32, P],
+            "nnca_matvec_noalloc": [P, P, P, i64, i64, i64, i32, i32, P],
             "nnca_matvec_backward": [P, P, P, i64, i64, i64, i32, P, i64, P, P],
             "nnca_direct": [P, i64, i32, i64, i32, f64, P, P, i64, i64, i64, P],
             "nnca_query": [P, P],
@@ -234,6 +236,11 @@ class H2Matrix:
     def rmatvec(self, X, precision: str = "fp64"):
         """Y = A~^T X."""
         return self._apply(X, precision, True)
+
+    def matvec_noalloc(self, X, precision: str = "fp64"):
+        """Y = A~ X through ``nnca_matvec_noalloc`` (per-call buffers in the
+        library's static device array; columns one at a time)."""
+        return self._apply(X, precision, False, fn=lib().nnca_matvec_noalloc)
 
     def set_symmetric(self, enable: bool = True):
         """Use (default) or not the symmetric evaluation (transverse pass and

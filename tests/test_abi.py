@@ -55,6 +55,7 @@ def test_invalid_arguments(lib):
     assert _build(lib, P, 10, 3, 10, kind=1)[0] == 4   # log only in 2D
     assert b"dim" in lib.nnca_last_error() or lib.nnca_last_error()
     assert lib.nnca_matvec(None, None, None, 1, 1, 1, 1, 0, None) == 1
+    assert lib.nnca_matvec_noalloc(None, None, None, 1, 1, 1, 1, 0, None) == 1
     assert lib.nnca_matvec_adjoint(None, None, None, 1, 1, 1, 1, 0, None) == 1
     assert lib.nnca_query(None, None) == 1
     assert lib.nnca_destroy(None) == 0
