@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="counter runs: one 256 MiB device copy (calibration of byte counters) and --steps "
                          "mixed matvecs of the workload, no timing")
+    ap.add_argument("--rates", action="store_true",
+                    help="print the device's attainable rates (copy, FMA, rsq, the symmetric pass's inner loop)")
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
                          "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
@@ -129,6 +131,11 @@ def main():
 
     if args.probe:
         return probe(args)
+    if args.rates:
+        print(json.dumps({"attainable": nnca.probe_rates(torch.device("cuda:0")),
+                          "peaks": {"hbm_bytes_per_s": 8e12, "fp32_lane_ops_per_s": VALU_LANE_SLOTS,
+                                    "yardstick_pairs_per_s": PEAK_PAIRS}}), flush=True)
+        return
     if args.config == "c3":
         return bench_many_rhs(args)
     if args.config == "c4":
@@ -249,6 +256,8 @@ def main():
                      "directed_interactions_per_s": 2 * pair_rate,
                      "peak_derivation": "7.864e13 FP32 lane-instr/s / 10 slots per pair "
                                         "(r^2: add + 3 fma; 1/r: v_rsq_f32 = 4; 2 fma)"},
+        "m2l_fine_ms_per_launch_by_level": {int(l): float(ms[(passes == 2) & (levels == l)].mean())
+                                            for l in range(max(kap - 1, 0), kap + 1)},
         "m2l_coarse_fp64_ms_per_step": coarse_ms, "m2l_level_interactions": info["m2l_level"],
         # both forms with the symmetric transverse pass (the same schedule)
         "fp64_ms_per_step": fp64_ms, "fp64_matvecs_per_s": 1e3 / fp64_ms, "speedup_vs_fp64": fp64_ms / ms_step,
@@ -259,6 +268,11 @@ def main():
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,
         "interactions_per_step": inter, "ms_per_step_without_events": ms_plain,
     }
+    # attainable rates measured on this device (copy, FMA, rsq, and the
+    # kernel's inner loop with its operands in registers)
+    att = nnca.probe_rates(dev)
+    out["attainable"] = att
+    out["roofline"]["frac_of_attainable_inner_loop"] = pair_rate / att["sym_pairs_per_s_valu"]
     yd = None
     if not args.no_direct:
         yd = nnca.direct(p, X.reshape(n), "inv_r", device=dev)

@@ -309,6 +309,21 @@ nnca_status nnca_profile_enable(nnca_handle h, int32_t enable);
 nnca_status nnca_profile_read(nnca_handle h, int64_t *count, int32_t *pass, int32_t *level, double *ms,
                               int64_t cap);
 
+/* Attainable rates on the current device, for the rooflines of the apply
+ * passes (blocking; allocates and frees 512 MiB of workspace):
+ *   out[0]  bytes/s of a device-to-device copy (read + write, 2 x 256 MiB);
+ *   out[1]  FP32 FMA lane-operations/s (independent chains, no packed FP32);
+ *   out[2]  v_rsq_f32 lane-operations/s;
+ *   out[3]  pairs/s of the inner loop of the FP32 symmetric transverse pass
+ *           of Sec. 4 with its operands in registers (r^2 = |t|^2 + |s|^2
+ *           - 2 t.s by one addition and three FMAs, 1/sqrt, the row and the
+ *           column FMA);
+ *   out[4]  the same loop with r^2 of 16 x 16 pairs from one
+ *           v_mfma_f32_16x16x4f32.
+ * Only the first `count` (at most 5) are written.
+ * Errors: INVALID_ARG (NULL out, count < 1); OUT_OF_MEMORY; HIP.           */
+nnca_status nnca_probe_rates(double *out, int32_t count, void *stream);
+
 nnca_status nnca_destroy(nnca_handle h);
 const char *nnca_status_string(nnca_status s);
 const char *nnca_last_error(void);

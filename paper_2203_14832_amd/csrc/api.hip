@@ -527,6 +527,14 @@ nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int
     });
 }
 
+nnca_status nnca_probe_rates(double *out, int32_t count, void *stream)
+{
+    return guarded([&] {
+        if (!out || count < 1) fail(NNCA_ERR_INVALID_ARG, "out is NULL or count < 1");
+        probe_rates(out, count, (hipStream_t)stream);
+    });
+}
+
 nnca_status nnca_profile_enable(nnca_handle h, int32_t enable)
 {
     return guarded([&] {

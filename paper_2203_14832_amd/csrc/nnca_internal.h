@@ -259,6 +259,10 @@ const Allocator *batch_allocator(const nnca_batch *B);
 int32_t batch_count(const nnca_batch *B);
 const int64_t *batch_offsets(const nnca_batch *B);
 enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4, PASS_M2L_COMBINE = 5 };
+// probe.hip: out[0..count) of {HBM copy bytes/s, FP32 FMA lane-ops/s,
+// v_rsq_f32 lane-ops/s, pairs/s of the symmetric pass's inner loop with r^2
+// on the vector ALUs, the same with r^2 on the matrix cores}
+void probe_rates(double *out, int32_t count, hipStream_t s);
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
                 const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);
 

@@ -133,6 +133,7 @@ def lib():
             "nnca_batch_query": [P, P, P, P],
             "nnca_batch_matvec": [P, P, P, i64, i64, i64, i32, P],
             "nnca_batch_destroy": [P],
+            "nnca_probe_rates": [P, i32, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -454,6 +455,17 @@ def direct(points, X, kernel: str = "inv_r", length_scale: float = 1.0, device="
         _check(lib().nnca_direct(C.c_void_p(soa.data_ptr()), n, d, n, KINDS[kernel], float(length_scale),
                                  C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), r, n, n, _stream(torch)))
     return Y.reshape(n) if vec else Y.t()
+
+
+def probe_rates(device="cuda:0") -> dict:
+    """Attainable rates of the device (``nnca_probe_rates``)."""
+    import torch
+    out = np.zeros(5)
+    with torch.cuda.device(torch.device(device)):
+        _check(lib().nnca_probe_rates(_np_ptr(out), 5, _stream(torch)))
+    keys = ["copy_bytes_per_s", "fma_f32_lane_ops_per_s", "rsq_f32_lane_ops_per_s", "sym_pairs_per_s_valu",
+            "sym_pairs_per_s_mfma_r2"]
+    return dict(zip(keys, out.tolist()))
 
 
 def debug_kernel_eval(kernel: str, a, b, length_scale: float = 1.0):
