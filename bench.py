@@ -116,7 +116,7 @@ def main():
                          "mixed matvecs of the workload, no timing")
     ap.add_argument("--rates", action="store_true",
                     help="print the device's attainable rates (copy, FMA, rsq, the symmetric pass's inner loop)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie"],
                     help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
                          "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
     args = ap.parse_args()
@@ -142,6 +142,8 @@ def main():
         return bench_backward(args)
     if args.config == "c5":
         return bench_batch(args)
+    if args.config == "ie":
+        return bench_integral_equation(args)
     dev = torch.device("cuda:0")
     p, x = workload("c2", n=args.n)
     n = p.shape[0]
@@ -283,6 +285,48 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inter, points=p, x=x[:, 0], yd_gpu=yd)
     print(json.dumps(out), flush=True)
+
+
+def bench_integral_equation(args):
+    """Exp. 5: (I + w A~) sigma = f on the cell centres of uniform grids of
+    20^3 ... 90^3 points in [-1,1]^3, 1/r, tol 1e-7, leaf 64, f = (I + w A~)
+    sigma for a seeded sigma, GMRES to a relative residual of 1e-10 with the
+    FP64 matvec (and, with --steps > 0, with the mixed one to 1e-6)."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import nystrom_grid
+    dev = torch.device("cuda:0")
+    rows = []
+    for na in (20, 30, 40, 50, 60, 70, 80, 90):
+        p, w, sigma = nystrom_grid(na)
+        t0 = time.perf_counter()
+        H = nnca.H2Matrix(p, "inv_r", 1e-7, 64, device=dev)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        s = torch.tensor(sigma, device=dev)
+        f = s + w * H.matvec(s, "fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, rr = H.solve(f, 1.0, w, tol=1e-10, restart=50, max_iter=200)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        es = float(torch.linalg.norm(x - s) / torch.linalg.norm(s))
+        row = {"n": int(p.shape[0]), "iters": it, "relres": rr, "eps_s": es, "assembly_s": ta, "solve_s": ts}
+        f32 = s + w * H.matvec(s, "mixed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xm, itm, rrm = H.solve(f32, 1.0, w, tol=1e-6, restart=50, max_iter=200, precision="mixed")
+        torch.cuda.synchronize()
+        row.update({"iters_mixed_1e-6": itm, "solve_s_mixed_1e-6": time.perf_counter() - t0,
+                    "eps_s_mixed": float(torch.linalg.norm(xm - s) / torch.linalg.norm(s))})
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        H.close()
+        del H
+        torch.cuda.empty_cache()
+    print(json.dumps({"config": "ie", "workload": "Nystrom (I + w A) sigma = f, 3D 1/r, uniform grid cell centres "
+                                                  "in [-1,1]^3, tol 1e-7, leaf 64, GMRES(50) to 1e-10",
+                      "rows": rows}), flush=True)
 
 
 def probe(args):

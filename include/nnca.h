@@ -309,6 +309,26 @@ nnca_status nnca_profile_enable(nnca_handle h, int32_t enable);
 nnca_status nnca_profile_read(nnca_handle h, int64_t *count, int32_t *pass, int32_t *level, double *ms,
                               int64_t cap);
 
+/* Solve (alpha I + beta A~) X = F by restarted GMRES(restart) with the H2
+ * matvec of the given precision (the integral-equation solve of Exp. 5 in
+ * Sec. 5: a Nystrom discretisation of sigma + int K sigma = f gives alpha =
+ * 1 and beta = the quadrature weight).  F, X: device FP64 vectors of n
+ * entries in original point order; X holds the initial guess on entry and
+ * the solution on return.  Stops when the relative residual
+ * ||F - (alpha I + beta A~) X|| / ||F|| is at most tol (checked with the
+ * Arnoldi recurrence, then recomputed for the final X) or after max_iter
+ * matvecs.  *iters receives the matvec count, *relres the final relative
+ * residual (host pointers, may be NULL).  Arnoldi uses classical
+ * Gram-Schmidt applied twice; inner products are fixed-shape device
+ * reductions (deterministic).  Blocking; allocates n (restart + 2) doubles
+ * of workspace for the call.
+ * Errors: INVALID_ARG (NULL pointers, F and X overlapping, tol < 0, alpha or
+ * beta not finite, max_iter < 0, restart outside 1..1000, bad precision);
+ * OUT_OF_MEMORY; HIP.                                                     */
+nnca_status nnca_gmres(nnca_handle h, double alpha, double beta, const double *F, double *X, double tol,
+                       int32_t max_iter, int32_t restart, int32_t precision, int32_t *iters, double *relres,
+                       void *stream);
+
 /* Attainable rates on the current device, for the rooflines of the apply
  * passes (blocking; allocates and frees 512 MiB of workspace):
  *   out[0]  bytes/s of a device-to-device copy (read + write, 2 x 256 MiB);

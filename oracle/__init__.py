@@ -289,3 +289,63 @@ def dense_grad_h(points, x, g, h: float) -> float:
     x = np.ascontiguousarray(x, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     return float(lib().orc_dense_grad_h(_p(pts), n, d, float(h), _p(x), _p(g)))
+
+
+def gmres(apply, f, tol: float = 1e-10, max_iter: int = 500, restart: int = 50, x0=None):
+    """Restarted GMRES(restart) for M x = f, M given by ``apply`` (Saad,
+    Iterative Methods for Sparse Linear Systems, Alg. 6.9 with Givens
+    rotations, Sec. 6.5.3): Arnoldi by modified Gram-Schmidt, the
+    least-squares problem of the Hessenberg matrix by plane rotations.
+    Stops when the recurrence's relative residual is at most tol or after
+    max_iter applications.  Returns (x, applications, relative residual of
+    the final x recomputed as ||f - M x|| / ||f||)."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    fn = np.linalg.norm(f)
+    if fn == 0.0:
+        return np.zeros(n), 0, 0.0
+    it = 0
+    while True:
+        r = f - apply(x)
+        beta = np.linalg.norm(r)
+        if beta / fn <= tol or it >= max_iter:
+            return x, it, beta / fn
+        m = restart
+        V = np.zeros((m + 1, n))
+        Hm = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        j = 0
+        done = False
+        while j < m and it < max_iter:
+            w = apply(V[j])
+            it += 1
+            for i in range(j + 1):
+                Hm[i, j] = w @ V[i]
+                w = w - Hm[i, j] * V[i]
+            Hm[j + 1, j] = np.linalg.norm(w)
+            if Hm[j + 1, j] > 0:
+                V[j + 1] = w / Hm[j + 1, j]
+            for i in range(j):
+                a = cs[i] * Hm[i, j] + sn[i] * Hm[i + 1, j]
+                Hm[i + 1, j] = -sn[i] * Hm[i, j] + cs[i] * Hm[i + 1, j]
+                Hm[i, j] = a
+            rr = np.hypot(Hm[j, j], Hm[j + 1, j])
+            cs[j] = Hm[j, j] / rr if rr > 0 else 1.0
+            sn[j] = Hm[j + 1, j] / rr if rr > 0 else 0.0
+            Hm[j, j] = rr
+            Hm[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            j += 1
+            if abs(g[j]) / fn <= tol or Hm[j, j - 1] == 0 and rr == 0:
+                done = True
+                break
+        y = np.linalg.solve(np.triu(Hm[:j, :j]), g[:j]) if j > 0 else np.zeros(0)
+        x = x + V[:j].T @ y
+        if done or it >= max_iter:
+            return x, it, np.linalg.norm(f - apply(x)) / fn

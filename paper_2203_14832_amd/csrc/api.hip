@@ -527,6 +527,31 @@ nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int
     });
 }
 
+nnca_status nnca_gmres(nnca_handle h, double alpha, double beta, const double *F, double *X, double tol,
+                       int32_t max_iter, int32_t restart, int32_t precision, int32_t *iters, double *relres,
+                       void *stream)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        if (!F || !X) fail(NNCA_ERR_INVALID_ARG, "F or X is NULL");
+        if (F == X) fail(NNCA_ERR_INVALID_ARG, "F and X are the same buffer");
+        {
+            const char *fb = (const char *)F, *fe = fb + sizeof(double) * h->n;
+            const char *xb = (const char *)X, *xe = xb + sizeof(double) * h->n;
+            if (fb < xe && xb < fe) fail(NNCA_ERR_INVALID_ARG, "F and X overlap");
+        }
+        if (!(tol >= 0.0) || !std::isfinite(alpha) || !std::isfinite(beta))
+            fail(NNCA_ERR_INVALID_ARG, "tol must be >= 0 and alpha, beta finite");
+        if (max_iter < 0 || restart < 1 || restart > 1000) fail(NNCA_ERR_INVALID_ARG, "bad max_iter or restart");
+        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+        AllocScope as(h->alloc);
+        const hipStream_t s = (hipStream_t)stream;
+        order_call_begin(h, s);
+        run_gmres(h, alpha, beta, F, X, tol, max_iter, restart, precision, iters, relres, s);
+        order_call_end(h, s);
+    });
+}
+
 nnca_status nnca_probe_rates(double *out, int32_t count, void *stream)
 {
     return guarded([&] {

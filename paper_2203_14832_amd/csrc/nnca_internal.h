@@ -259,6 +259,9 @@ const Allocator *batch_allocator(const nnca_batch *B);
 int32_t batch_count(const nnca_batch *B);
 const int64_t *batch_offsets(const nnca_batch *B);
 enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4, PASS_M2L_COMBINE = 5 };
+// gmres.hip: restarted GMRES(restart) for (alpha I + beta A~) x = f
+void run_gmres(nnca_h2 *H, double alpha, double beta, const double *F, double *X, double tol, int32_t max_iter,
+               int32_t restart, int precision, int32_t *iters, double *relres, hipStream_t s);
 // probe.hip: out[0..count) of {HBM copy bytes/s, FP32 FMA lane-ops/s,
 // v_rsq_f32 lane-ops/s, pairs/s of the symmetric pass's inner loop with r^2
 // on the vector ALUs, the same with r^2 on the matrix cores}

@@ -134,6 +134,7 @@ def lib():
             "nnca_batch_matvec": [P, P, P, i64, i64, i64, i32, P],
             "nnca_batch_destroy": [P],
             "nnca_probe_rates": [P, i32, P],
+            "nnca_gmres": [P, f64, f64, P, P, f64, i32, i32, i32, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -242,6 +243,22 @@ class H2Matrix:
         """Y = A~ X through ``nnca_matvec_noalloc`` (per-call buffers in the
         library's static device array; columns one at a time)."""
         return self._apply(X, precision, False, fn=lib().nnca_matvec_noalloc)
+
+    def solve(self, F, alpha: float = 1.0, beta: float = 1.0, tol: float = 1e-10, max_iter: int = 500,
+              restart: int = 50, precision: str = "fp64", x0=None):
+        """Solve (alpha I + beta A~) X = F by GMRES (``nnca_gmres``); returns
+        (X, matvecs, final relative residual)."""
+        torch = self.torch
+        Fd = torch.as_tensor(F, dtype=torch.float64, device=self.device).reshape(self.n).contiguous()
+        X = (torch.zeros_like(Fd) if x0 is None
+             else torch.as_tensor(x0, dtype=torch.float64, device=self.device).reshape(self.n).clone())
+        it = C.c_int32()
+        rr = C.c_double()
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_gmres(self._h, float(alpha), float(beta), C.c_void_p(Fd.data_ptr()),
+                                    C.c_void_p(X.data_ptr()), float(tol), int(max_iter), int(restart),
+                                    PRECISION[precision], C.byref(it), C.byref(rr), _stream(torch)))
+        return X, it.value, rr.value
 
     def set_symmetric(self, enable: bool = True):
         """Use (default) or not the symmetric evaluation (transverse pass and

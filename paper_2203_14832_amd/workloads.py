@@ -74,6 +74,16 @@ def cotangent(config: str, n: int | None = None) -> np.ndarray:
     return np.random.default_rng(seed_of(config) + 100).standard_normal(n)
 
 
+def nystrom_grid(n_axis: int, seed: int = 1005):
+    """Points, quadrature weight and density of the integral-equation solve
+    (Exp. 5): the n_axis^3 cell centres of a uniform grid on [-1,1]^3, the
+    weight (2 / n_axis)^3 of each, and sigma ~ N(0,1) (seeded)."""
+    c = -1.0 + (np.arange(n_axis) + 0.5) * (2.0 / n_axis)
+    g = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    sigma = np.random.default_rng(seed).standard_normal(g.shape[0])
+    return g, (2.0 / n_axis) ** 3, sigma
+
+
 def batch_sizes(count: int = 32, lo: float = 1e4, hi: float = 2e5, seed: int = 1004):
     """Sizes of the uneven batch: N_b = round(exp(U(ln lo, ln hi)))."""
     ss = np.random.SeedSequence(seed).spawn(count)

@@ -59,6 +59,7 @@ def test_invalid_arguments(lib):
     assert lib.nnca_matvec_adjoint(None, None, None, 1, 1, 1, 1, 0, None) == 1
     assert lib.nnca_query(None, None) == 1
     assert lib.nnca_probe_rates(None, 5, None) == 1
+    assert lib.nnca_gmres(None, 1.0, 1.0, None, None, 1e-10, 10, 5, 0, None, None, None) == 1
     assert lib.nnca_destroy(None) == 0
     assert lib.nnca_direct(None, 10, 3, 10, 2, 1.0, None, None, 1, 10, 10, None) == 1
     assert lib.nnca_matvec_backward(None, None, None, 1, 1, 1, 0, None, 1, None, None) == 1
