@@ -116,7 +116,7 @@ def main():
                          "mixed matvecs of the workload, no timing")
     ap.add_argument("--rates", action="store_true",
                     help="print the device's attainable rates (copy, FMA, rsq, the symmetric pass's inner loop)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie", "exp"],
                     help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
                          "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
     args = ap.parse_args()
@@ -144,6 +144,8 @@ def main():
         return bench_batch(args)
     if args.config == "ie":
         return bench_integral_equation(args)
+    if args.config == "exp":
+        return bench_experiments(args)
     dev = torch.device("cuda:0")
     p, x = workload("c2", n=args.n)
     n = p.shape[0]
@@ -285,6 +287,58 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inter, points=p, x=x[:, 0], yd_gpu=yd)
     print(json.dumps(out), flush=True)
+
+
+def bench_experiments(args):
+    """The trends of Exp. 1-4 (Sec. 5) with the regularised kernels (a = 1e-4):
+    assembly time, FP64 and mixed matvec times and the relative error against
+    the FP64 direct sum, (i) against the ACA tolerance at N = 102400 in 2D
+    (uniform points with both kernels, Exp. 1; the 320^2 Chebyshev grid with
+    the log kernel, Exp. 2), (ii) against N at tol 1e-7 in 3D (uniform points,
+    Exp. 3; Chebyshev grids, Exp. 4) with the 1/r kernel."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import chebyshev_grid
+    dev = torch.device("cuda:0")
+    a = 1e-4
+    rows = []
+
+    def one(exp, dist, kind, p, tol, leaf=64):
+        n = p.shape[0]
+        x = torch.tensor(np.random.default_rng(1010).standard_normal(n), device=dev)
+        t0 = time.perf_counter()
+        H = nnca.H2Matrix(p, kind, tol, leaf, length_scale=a, device=dev)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        yd = nnca.direct(p, x, kind, a, device=dev)
+        out = {"exp": exp, "dist": dist, "kernel": kind, "n": n, "tol": tol, "assembly_s": ta,
+               "kappa": H.info()["kappa"]}
+        for prec in ("fp64", "mixed"):
+            y = H.matvec(x, prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                y = H.matvec(x, prec)
+            torch.cuda.synchronize()
+            out[f"matvec_ms_{prec}"] = (time.perf_counter() - t0) / 5 * 1e3
+            out[f"eps_m_{prec}"] = float(torch.linalg.norm(y - yd) / torch.linalg.norm(yd))
+        rows.append(out)
+        print(json.dumps(out), file=sys.stderr, flush=True)
+        H.close()
+        torch.cuda.empty_cache()
+
+    rng = np.random.default_rng(1011)
+    p2u = rng.uniform(-1, 1, (102400, 2))
+    p2c = chebyshev_grid(320, 2)
+    for tol in (1e-3, 1e-5, 1e-7, 1e-9, 1e-11):
+        one(1, "uniform 2D", "log_reg", p2u, tol)
+        one(1, "uniform 2D", "inv_reg", p2u, tol)
+        one(2, "Chebyshev 2D", "log_reg", p2c, tol)
+    for m in (15, 16, 17, 18, 19, 20):
+        one(3, "uniform 3D", "inv_reg", rng.uniform(-1, 1, (1 << m, 3)), 1e-7)
+    for na in (32, 40, 50, 64, 80, 100):
+        one(4, "Chebyshev 3D", "inv_reg", chebyshev_grid(na, 3), 1e-7)
+    print(json.dumps({"config": "exp", "a": a, "rows": rows}), flush=True)
 
 
 def bench_integral_equation(args):

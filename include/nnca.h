@@ -52,11 +52,17 @@ typedef enum {
 } nnca_status;
 
 /* Kernel functions K(x, y) = K(r), r = |x - y| (Sec. 5, Exp. 1-6).
- * log r and 1/r are zero at r = 0; the Gaussian exp(-r^2/h^2) is 1 there. */
+ * log r and 1/r are zero at r = 0; the Gaussian exp(-r^2/h^2) is 1 there.
+ * The regularised kernels of Exp. 1-4 take a = length_scale > 0:
+ *   NNCA_K_LOG_REG: r (log r - 1) / (a (log a - 1)) for r < a,
+ *                   log r / log a for r >= a (2D only; 0 at r = 0);
+ *   NNCA_K_INV_REG: r / a for r < a, a / r for r >= a (0 at r = 0).      */
 typedef enum {
     NNCA_K_LOG_R = 1,   /* log r, 2D only                                 */
     NNCA_K_INV_R = 2,   /* 1/r                                            */
-    NNCA_K_GAUSS = 3    /* exp(-r^2 / h^2), h = length_scale > 0          */
+    NNCA_K_GAUSS = 3,   /* exp(-r^2 / h^2), h = length_scale > 0          */
+    NNCA_K_LOG_REG = 4, /* regularised log r, a = length_scale, 2D only   */
+    NNCA_K_INV_REG = 5  /* regularised 1/r, a = length_scale              */
 } nnca_kernel_kind;
 
 /* Arithmetic of a matvec.

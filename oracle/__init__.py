@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nnca_oracle.c")
 _LIB = os.path.join(_HERE, "libnnca_oracle.so")
 
-KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "poly2": 99}
+KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "log_reg": 4, "inv_reg": 5, "poly2": 99}
 
 
 def build(force: bool = True) -> str:

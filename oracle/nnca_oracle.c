@@ -132,6 +132,18 @@ static double kern(int kind, double hparam, const double *a, const double *b, in
         double d2 = dist2(a, b, d);
         return orc_exp(-(d2 / (hparam * hparam)));
     }
+    case ORC_K_INV_REG: {   /* Exp. 1-4: r/a for r < a, a/r for r >= a; hparam = a */
+        double d2 = dist2(a, b, d);
+        if (d2 == 0.0) return 0.0;
+        return d2 >= hparam * hparam ? hparam / sqrt(d2) : sqrt(d2) / hparam;
+    }
+    case ORC_K_LOG_REG: {   /* Exp. 1-2: r (log r - 1)/(a (log a - 1)) for r < a, log r / log a else */
+        double d2 = dist2(a, b, d);
+        if (d2 == 0.0) return 0.0;
+        double la = orc_log(hparam);
+        return d2 >= hparam * hparam ? (0.5 * orc_log(d2)) / la
+                                     : (sqrt(d2) * (0.5 * orc_log(d2) - 1.0)) / (hparam * (la - 1.0));
+    }
     case ORC_K_POLY2: {
         double s = 1.0;
         for (int q = 0; q < d; q++) s = s + a[q] * b[q];
@@ -151,6 +163,16 @@ static double kern_ref(int kind, double hparam, const double *a, const double *b
     case ORC_K_INV_R: return d2 == 0.0 ? 0.0 : 1.0 / sqrt(d2);
     case ORC_K_LOG_R: return d2 == 0.0 ? 0.0 : log(sqrt(d2));
     case ORC_K_GAUSS: return exp(-d2 / (hparam * hparam));
+    case ORC_K_INV_REG: {
+        double r = sqrt(d2), a0 = hparam;
+        if (r == 0.0) return 0.0;
+        return r < a0 ? r / a0 : a0 / r;
+    }
+    case ORC_K_LOG_REG: {
+        double r = sqrt(d2), a0 = hparam;
+        if (r == 0.0) return 0.0;
+        return r < a0 ? r * (log(r) - 1.0) / (a0 * (log(a0) - 1.0)) : log(r) / log(a0);
+    }
     case ORC_K_POLY2: {
         double s = 1.0;
         for (int q = 0; q < d; q++) s += a[q] * b[q];

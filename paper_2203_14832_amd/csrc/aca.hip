@@ -105,8 +105,21 @@ __device__ inline double kval(int kind, double hh, int d, double ax, double ay, 
     }
     if (kind == NNCA_K_INV_R) return s == 0.0 ? 0.0 : 1.0 / sqrt(s);
     if (kind == NNCA_K_LOG_R) return s == 0.0 ? 0.0 : 0.5 * dlog(s);
+    if (kind == NNCA_K_INV_REG) {   // hh = a
+        if (s == 0.0) return 0.0;
+        return s >= hh * hh ? hh / sqrt(s) : sqrt(s) / hh;
+    }
+    if (kind == NNCA_K_LOG_REG) {   // hh = a
+        if (s == 0.0) return 0.0;
+        const double la = dlog(hh);
+        return s >= hh * hh ? (0.5 * dlog(s)) / la : (sqrt(s) * (0.5 * dlog(s) - 1.0)) / (hh * (la - 1.0));
+    }
     return dexp(-(s / hh));
 }
+
+// the kernel parameter kval takes: the Gaussian h^2, the regularised
+// kernels their a
+inline double aca_param(int kind, double hparam) { return kind == NNCA_K_GAUSS ? hparam * hparam : hparam; }
 
 __global__ void k_debug_kernel(int kind, double hh, int d, const double *a, const double *b, int64_t cnt,
                                double *out)
@@ -508,7 +521,7 @@ void debug_kernel_eval(int kind, double hparam, int dim, const double *a, const 
     HIPCHECK(hipMemsetAsync(db, 0, sizeof(double) * 3 * count, s));
     HIPCHECK(hipMemcpyAsync(da, a, sizeof(double) * dim * count, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(db, b, sizeof(double) * dim * count, hipMemcpyHostToDevice, s));
-    k_debug_kernel<<<grid_for(count, 256), 256, 0, s>>>(kind, hparam * hparam, dim, da, db, count, dout);
+    k_debug_kernel<<<grid_for(count, 256), 256, 0, s>>>(kind, aca_param(kind, hparam), dim, da, db, count, dout);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipMemcpyAsync(out, dout, sizeof(double) * count, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
@@ -620,7 +633,7 @@ static void build_level(nnca_h2 *H, int l)
                                               H->n, H->dim, sid, sc, so);
         HIPCHECK(hipGetLastError());
         k_aca<<<(int)cn, NT, 0, s>>>(dcells, (int32_t)c0, H->pts64, H->n, H->dim, tsrc, sid, sc, so, U, V, fl,
-                                     H->kind, H->hparam * H->hparam, H->tol, L.k, ipos_cap, jid_cap);
+                                     H->kind, aca_param(H->kind, H->hparam), H->tol, L.k, ipos_cap, jid_cap);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(hk.data() + c0, L.k + c0, sizeof(int32_t) * cn, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));

@@ -126,13 +126,22 @@ void nnca::destroy_handle(nnca_h2 *H)
     delete H;
 }
 
+static bool uses_length_scale(int32_t kind)
+{
+    return kind == NNCA_K_GAUSS || kind == NNCA_K_LOG_REG || kind == NNCA_K_INV_REG;
+}
+
 static void check_kernel(int32_t kind, int32_t dim, double hparam)
 {
-    if (kind != NNCA_K_LOG_R && kind != NNCA_K_INV_R && kind != NNCA_K_GAUSS)
+    if (kind != NNCA_K_LOG_R && kind != NNCA_K_INV_R && kind != NNCA_K_GAUSS && kind != NNCA_K_LOG_REG &&
+        kind != NNCA_K_INV_REG)
         fail(NNCA_ERR_INVALID_ARG, "unknown kernel kind");
-    if (kind == NNCA_K_LOG_R && dim != 2) fail(NNCA_ERR_NOT_SUPPORTED, "log kernel is provided in 2D only");
-    if (kind == NNCA_K_GAUSS && !(hparam > 0.0 && std::isfinite(hparam)))
-        fail(NNCA_ERR_INVALID_ARG, "Gaussian length scale must be positive and finite");
+    if ((kind == NNCA_K_LOG_R || kind == NNCA_K_LOG_REG) && dim != 2)
+        fail(NNCA_ERR_NOT_SUPPORTED, "log kernels are provided in 2D only");
+    if (uses_length_scale(kind) && !(hparam > 0.0 && std::isfinite(hparam)))
+        fail(NNCA_ERR_INVALID_ARG, "the kernel's length scale must be positive and finite");
+    if ((kind == NNCA_K_LOG_REG) && !(hparam < 1.0))
+        fail(NNCA_ERR_INVALID_ARG, "the regularised log kernel needs a < 1 (log a must be negative)");
 }
 
 static const Level &level_of(nnca_handle h, int32_t level)
@@ -211,7 +220,7 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
         H->n = n;
         H->dim = dim;
         H->kind = kernel_kind;
-        H->hparam = kernel_kind == NNCA_K_GAUSS ? length_scale : 1.0;
+        H->hparam = uses_length_scale(kernel_kind) ? length_scale : 1.0;
         H->tol = tol;
         H->leaf = leaf_size;
         H->eta_num = o.eta2_num ? o.eta2_num : dim;
@@ -398,7 +407,7 @@ nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld
         if (n < 1 || (dim != 2 && dim != 3) || ld < n || nrhs < 1 || ldx < n || ldy < n)
             fail(NNCA_ERR_INVALID_ARG, "bad size");
         check_kernel(kernel_kind, dim, length_scale);
-        run_direct(points, n, dim, ld, kernel_kind, kernel_kind == NNCA_K_GAUSS ? length_scale : 1.0, X, Y, nrhs,
+        run_direct(points, n, dim, ld, kernel_kind, uses_length_scale(kernel_kind) ? length_scale : 1.0, X, Y, nrhs,
                    ldx, ldy, (hipStream_t)stream);
     });
 }
@@ -522,7 +531,7 @@ nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int
     return guarded([&] {
         if (!a || !b || !out || count < 1 || (dim != 2 && dim != 3)) fail(NNCA_ERR_INVALID_ARG, "bad argument");
         check_kernel(kernel_kind, dim, length_scale);
-        debug_kernel_eval(kernel_kind, kernel_kind == NNCA_K_GAUSS ? length_scale : 1.0, dim, a, b, count, out,
+        debug_kernel_eval(kernel_kind, uses_length_scale(kernel_kind) ? length_scale : 1.0, dim, a, b, count, out,
                           nullptr);
     });
 }

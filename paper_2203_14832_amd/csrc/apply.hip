@@ -1026,6 +1026,8 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
 #define M2L_CASE(K) k_m2l<K, MODE, M2L_TILE><<<g, NT, 0, s>>>(M2L_ARGS);
     if (kind == NNCA_K_INV_R) { M2L_CASE(NNCA_K_INV_R) }
     else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }
+    else if (kind == NNCA_K_LOG_REG) { M2L_CASE(NNCA_K_LOG_REG) }
+    else if (kind == NNCA_K_INV_REG) { M2L_CASE(NNCA_K_INV_REG) }
     else if (kind == K_GAUSS_DH) { M2L_CASE(K_GAUSS_DH) }
     else { M2L_CASE(NNCA_K_GAUSS) }
 #undef M2L_CASE
@@ -1107,6 +1109,8 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
 #define SYM_CASE(K) sym_launch<K, MODE>(L.max_k, g, A, s)
         if (kind == NNCA_K_INV_R) SYM_CASE(NNCA_K_INV_R);
         else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
+        else if (kind == NNCA_K_LOG_REG) SYM_CASE(NNCA_K_LOG_REG);
+        else if (kind == NNCA_K_INV_REG) SYM_CASE(NNCA_K_INV_REG);
         else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
         else SYM_CASE(NNCA_K_GAUSS);
 #undef SYM_CASE
@@ -1359,6 +1363,8 @@ void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *f
 #define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(c0, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, order, y, prm)
     if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
+    else if (kind == NNCA_K_LOG_REG) P2P_CASE(NNCA_K_LOG_REG);
+    else if (kind == NNCA_K_INV_REG) P2P_CASE(NNCA_K_INV_REG);
     else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
     else P2P_CASE(NNCA_K_GAUSS);
 #undef P2P_CASE
@@ -1377,6 +1383,8 @@ static void launch_p2p_sym(int kind, nnca_h2 *H, const float *xhi, const float *
 #define PS_CASE(K) k_p2p_sym<K><<<(int)nc, NT, 0, s>>>(c0, A)
     if (kind == NNCA_K_INV_R) PS_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) PS_CASE(NNCA_K_LOG_R);
+    else if (kind == NNCA_K_LOG_REG) PS_CASE(NNCA_K_LOG_REG);
+    else if (kind == NNCA_K_INV_REG) PS_CASE(NNCA_K_INV_REG);
     else if (kind == K_GAUSS_DH) PS_CASE(K_GAUSS_DH);
     else PS_CASE(NNCA_K_GAUSS);
 #undef PS_CASE
@@ -1397,10 +1405,7 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, void
 {
     const bool f32 = sizeof(T) == 4;
     const int kap = H->kappa, lmin = H->lmin;
-    const bool gauss = kind == NNCA_K_GAUSS || kind == K_GAUSS_DH;
-    const T prm = gauss ? (f32 ? (T)(1.4426950408889634 / (H->hparam * H->hparam))
-                               : (T)(1.0 / (H->hparam * H->hparam)))
-                        : T(0);
+    const T prm = f32 ? (T)kernel_prm32(kind, H->hparam) : (T)kernel_prm64(kind, H->hparam);
     double *far = nullptr;
     // With a far field, the near field runs on the handle's second stream
     // while the far-field passes run here (it reads only x and the points);
@@ -1464,7 +1469,7 @@ void one_column(nnca_h2 *H, const double *xs64, const T *xhi, const T *xlo, void
         }
         // transverse pass; the mixed matvec keeps the coarse levels
         // (l <= kappa - fp32_levels) in refined FP64 arithmetic
-        const double prm64 = 1.0 / (H->hparam * H->hparam);
+        const double prm64 = kernel_prm64(kind, H->hparam);
         const int lf64 = kap - H->fp32_levels;
         for (int l = lmin; l <= kap; l++) {
             nnca::Level &L = H->lev[l];
@@ -1793,7 +1798,7 @@ void prepare_apply(nnca_h2 *H)
 // points 3.8e-7 with two FP32 levels; the Gaussian mixture of 200 000 points
 // 0.45-1.08e-6 with two, 0.14-0.38e-6 with one.  The 2D log kernel's
 // operators have the largest entries.
-int mixed_fp32_levels(int kind) { return kind == NNCA_K_INV_R ? 2 : 1; }
+int mixed_fp32_levels(int kind) { return kind == NNCA_K_INV_R || kind == NNCA_K_INV_REG ? 2 : 1; }
 
 void run_matvec(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
                 int precision, hipStream_t s)
@@ -1841,13 +1846,15 @@ void prepare_workspace(nnca_h2 *H)
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam, const double *X,
                 double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s)
 {
-    double prm = 1.0 / (hparam * hparam);
+    double prm = kernel_prm64(kind, hparam);
     for (int64_t col = 0; col < nrhs; col++) {
         const double *x = X + col * ldx;
         double *y = Y + col * ldy;
         int g = grid_for(n, NT);
         if (kind == NNCA_K_INV_R) k_direct<NNCA_K_INV_R><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         else if (kind == NNCA_K_LOG_R) k_direct<NNCA_K_LOG_R><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
+        else if (kind == NNCA_K_LOG_REG) k_direct<NNCA_K_LOG_REG><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
+        else if (kind == NNCA_K_INV_REG) k_direct<NNCA_K_INV_REG><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         else k_direct<NNCA_K_GAUSS><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         HIPCHECK(hipGetLastError());
     }

@@ -830,14 +830,16 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
     auto &W = H->multi;
     Level &L = H->lev[l];
     const int kap = H->kappa, kind = H->kind;
-    const double prm64 = 1.0 / (H->hparam * H->hparam);
-    const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
+    const double prm64 = kernel_prm64(kind, H->hparam);
+    const float prm32 = kernel_prm32(kind, H->hparam);
     double *part = P > 1 ? W.part : nullptr;
     const int g = (int)(L.ncell * P);
     if (mixed && l > kap - H->fp32_levels) {
 #define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w32[l], W.R, W.u[l], part, prm32)
         if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
         else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
+        else if (kind == NNCA_K_LOG_REG) MF(NNCA_K_LOG_REG);
+        else if (kind == NNCA_K_INV_REG) MF(NNCA_K_INV_REG);
         else MF(NNCA_K_GAUSS);
 #undef MF
     } else {
@@ -845,10 +847,14 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
         if (!mixed) {
             if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 1);
             else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 1);
+            else if (kind == NNCA_K_LOG_REG) VM(NNCA_K_LOG_REG, 1);
+            else if (kind == NNCA_K_INV_REG) VM(NNCA_K_INV_REG, 1);
             else VM(NNCA_K_GAUSS, 1);
         } else {
             if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 2);
             else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 2);
+            else if (kind == NNCA_K_LOG_REG) VM(NNCA_K_LOG_REG, 2);
+            else if (kind == NNCA_K_INV_REG) VM(NNCA_K_INV_REG, 2);
             else VM(NNCA_K_GAUSS, 2);
         }
 #undef VM
@@ -933,8 +939,8 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
     k_gather_multi<TI><<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, X, ldx, W.xs,
                                                                  mixed ? W.xhi : nullptr, mixed ? W.xlo : nullptr);
     HIPCHECK(hipGetLastError());
-    const double prm64 = 1.0 / (H->hparam * H->hparam);
-    const float prm32 = (float)(1.4426950408889634 / (H->hparam * H->hparam));
+    const double prm64 = kernel_prm64(kind, H->hparam);
+    const float prm32 = kernel_prm32(kind, H->hparam);
     double *far = nullptr;
     if (kap >= lmin) {
         for (int l = kap; l >= lmin; l--) {
@@ -989,10 +995,14 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
     if (mixed) {
         if (kind == NNCA_K_INV_R) PP(float, NNCA_K_INV_R, W.xhi, W.xlo, prm32);
         else if (kind == NNCA_K_LOG_R) PP(float, NNCA_K_LOG_R, W.xhi, W.xlo, prm32);
+        else if (kind == NNCA_K_LOG_REG) PP(float, NNCA_K_LOG_REG, W.xhi, W.xlo, prm32);
+        else if (kind == NNCA_K_INV_REG) PP(float, NNCA_K_INV_REG, W.xhi, W.xlo, prm32);
         else PP(float, NNCA_K_GAUSS, W.xhi, W.xlo, prm32);
     } else {
         if (kind == NNCA_K_INV_R) PP(double, NNCA_K_INV_R, W.xs, (const double *)nullptr, prm64);
         else if (kind == NNCA_K_LOG_R) PP(double, NNCA_K_LOG_R, W.xs, (const double *)nullptr, prm64);
+        else if (kind == NNCA_K_LOG_REG) PP(double, NNCA_K_LOG_REG, W.xs, (const double *)nullptr, prm64);
+        else if (kind == NNCA_K_INV_REG) PP(double, NNCA_K_INV_REG, W.xs, (const double *)nullptr, prm64);
         else PP(double, NNCA_K_GAUSS, W.xs, (const double *)nullptr, prm64);
     }
 #undef PP

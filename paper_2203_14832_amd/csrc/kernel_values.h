@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "nnca.h"
 
 namespace nnca {
@@ -12,11 +14,37 @@ namespace nnca {
 // through the same interaction kernels as K; it is zero at r = 0.
 constexpr int K_GAUSS_DH = 103;
 
+// The parameter `prm` of the apply kernels, from the kernel's length scale:
+// the Gaussian 1/h^2 (FP64) or log2(e)/h^2 (FP32), the regularised 1/r its
+// a, the regularised log r 1/log(a^2); unused by the others.
+inline double kernel_prm64(int kind, double hp)
+{
+    if (kind == NNCA_K_GAUSS || kind == K_GAUSS_DH) return 1.0 / (hp * hp);
+    if (kind == NNCA_K_INV_REG) return hp;
+    if (kind == NNCA_K_LOG_REG) return 1.0 / std::log(hp * hp);
+    return 0.0;
+}
+inline float kernel_prm32(int kind, double hp)
+{
+    if (kind == NNCA_K_GAUSS || kind == K_GAUSS_DH) return (float)(1.4426950408889634 / (hp * hp));
+    return (float)kernel_prm64(kind, hp);
+}
+
 template <int KIND>
 __device__ inline float kv32(float d2, float prm)
 {
     if (KIND == NNCA_K_INV_R) return __builtin_amdgcn_rsqf(d2);
     if (KIND == NNCA_K_LOG_R) return 0.5f * logf(d2);
+    if (KIND == NNCA_K_INV_REG) {   // prm = a
+        const float rs = __builtin_amdgcn_rsqf(d2);
+        return d2 >= prm * prm ? prm * rs : (d2 * rs) / prm;
+    }
+    if (KIND == NNCA_K_LOG_REG) {   // prm = 1 / log(a^2)
+        const float l = logf(d2), t = 1.0f / prm;
+        if (l >= t) return l * prm;
+        const float r = sqrtf(d2), a = expf(0.5f * t);
+        return (r * (0.5f * l - 1.0f)) / (a * (0.5f * t - 1.0f));
+    }
     if (KIND == K_GAUSS_DH) {
         float t = d2 * prm;   // log2(e) r^2 / h^2
         return (t * 0.693147180559945309f) * __builtin_amdgcn_exp2f(-t);
@@ -28,6 +56,13 @@ __device__ inline double kv64(double d2, double prm)
 {
     if (KIND == NNCA_K_INV_R) return 1.0 / sqrt(d2);
     if (KIND == NNCA_K_LOG_R) return 0.5 * log(d2);
+    if (KIND == NNCA_K_INV_REG) return d2 >= prm * prm ? prm / sqrt(d2) : sqrt(d2) / prm;   // prm = a
+    if (KIND == NNCA_K_LOG_REG) {   // prm = 1 / log(a^2)
+        const double l = log(d2), t = 1.0 / prm;
+        if (l >= t) return l * prm;
+        const double r = sqrt(d2), a = exp(0.5 * t);
+        return (r * (0.5 * l - 1.0)) / (a * (0.5 * t - 1.0));
+    }
     if (KIND == K_GAUSS_DH) {
         double t = d2 * prm;  // r^2 / h^2
         return t * exp(-t);

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnnca.so")
 
-KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3}
+KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "log_reg": 4, "inv_reg": 5}
 PRECISION = {"fp64": 0, "mixed": 1}
 DTYPE_F32, DTYPE_F64 = 0, 1
 MAX_LEVELS = 64

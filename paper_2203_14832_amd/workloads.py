@@ -14,6 +14,8 @@ Configurations (the point distributions of the paper's experiments, Sec. 5):
       std 0.3), exp(-r^2/h^2) with h=0.5, leaf 128, tol 1e-6
   c5  32 independent problems, N_b = round(exp(U(ln 1e4, ln 2e5))) points
       uniform in [-1,1]^3, 1/r, leaf 64, tol 1e-6, 8 columns each
+The experiments' other point sets: chebyshev_grid (Exp. 2 and 4) and
+nystrom_grid (the integral equation of Exp. 5).
 """
 from __future__ import annotations
 
@@ -72,6 +74,14 @@ def cotangent(config: str, n: int | None = None) -> np.ndarray:
     c = CONFIGS[config]
     n = c["n"] if n is None else int(n)
     return np.random.default_rng(seed_of(config) + 100).standard_normal(n)
+
+
+def chebyshev_grid(n_axis: int, dim: int) -> np.ndarray:
+    """(n_axis^dim, dim) points of the tensor-product Chebyshev grid of
+    [-1,1]^dim (Exp. 2 and 4): the first-kind nodes cos((2i + 1) pi / (2 n))
+    on every axis."""
+    c = np.cos((2.0 * np.arange(n_axis) + 1.0) * np.pi / (2.0 * n_axis))
+    return np.stack(np.meshgrid(*([c] * dim), indexing="ij"), -1).reshape(-1, dim)
 
 
 def nystrom_grid(n_axis: int, seed: int = 1005):
