@@ -75,6 +75,17 @@ def lib():
         L.orc_h2_frozen.restype = P; L.orc_h2_frozen.argtypes = [P, f64]
         L.orc_h2_grad_h.restype = f64; L.orc_h2_grad_h.argtypes = [P, P, P, i32]
         L.orc_dense_grad_h.restype = f64; L.orc_dense_grad_h.argtypes = [P, i64, i32, f64, P, P]
+        L.orc_tree_build2.restype = P
+        L.orc_tree_build2.argtypes = [P, i64, P, i64, i32, i32, i64, i64]
+        L.orc_g2_new.restype = P; L.orc_g2_new.argtypes = [P, i32, f64, f64, i32]
+        L.orc_g2_lmin.restype = i32; L.orc_g2_lmin.argtypes = [P]
+        L.orc_g2_build.restype = i32; L.orc_g2_build.argtypes = [P]
+        L.orc_g2_free.argtypes = [P]
+        L.orc_g2_cell.restype = i32; L.orc_g2_cell.argtypes = [P, i32, i32, i64, P, P, P, P, P]
+        L.orc_g2_matvec.argtypes = [P, P, P, i64, i32]
+        L.orc_g2_interactions.argtypes = [P, P]
+        L.orc_direct2.restype = None
+        L.orc_direct2.argtypes = [P, i64, P, i64, i32, i32, f64, P, i64, P, i64, P]
         _lib = L
     return _lib
 
@@ -125,6 +136,23 @@ def direct(points, x, kind: str, h: float = 1.0, rows=None) -> np.ndarray:
         nr = r.shape[0]
     Y = np.zeros((nrhs, nr))
     lib().orc_direct(_p(pts), n, d, KINDS[kind], float(h), _p(X), nrhs, _p(r), nr, _p(Y))
+    return Y[0] if vec else Y.T.copy()
+
+
+def direct2(P, Q, x, kind: str, h: float = 1.0, rows=None) -> np.ndarray:
+    """Dense sum of the general case y_i = sum_j K(p_i, q_j) x_j
+    (compensated, FP64); ``x`` is (nq,) or (nq, r)."""
+    Pp = np.ascontiguousarray(P, dtype=np.float64)
+    Qp = np.ascontiguousarray(Q, dtype=np.float64)
+    np_, d = Pp.shape
+    nq = Qp.shape[0]
+    x = np.asarray(x, dtype=np.float64)
+    vec = x.ndim == 1
+    X = np.ascontiguousarray(x.reshape(nq, -1).T)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = np_ if r is None else r.shape[0]
+    Y = np.zeros((X.shape[0], nr))
+    lib().orc_direct2(_p(Pp), np_, _p(Qp), nq, d, KINDS[kind], float(h), _p(X), X.shape[0], _p(r), nr, _p(Y))
     return Y[0] if vec else Y.T.copy()
 
 
@@ -198,6 +226,93 @@ class Tree:
         idx = np.zeros(max(tot, 1), np.int64)
         lib().orc_tree_lists(self._h, l, w, _p(ptr), _p(idx))
         return ptr, idx[:tot]
+
+
+class Tree2(Tree):
+    """The tree of the general case over the union of targets P and sources
+    Q (Sec. 2.1: a leaf holds at most ``leaf_size`` points of each set).
+    Union index i < np is p_i, np + j is q_j."""
+
+    def __init__(self, P, Q, leaf_size: int, eta2=None):
+        Pp = np.ascontiguousarray(P, dtype=np.float64)
+        Qp = np.ascontiguousarray(Q, dtype=np.float64)
+        self.np, self.d = Pp.shape
+        self.nq = Qp.shape[0]
+        self.n = self.np + self.nq
+        if eta2 is None:
+            eta2 = (self.d, 1)
+        num, den = eta2
+        self._free = lib().orc_tree_free
+        self._h = lib().orc_tree_build2(_p(Pp), self.np, _p(Qp), self.nq, self.d, int(leaf_size), int(num), int(den))
+        if not self._h:
+            raise ValueError("oracle tree build rejected its arguments")
+        self.kappa = lib().orc_tree_kappa(self._h)
+
+    def counts(self, l: int):
+        """(targets, sources) per cell of level l."""
+        c = self.cells(l)
+        src = self.order() >= self.np
+        ns = np.array([src[f:f + k].sum() for f, k in zip(c["first"], c["count"])], np.int64)
+        return c["count"] - ns, ns
+
+
+class H2General:
+    """NNCA of the general case (Sec. 2.3): incoming and outgoing pivots and
+    operators per cell and the matvec y = A~ x, A_ij = K(p_i, q_j)."""
+
+    def __init__(self, tree: Tree2, kind: str, tol: float, h: float = 1.0, policy: int = 1):
+        self.tree = tree
+        self.kind = kind
+        self.h = float(h)
+        self._free = lib().orc_g2_free
+        self._h = lib().orc_g2_new(tree._h, KINDS[kind], float(h), float(tol), int(policy))
+        if not self._h:
+            raise ValueError("not a tree of the general case")
+        self.lmin = lib().orc_g2_lmin(self._h)
+        lib().orc_g2_build(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and not sys.is_finalizing():
+            self._free(self._h)
+        self._h = None
+
+    def cell(self, half: str, l: int, b: int):
+        """half "in": piv = t^{B,i} (P indices), colpts = s^{B,i} (Q), C (m x k)
+        = U_B or the stacked C_{B_c B}; half "out": piv = s^{B,o} (Q),
+        colpts = t^{B,o} (P), C = V_B or the stacked T_{B B_c}^T."""
+        h = 0 if half == "in" else 1
+        mnk = np.zeros(4, np.int64)
+        if lib().orc_g2_cell(self._h, h, l, b, _p(mnk), None, None, None, None) != 0:
+            raise KeyError((half, l, b))
+        m, n, k, pt = (int(v) for v in mnk)
+        piv = np.zeros(max(k, 1), np.int64)
+        col = np.zeros(max(k, 1), np.int64)
+        tt = np.zeros(max(m, 1), np.int64)
+        Cm = np.zeros(max(m * k, 1))
+        lib().orc_g2_cell(self._h, h, l, b, None, _p(piv), _p(col), _p(tt), _p(Cm))
+        return dict(m=m, n=n, k=k, passthrough=bool(pt), piv=piv[:k].copy(),
+                    colpts=None if pt else col[:k].copy(), tt=tt[:m].copy(),
+                    C=Cm[: m * k].reshape(m, k).copy())
+
+    def matvec(self, x, adjoint: bool = False) -> np.ndarray:
+        """A~ x (x over Q) or, with adjoint, A~^T x (x over P)."""
+        x = np.asarray(x, dtype=np.float64)
+        nin, nout = (self.tree.np, self.tree.nq) if adjoint else (self.tree.nq, self.tree.np)
+        vec = x.ndim == 1
+        X = np.ascontiguousarray(x.reshape(nin, -1).T)
+        Y = np.zeros((X.shape[0], nout))
+        lib().orc_g2_matvec(self._h, _p(X), _p(Y), X.shape[0], int(adjoint))
+        return Y[0] if vec else Y.T.copy()
+
+    def interactions(self):
+        out = np.zeros(2 + self.tree.kappa + 1, np.int64)
+        lib().orc_g2_interactions(self._h, _p(out))
+        return int(out[0]), int(out[1])
+
+    def interactions_by_level(self):
+        out = np.zeros(2 + self.tree.kappa + 1, np.int64)
+        lib().orc_g2_interactions(self._h, _p(out))
+        return [int(v) for v in out[2:]]
 
 
 class H2:

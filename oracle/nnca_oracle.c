@@ -231,6 +231,8 @@ typedef struct {
 struct orc_tree {
     int d, nu, kmax, kappa;
     int64_t n;
+    int64_t split;          /* general case: original indices < split are the
+                               targets P, the rest the sources Q; -1 if P = Q */
     int64_t eta_num, eta_den;
     double lo[3], L;
     double *pts;            /* n x d, in sorted order                        */
@@ -316,12 +318,12 @@ static int64_t box_cells(const orc_tree *T, int l, const int64_t *c, int R, int6
     return cnt;
 }
 
-orc_tree *orc_tree_build(const double *pts, int64_t n, int d, int leaf_size,
-                         int64_t eta_num, int64_t eta_den)
+static orc_tree *tree_build(const double *pts, int64_t n, int d, int leaf_size,
+                            int64_t eta_num, int64_t eta_den, int64_t split)
 {
     if (n < 1 || (d != 2 && d != 3) || leaf_size < 1 || eta_num < 1 || eta_den < 1) return NULL;
     orc_tree *T = (orc_tree *)calloc(1, sizeof(orc_tree));
-    T->d = d; T->n = n; T->nu = leaf_size;
+    T->d = d; T->n = n; T->nu = leaf_size; T->split = split;
     T->eta_num = eta_num; T->eta_den = eta_den;
     T->kmax = 60 / d;
 
@@ -362,18 +364,21 @@ orc_tree *orc_tree_build(const double *pts, int64_t n, int d, int leaf_size,
     }
     free(ki);
 
-    /* Depth: the first level at which no cell holds more than nu points
-     * (capped at kmax; all points identical => a single leaf).             */
+    /* Depth (Sec. 2.1): the first level at which no cell holds more than nu
+     * points of P and no more than nu points of Q (capped at kmax; all points
+     * identical => a single leaf).  With P = Q the two counts are one.      */
     T->kappa = T->kmax;
     if (T->L == 0.0) T->kappa = 0;
     else
         for (int l = 0; l <= T->kmax; l++) {
             int shift = d * (T->kmax - l);
-            int64_t run = 1, maxrun = 1;
-            for (int64_t p = 1; p < n; p++) {
-                if ((T->key[p] >> shift) == (T->key[p - 1] >> shift)) run++;
-                else run = 1;
-                if (run > maxrun) maxrun = run;
+            int64_t runp = 0, runq = 0, maxrun = 0;
+            for (int64_t p = 0; p < n; p++) {
+                if (p > 0 && (T->key[p] >> shift) != (T->key[p - 1] >> shift)) runp = runq = 0;
+                if (split < 0 || T->order[p] < split) runp++;
+                else runq++;
+                if (runp > maxrun) maxrun = runp;
+                if (runq > maxrun) maxrun = runq;
             }
             if (maxrun <= leaf_size) { T->kappa = l; break; }
         }
@@ -485,6 +490,27 @@ orc_tree *orc_tree_build(const double *pts, int64_t n, int d, int leaf_size,
     return T;
 }
 
+orc_tree *orc_tree_build(const double *pts, int64_t n, int d, int leaf_size,
+                         int64_t eta_num, int64_t eta_den)
+{
+    return tree_build(pts, n, d, leaf_size, eta_num, eta_den, -1);
+}
+
+/* The tree of the general case (Sec. 2.1): one tree over the union of the
+ * targets P (np points) and the sources Q (nq points); a point of the union
+ * has original index i < np for p_i and np + j for q_j.                      */
+orc_tree *orc_tree_build2(const double *P, int64_t np, const double *Q, int64_t nq, int d, int leaf_size,
+                          int64_t eta_num, int64_t eta_den)
+{
+    if (np < 1 || nq < 1 || (d != 2 && d != 3)) return NULL;
+    double *Z = (double *)malloc(sizeof(double) * (np + nq) * d);
+    memcpy(Z, P, sizeof(double) * np * d);
+    memcpy(Z + np * d, Q, sizeof(double) * nq * d);
+    orc_tree *T = tree_build(Z, np + nq, d, leaf_size, eta_num, eta_den, np);
+    free(Z);
+    return T;
+}
+
 void orc_tree_free(orc_tree *T)
 {
     if (!T) return;
@@ -555,6 +581,8 @@ static double dot256(const double *a, const double *b, int64_t n)
  * V (kcap x n) is scratch.  kcap = min(m, n).
  *
  * Step k (1-based):
+ * With swap = 1 the block is the transpose, A(r, c) = K(P[cols[c]], P[rows[r]]).
+ *
  *   1. residual of row i_k:  R(c) = K(i_k, c) - sum_{l<k} u_l(i_k) v_l(c);
  *   2. j_k = argmax over unused columns of |R(c)|, ties to the smallest c;
  *      if that maximum is 0 the row is marked used without a cross and the
@@ -569,7 +597,7 @@ static double dot256(const double *a, const double *b, int64_t n)
  *   7. i_{k+1} = argmax over unused rows of |u_k(r)|, ties to the smallest r. */
 static int64_t aca_core(const double *P, int d, int kind, double hparam,
                         const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
-                        double tol, int64_t *rowpos, int64_t *colpos, double *U, double *V)
+                        double tol, int64_t *rowpos, int64_t *colpos, double *U, double *V, int swap)
 {
     int64_t kcap = m < n ? m : n;
     char *rused = (char *)calloc(m, 1);
@@ -582,7 +610,7 @@ static int64_t aca_core(const double *P, int d, int kind, double hparam,
     while (k < kcap) {
         const double *pi = P + rows[i] * d;
         for (int64_t c = 0; c < n; c++) {
-            double r = kern(kind, hparam, pi, P + cols[c] * d, d);
+            double r = swap ? kern(kind, hparam, P + cols[c] * d, pi, d) : kern(kind, hparam, pi, P + cols[c] * d, d);
             for (int64_t l = 0; l < k; l++) r = r - U[l * m + i] * V[l * n + c];
             R[c] = r;
         }
@@ -604,7 +632,7 @@ static int64_t aca_core(const double *P, int d, int kind, double hparam,
         const double *pj = P + cols[jk] * d;
         for (int64_t r = 0; r < m; r++) {
             if (rused[r]) { uk[r] = 0.0; continue; }
-            double u = kern(kind, hparam, P + rows[r] * d, pj, d);
+            double u = swap ? kern(kind, hparam, pj, P + rows[r] * d, d) : kern(kind, hparam, P + rows[r] * d, pj, d);
             for (int64_t l = 0; l < k; l++) u = u - V[l * n + jk] * U[l * m + r];
             uk[r] = u;
         }
@@ -673,7 +701,7 @@ int64_t orc_aca_block(const double *prow, int64_t m, const double *pcol, int64_t
     memcpy(P + m * d, pcol, sizeof(double) * n * d);
     for (int64_t r = 0; r < m; r++) rows[r] = r;
     for (int64_t c = 0; c < n; c++) cols[c] = m + c;
-    int64_t k = aca_core(P, d, kind, hparam, rows, m, cols, n, tol, rowpos, colpos, U, V);
+    int64_t k = aca_core(P, d, kind, hparam, rows, m, cols, n, tol, rowpos, colpos, U, V, 0);
     if (C) transfer_from_aca(m, k, rowpos, U, C);
     free(P); free(rows); free(cols);
     return k;
@@ -744,7 +772,7 @@ static void cell_pivots(orc_h2 *H, int l, int64_t b)
     }
     /* s~^{B,i}: points of the interaction list at a leaf; else the pivots
      * s^{B'',o} = t^{B'',i} of the children B'' of every B' in IL(B).       */
-    int64_t *ss;
+    int64_t *ss = NULL;
     for (int pass = 0; pass < 2; pass++) {
         n = 0;
         for (int64_t e = lv->il_ptr[b]; e < lv->il_ptr[b + 1]; e++) {
@@ -787,7 +815,7 @@ static void cell_pivots(orc_h2 *H, int l, int64_t b)
         double *V = (double *)malloc(sizeof(double) * kcap * n);
         int64_t *rp = (int64_t *)malloc(sizeof(int64_t) * kcap);
         int64_t *cp = (int64_t *)malloc(sizeof(int64_t) * kcap);
-        int64_t k = aca_core(T->pts, T->d, H->kind, H->hparam, cb->tt, m, ss, n, H->tol, rp, cp, U, V);
+        int64_t k = aca_core(T->pts, T->d, H->kind, H->hparam, cb->tt, m, ss, n, H->tol, rp, cp, U, V, 0);
         cb->k = k;
         cb->rowpos = rp;
         cb->colpos = cp;
@@ -1364,4 +1392,408 @@ double orc_dense_grad_h(const double *pts, int64_t n, int d, double h, const dou
     }
     free(row);
     return sum + comp;
+}
+
+/* ------------------------------------------------------------------------- */
+/* General case P != Q (Sec. 2.3): two ACAs per cell                          */
+/* ------------------------------------------------------------------------- */
+
+/* Every cell carries two halves.  Half 0 (incoming) compresses
+ * A(t~^{B,i}, s~^{B,i}): rows are the cell's own targets (a leaf's t^B, else
+ * the children's t^{B_c,i}), columns the sources of the interaction-list
+ * region (a leaf: s^{B'} for B' in IL(B); else the outgoing pivots s^{B'',o}
+ * of the children of every B' in IL(B)).  Its row pivots are t^{B,i}, its
+ * column pivots s^{B,i}, and C = U~ L^{-1} is U_B (leaf) or the stacked
+ * C_{B_c B} (Sec. 2.3.1).
+ *
+ * Half 1 (outgoing) compresses A(t~^{B,o}, s~^{B,o}) with rows t~^{B,o} (the
+ * targets of the interaction-list region: a leaf's t^{B'}, else the incoming
+ * pivots t^{B'',i} of the IL cells' children) and columns s~^{B,o} (a leaf's
+ * s^B, else the children's s^{B_c,o}).  The ACA runs on the transposed block,
+ * its first pivot taken among the cell's own sources, so that its row pivots
+ * are s^{B,o} and its column pivots t^{B,o}; then
+ *   C = U~ L^{-1} = A(s~^{B,o}, t^{B,o}) A(s^{B,o}, t^{B,o})^{-1}
+ * (entries read as K(p, q)) is the transpose of
+ *   A(t^{B,o}, s^{B,o})^{-1} A(t^{B,o}, s~^{B,o}),
+ * i.e. V_B at a leaf and the stacked T_{B B_c}^T above (Sec. 2.3.1).  With
+ * P = Q and a symmetric kernel the two halves are the same ACA, which is the
+ * one-ACA symmetric case of Sec. 5 (t^{B,o} = s^{B,i}, s^{B,o} = t^{B,i}).
+ * Pass-through cells (empty far-field candidates, or fewer candidate columns
+ * than rows under policy 1) keep every row with the identity operator.      */
+
+struct orc_g2 {
+    orc_tree *T;
+    int kind;
+    double hparam, tol;
+    int policy, lmin;
+    ocell **half[2];    /* [0] incoming, [1] outgoing; levels 0..kappa       */
+};
+
+static int is_target(const orc_tree *T, int64_t pos) { return T->order[pos] < T->split; }
+
+orc_g2 *orc_g2_new(orc_tree *T, int kind, double hparam, double tol, int policy)
+{
+    if (T->split < 0) return NULL;
+    orc_g2 *G = (orc_g2 *)calloc(1, sizeof(orc_g2));
+    G->T = T; G->kind = kind; G->hparam = hparam; G->tol = tol; G->policy = policy;
+    for (int h = 0; h < 2; h++) {
+        G->half[h] = (ocell **)calloc(T->kappa + 1, sizeof(ocell *));
+        for (int l = 0; l <= T->kappa; l++) G->half[h][l] = (ocell *)calloc(T->lev[l].ncell, sizeof(ocell));
+    }
+    G->lmin = T->kappa + 1;
+    for (int l = 1; l <= T->kappa; l++)
+        if (T->lev[l].il_ptr[T->lev[l].ncell] > 0) { G->lmin = l; break; }
+    return G;
+}
+
+int orc_g2_lmin(const orc_g2 *G) { return G->lmin; }
+
+/* Positions of a leaf cell's own points of one class: targets for half 0,
+ * sources for half 1 (want_target = 1 - h).  With out == NULL only counts.  */
+static int64_t class_positions(const orc_tree *T, const olevel *lv, int64_t b, int want_target, int64_t *out)
+{
+    int64_t k = 0;
+    for (int64_t r = 0; r < lv->count[b]; r++) {
+        int64_t pos = lv->first[b] + r;
+        if (is_target(T, pos) == want_target) {
+            if (out) out[k] = pos;
+            k++;
+        }
+    }
+    return k;
+}
+
+/* Candidates of Sec. 2.3.2 step 1 for half h of cell b at level l. */
+static int64_t g2_rows(const orc_g2 *G, int h, int l, int64_t b, int64_t *out)
+{
+    const orc_tree *T = G->T;
+    const olevel *lv = &T->lev[l];
+    if (l == T->kappa) return class_positions(T, lv, b, 1 - h, out);
+    int64_t m = 0;
+    for (int64_t c = lv->child_first[b]; c < lv->child_first[b] + lv->child_count[b]; c++) {
+        const ocell *cc = &G->half[h][l + 1][c];
+        if (out) memcpy(out + m, cc->piv, sizeof(int64_t) * cc->k);
+        m += cc->k;
+    }
+    return m;
+}
+static int64_t g2_cols(const orc_g2 *G, int h, int l, int64_t b, int64_t *out)
+{
+    const orc_tree *T = G->T;
+    const olevel *lv = &T->lev[l];
+    int64_t n = 0;
+    for (int64_t e = lv->il_ptr[b]; e < lv->il_ptr[b + 1]; e++) {
+        int64_t bp = lv->il[e];
+        if (l == T->kappa) {
+            n += class_positions(T, lv, bp, h, out ? out + n : NULL);
+        } else {
+            /* half 0 takes the IL children's outgoing pivots s^{B'',o},
+             * half 1 their incoming pivots t^{B'',i}                        */
+            for (int64_t c = lv->child_first[bp]; c < lv->child_first[bp] + lv->child_count[bp]; c++) {
+                const ocell *cc = &G->half[1 - h][l + 1][c];
+                if (out) memcpy(out + n, cc->piv, sizeof(int64_t) * cc->k);
+                n += cc->k;
+            }
+        }
+    }
+    return n;
+}
+
+static void g2_half_pivots(orc_g2 *G, int h, int l, int64_t b)
+{
+    orc_tree *T = G->T;
+    ocell *cb = &G->half[h][l][b];
+    int64_t m = g2_rows(G, h, l, b, NULL);
+    int64_t n = g2_cols(G, h, l, b, NULL);
+    cb->tt = (int64_t *)malloc(sizeof(int64_t) * (m + 1));
+    int64_t *ss = (int64_t *)malloc(sizeof(int64_t) * (n + 1));
+    g2_rows(G, h, l, b, cb->tt);
+    g2_cols(G, h, l, b, ss);
+    cb->m = m;
+    cb->n = n;
+    if (n == 0 || (G->policy == 1 && n < m)) {
+        cb->passthrough = 1;
+        cb->k = m;
+        cb->piv = (int64_t *)malloc(sizeof(int64_t) * (m + 1));
+        cb->rowpos = (int64_t *)malloc(sizeof(int64_t) * (m + 1));
+        cb->colpos = (int64_t *)malloc(sizeof(int64_t) * 1);
+        cb->colpts = (int64_t *)malloc(sizeof(int64_t) * 1);
+        cb->C = (double *)calloc(m * m + 1, sizeof(double));
+        for (int64_t r = 0; r < m; r++) {
+            cb->piv[r] = cb->tt[r];
+            cb->rowpos[r] = r;
+            cb->C[r * m + r] = 1.0;
+        }
+    } else {
+        int64_t kcap = m < n ? m : n;
+        double *U = (double *)malloc(sizeof(double) * (m * kcap + 1));
+        double *V = (double *)malloc(sizeof(double) * (kcap * n + 1));
+        int64_t *rp = (int64_t *)malloc(sizeof(int64_t) * (kcap + 1));
+        int64_t *cp = (int64_t *)malloc(sizeof(int64_t) * (kcap + 1));
+        int64_t k = aca_core(T->pts, T->d, G->kind, G->hparam, cb->tt, m, ss, n, G->tol, rp, cp, U, V, h);
+        cb->k = k;
+        cb->rowpos = rp;
+        cb->colpos = cp;
+        cb->piv = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+        cb->colpts = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+        for (int64_t q = 0; q < k; q++) {
+            cb->piv[q] = cb->tt[rp[q]];
+            cb->colpts[q] = ss[cp[q]];
+        }
+        cb->C = (double *)malloc(sizeof(double) * (m * k + 1));
+        transfer_from_aca(m, k, rp, U, cb->C);
+        free(U); free(V);
+    }
+    free(ss);
+    cb->done = 1;
+}
+
+/* Both halves of every cell, one reverse level-order traversal (Sec. 2.3.2). */
+int orc_g2_build(orc_g2 *G)
+{
+    orc_tree *T = G->T;
+    for (int l = T->kappa; l >= G->lmin; l--) {
+        int64_t nc = T->lev[l].ncell;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t e = 0; e < 2 * nc; e++) g2_half_pivots(G, (int)(e % 2), l, e / 2);
+    }
+    return 0;
+}
+
+void orc_g2_free(orc_g2 *G)
+{
+    if (!G) return;
+    for (int h = 0; h < 2; h++) {
+        for (int l = 0; l <= G->T->kappa; l++) {
+            for (int64_t b = 0; b < G->T->lev[l].ncell; b++) {
+                ocell *c = &G->half[h][l][b];
+                free(c->tt); free(c->piv); free(c->rowpos); free(c->colpos); free(c->colpts); free(c->C);
+            }
+            free(G->half[h][l]);
+        }
+        free(G->half[h]);
+    }
+    free(G);
+}
+
+/* Index of a union point inside its own set: p_i -> i, q_j -> j. */
+static int64_t own_index(const orc_tree *T, int64_t pos)
+{
+    int64_t z = T->order[pos];
+    return z < T->split ? z : z - T->split;
+}
+
+/* Half h of a cell: m, n, k, pass-through flag; piv (k row pivots), colpts
+ * (k column pivots), tt (m candidate rows), as indices into P or Q (half 0:
+ * piv and tt in P, colpts in Q; half 1 the other way round); C (m x k).      */
+int orc_g2_cell(const orc_g2 *G, int h, int l, int64_t b, int64_t *mnk, int64_t *piv, int64_t *colpts,
+                int64_t *tt, double *C)
+{
+    if (h < 0 || h > 1 || l < 0 || l > G->T->kappa || b < 0 || b >= G->T->lev[l].ncell) return -1;
+    const ocell *c = &G->half[h][l][b];
+    if (!c->done) return -1;
+    if (mnk) { mnk[0] = c->m; mnk[1] = c->n; mnk[2] = c->k; mnk[3] = c->passthrough; }
+    if (piv) for (int64_t q = 0; q < c->k; q++) piv[q] = own_index(G->T, c->piv[q]);
+    if (colpts && !c->passthrough) for (int64_t q = 0; q < c->k; q++) colpts[q] = own_index(G->T, c->colpts[q]);
+    if (tt) for (int64_t q = 0; q < c->m; q++) tt[q] = own_index(G->T, c->tt[q]);
+    if (C) memcpy(C, c->C, sizeof(double) * c->m * c->k);
+    return 0;
+}
+
+/* y = A~ x (adjoint = 0: x has nq entries per column, y np) or y = A~^T x
+ * (adjoint = 1: x has np entries, y nq), column-major, original order.
+ * A~ = sum over admissible pairs of U_X S_{X,Y} V_Y^T plus the near field
+ * (Sec. 3-4):
+ *   upward    w^{B,o} = V_B^T x^B at a leaf, sum_c T_{B B_c} w^{B_c,o} above;
+ *   transverse u^{B,i} = sum_{B' in IL(B)} S_{B,B'} w^{B',o},
+ *              S_{B,B'} = A(t^{B,i}, s^{B',o});
+ *   downward  u^{B_c,i} += C_{B_c B} u^{B,i};
+ *   leaves    y^B = U_B u^{B,i} + sum_{B' in N(B)} A(t^B, s^{B'}) x^{B'}.
+ * The transposed product runs the same passes with the halves exchanged:
+ * up with U^T and C^T, S^T across, down with T^T and V.                     */
+void orc_g2_matvec(const orc_g2 *G, const double *x, double *y, int64_t nrhs, int adjoint)
+{
+    const orc_tree *T = G->T;
+    int d = T->d, kap = T->kappa;
+    int64_t n = T->n, np = T->split, nq = T->n - T->split;
+    int64_t nin = adjoint ? np : nq, nout = adjoint ? nq : np;
+    const int sh = adjoint ? 0 : 1;   /* half gathered on the way up      */
+    const int dh = 1 - sh;            /* half scattered on the way down    */
+    ocell *const *S = G->half[sh];
+    ocell *const *D = G->half[dh];
+    double *xs = (double *)calloc(n, sizeof(double));
+    double *ys = (double *)calloc(n, sizeof(double));
+    double **w = (double **)calloc(kap + 1, sizeof(double *));
+    double **u = (double **)calloc(kap + 1, sizeof(double *));
+    int64_t **offs = (int64_t **)calloc(kap + 1, sizeof(int64_t *));
+    int64_t **offd = (int64_t **)calloc(kap + 1, sizeof(int64_t *));
+    for (int l = G->lmin; l <= kap; l++) {
+        int64_t nc = T->lev[l].ncell;
+        offs[l] = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+        offd[l] = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+        offs[l][0] = offd[l][0] = 0;
+        for (int64_t b = 0; b < nc; b++) {
+            offs[l][b + 1] = offs[l][b] + S[l][b].k;
+            offd[l][b + 1] = offd[l][b] + D[l][b].k;
+        }
+        w[l] = (double *)calloc(offs[l][nc] + 1, sizeof(double));
+        u[l] = (double *)calloc(offd[l][nc] + 1, sizeof(double));
+    }
+    for (int64_t col = 0; col < nrhs; col++) {
+        for (int64_t p = 0; p < n; p++) {
+            int64_t z = T->order[p];
+            int inp = adjoint ? (z < np) : (z >= np);
+            xs[p] = inp ? x[col * nin + (adjoint ? z : z - np)] : 0.0;
+        }
+        for (int l = G->lmin; l <= kap; l++) {
+            memset(w[l], 0, sizeof(double) * (offs[l][T->lev[l].ncell] + 1));
+            memset(u[l], 0, sizeof(double) * (offd[l][T->lev[l].ncell] + 1));
+        }
+        /* upward pass with the gathered half's operators (C^T times the
+         * stacked input: x at a leaf, the children's w above)               */
+        for (int l = kap; l >= G->lmin; l--) {
+            const olevel *lv = &T->lev[l];
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t b = 0; b < lv->ncell; b++) {
+                const ocell *cb = &S[l][b];
+                double *xt = (double *)malloc(sizeof(double) * (cb->m + 1));
+                if (l == kap) {
+                    for (int64_t r = 0; r < cb->m; r++) xt[r] = xs[cb->tt[r]];
+                } else {
+                    int64_t r = 0;
+                    for (int64_t c = lv->child_first[b]; c < lv->child_first[b] + lv->child_count[b]; c++)
+                        for (int64_t q = offs[l + 1][c]; q < offs[l + 1][c + 1]; q++) xt[r++] = w[l + 1][q];
+                }
+                double *wb = w[l] + offs[l][b];
+                for (int64_t q = 0; q < cb->k; q++) {
+                    double s = 0.0;
+                    for (int64_t r = 0; r < cb->m; r++) s += cb->C[r * cb->k + q] * xt[r];
+                    wb[q] = s;
+                }
+                free(xt);
+            }
+        }
+        /* transverse pass: K between the scattered half's pivots of B and
+         * the gathered half's pivots of B' in IL(B), entries K(p, q)       */
+        for (int l = G->lmin; l <= kap; l++) {
+            const olevel *lv = &T->lev[l];
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t b = 0; b < lv->ncell; b++) {
+                const ocell *cb = &D[l][b];
+                double *ub = u[l] + offd[l][b];
+                for (int64_t e = lv->il_ptr[b]; e < lv->il_ptr[b + 1]; e++) {
+                    int64_t bp = lv->il[e];
+                    const ocell *cp = &S[l][bp];
+                    const double *wp = w[l] + offs[l][bp];
+                    for (int64_t i = 0; i < cb->k; i++) {
+                        double s = 0.0;
+                        for (int64_t j = 0; j < cp->k; j++) {
+                            const double *a = T->pts + cb->piv[i] * d, *bb = T->pts + cp->piv[j] * d;
+                            double kij = adjoint ? kern(G->kind, G->hparam, bb, a, d)
+                                                 : kern(G->kind, G->hparam, a, bb, d);
+                            s += kij * wp[j];
+                        }
+                        ub[i] += s;
+                    }
+                }
+            }
+        }
+        /* downward pass with the scattered half's operators */
+        for (int l = G->lmin; l < kap; l++) {
+            const olevel *lv = &T->lev[l];
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t b = 0; b < lv->ncell; b++) {
+                const ocell *cb = &D[l][b];
+                const double *ub = u[l] + offd[l][b];
+                int64_t r = 0;
+                for (int64_t c = lv->child_first[b]; c < lv->child_first[b] + lv->child_count[b]; c++)
+                    for (int64_t q = offd[l + 1][c]; q < offd[l + 1][c + 1]; q++, r++) {
+                        double s = 0.0;
+                        for (int64_t j = 0; j < cb->k; j++) s += cb->C[r * cb->k + j] * ub[j];
+                        u[l + 1][q] += s;
+                    }
+            }
+        }
+        /* leaves: the scattered half's basis times u, plus the near field
+         * over the input points of the neighbours                           */
+        const olevel *lf = &T->lev[kap];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t b = 0; b < lf->ncell; b++) {
+            int64_t mo = class_positions(T, lf, b, adjoint ? 0 : 1, NULL);
+            int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (mo + 1));
+            class_positions(T, lf, b, adjoint ? 0 : 1, rows);
+            for (int64_t r = 0; r < mo; r++) {
+                int64_t p = rows[r];
+                double s = 0.0;
+                if (kap >= G->lmin) {
+                    const ocell *cb = &D[kap][b];
+                    const double *ub = u[kap] + offd[kap][b];
+                    for (int64_t j = 0; j < cb->k; j++) s += cb->C[r * cb->k + j] * ub[j];
+                }
+                for (int64_t e = lf->nb_ptr[b]; e < lf->nb_ptr[b + 1]; e++) {
+                    int64_t bp = lf->nb[e];
+                    for (int64_t q = lf->first[bp]; q < lf->first[bp] + lf->count[bp]; q++) {
+                        if (is_target(T, q) == !adjoint) continue;   /* only input points */
+                        const double *a = T->pts + p * d, *bb = T->pts + q * d;
+                        double kij = adjoint ? kern(G->kind, G->hparam, bb, a, d)
+                                             : kern(G->kind, G->hparam, a, bb, d);
+                        s += kij * xs[q];
+                    }
+                }
+                ys[p] = s;
+            }
+            free(rows);
+        }
+        for (int64_t p = 0; p < n; p++) {
+            int64_t z = T->order[p];
+            int outp = adjoint ? (z >= np) : (z < np);
+            if (outp) y[col * nout + (adjoint ? z - np : z)] = ys[p];
+        }
+    }
+    for (int l = G->lmin; l <= kap; l++) { free(w[l]); free(u[l]); free(offs[l]); free(offd[l]); }
+    free(w); free(u); free(offs); free(offd); free(xs); free(ys);
+}
+
+/* Kernel interactions of one product column: out[0] transverse total
+ * (k^{B,i} x k^{B',o} for every B' in IL(B)), out[1] near field
+ * (|t^B| x |s^{B'}| for every B' in N(B) of a leaf), out[2 + l] per level.  */
+void orc_g2_interactions(const orc_g2 *G, int64_t *out)
+{
+    const orc_tree *T = G->T;
+    out[0] = out[1] = 0;
+    for (int l = 0; l <= T->kappa; l++) out[2 + l] = 0;
+    for (int l = G->lmin; l <= T->kappa; l++) {
+        const olevel *lv = &T->lev[l];
+        for (int64_t b = 0; b < lv->ncell; b++)
+            for (int64_t e = lv->il_ptr[b]; e < lv->il_ptr[b + 1]; e++)
+                out[2 + l] += G->half[0][l][b].k * G->half[1][l][lv->il[e]].k;
+        out[0] += out[2 + l];
+    }
+    const olevel *lf = &T->lev[T->kappa];
+    for (int64_t b = 0; b < lf->ncell; b++)
+        for (int64_t e = lf->nb_ptr[b]; e < lf->nb_ptr[b + 1]; e++)
+            out[1] += class_positions(T, lf, b, 1, NULL) * class_positions(T, lf, lf->nb[e], 0, NULL);
+}
+
+/* Dense sum of the general case, y_i = sum_j K(p_i, q_j) x_j, Neumaier-
+ * compensated, with the textbook kernel (K = 0 at r = 0 for log and 1/r).   */
+void orc_direct2(const double *P, int64_t np, const double *Q, int64_t nq, int d, int kind, double hparam,
+                 const double *x, int64_t nrhs, const int64_t *rows, int64_t nrows, double *y)
+{
+    int64_t nr = rows ? nrows : np;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; r++) {
+        int64_t i = rows ? rows[r] : r;
+        for (int64_t c = 0; c < nrhs; c++) {
+            double sum = 0.0, comp = 0.0;
+            for (int64_t j = 0; j < nq; j++) {
+                double t = kern_ref(kind, hparam, P + i * d, Q + j * d, d) * x[c * nq + j];
+                double s2 = sum + t;
+                if (fabs(sum) >= fabs(t)) comp += (sum - s2) + t;
+                else comp += (t - s2) + sum;
+                sum = s2;
+            }
+            y[c * nr + r] = sum + comp;
+        }
+    }
 }

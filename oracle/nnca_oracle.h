@@ -49,4 +49,19 @@ double orc_h2_grad_h(const orc_h2 *H, const double *x, const double *g, int part
 double orc_dense_grad_h(const double *pts, int64_t n, int d, double h, const double *x, const double *g);
 int orc_num_threads(void);
 
+/* general case P != Q (targets P, sources Q) */
+typedef struct orc_g2 orc_g2;
+orc_tree *orc_tree_build2(const double *P, int64_t np, const double *Q, int64_t nq, int d, int leaf_size,
+                          int64_t eta_num, int64_t eta_den);
+orc_g2 *orc_g2_new(orc_tree *T, int kind, double hparam, double tol, int policy);
+int orc_g2_lmin(const orc_g2 *G);
+int orc_g2_build(orc_g2 *G);
+void orc_g2_free(orc_g2 *G);
+int orc_g2_cell(const orc_g2 *G, int h, int l, int64_t b, int64_t *mnk, int64_t *piv, int64_t *colpts,
+                int64_t *tt, double *C);
+void orc_g2_matvec(const orc_g2 *G, const double *x, double *y, int64_t nrhs, int adjoint);
+void orc_g2_interactions(const orc_g2 *G, int64_t *out);
+void orc_direct2(const double *P, int64_t np, const double *Q, int64_t nq, int d, int kind, double hparam,
+                 const double *x, int64_t nrhs, const int64_t *rows, int64_t nrows, double *y);
+
 #endif
