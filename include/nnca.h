@@ -4,7 +4,8 @@
  * Approximation".
  *
  * The operator is A_ij = K(p_i, p_j) over one point set P = Q in 2D or 3D
- * (Sec. 1; the symmetric case of Sec. 5).  nnca_build runs the single
+ * (Sec. 1; the symmetric case of Sec. 5), or A_ij = K(p_i, q_j) between
+ * targets P and sources Q (nnca_build_general, Sec. 2.1-2.3).  nnca_build runs the single
  * bottom-up traversal of Sec. 2.3.2 on the GPU (tree of Sec. 2.1, lists of
  * Sec. 2.2 / Table 1, one partially pivoted ACA per cell, Sec. 2.2.1, with the
  * transfer operators taken from the ACA by-products, Remark in Sec. 2.3.2).
@@ -127,6 +128,36 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
                        double tol, int32_t leaf_size, const nnca_build_options *opts,
                        void *stream, nnca_handle *out);
 
+/* The general case P != Q (Sec. 2.1, 2.3): A_ij = K(p_i, q_j) with targets
+ * P (np points) and sources Q (nq points), for rectangular sets such as the
+ * evaluation of a kernel expansion at new points.
+ *   targets: dim x np, SoA with stride ldp; sources: dim x nq, stride ldq;
+ *   both host memory if points_on_device == 0, else device memory; copied.
+ * One uniform tree covers P and Q; it stops at the first level where no
+ * cell holds more than leaf_size points of P or more than leaf_size of Q.
+ * Every cell runs two ACAs of the bottom-up traversal (Sec. 2.3.2): the
+ * incoming one on A(t~^{B,i}, s~^{B,i}) gives t^{B,i}, s^{B,i} and U_B (or
+ * the C_{B_c B}); the outgoing one gives t^{B,o}, s^{B,o} and V_B (or the
+ * T_{B B_c}).  The outgoing ACA runs on the transposed block, its first
+ * pivot among the cell's own sources, so that with P = Q it picks the
+ * incoming pivots of the symmetric case (Sec. 5).
+ * On such a handle nnca_matvec takes X with nq rows (Q's original order) and
+ * writes Y with np rows (P's original order); nnca_matvec_adjoint maps np
+ * rows to nq.  Both precisions and dtypes are supported; the transverse pass
+ * and the near field evaluate every ordered pair of cells (there is no
+ * symmetric form).  nnca_matvec_noalloc, nnca_matvec_backward,
+ * nnca_batch_create and nnca_gmres return NOT_SUPPORTED for it.
+ * Other arguments and errors as nnca_build; INVALID_ARG also for np or nq
+ * < 1 or np + nq > 2^30.                                                  */
+nnca_status nnca_build_general(const double *targets, int64_t np, int64_t ldp, const double *sources,
+                               int64_t nq, int64_t ldq, int32_t dim, int32_t points_on_device,
+                               int32_t kernel_kind, double length_scale, double tol, int32_t leaf_size,
+                               const nnca_build_options *opts, void *stream, nnca_handle *out);
+
+/* Rows (|P|) and columns (|Q|; n and n when P = Q) of the operator, and
+ * whether the handle is of the general case (host pointers, may be NULL).  */
+nnca_status nnca_query_shape(nnca_handle h, int64_t *rows, int64_t *cols, int32_t *general);
+
 /* Y = A~ X (Sec. 4) for nrhs columns.  X, Y: device memory of element type
  * dtype (an nnca_dtype), original point order, column-major with leading
  * dimensions ldx, ldy >= n (elements); X and Y must not overlap.  precision
@@ -136,11 +167,14 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
 nnca_status nnca_matvec(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                         int32_t dtype, int32_t precision, void *stream);
 
-/* Y = A~^T X.  The library covers the symmetric case of Sec. 5 only (P = Q,
- * K(x, y) = K(y, x)): there V_B = U_B and T_{B B_c} = C_{B_c B}^T, so the
- * transposed passes (P2M <-> L2P, M2M <-> L2L, S_{B,B'}^T = S_{B',B}, near
- * blocks likewise) are the forward ones and A~^T = A~; this entry point runs
- * the forward passes.  Arguments and errors as nnca_matvec.               */
+/* Y = A~^T X.  In the symmetric case of Sec. 5 (P = Q, K(x, y) = K(y, x))
+ * V_B = U_B and T_{B B_c} = C_{B_c B}^T, so the transposed passes (P2M <->
+ * L2P, M2M <-> L2L, S_{B,B'}^T = S_{B',B}, near blocks likewise) are the
+ * forward ones and A~^T = A~; this entry point runs the forward passes.  On
+ * a handle of nnca_build_general it runs the transposed passes (up with U_B^T
+ * and C_{B_c B}^T over P, across with the transposed blocks, down with V_B
+ * and T_{B B_c}^T over Q); X has np rows, Y nq.  Arguments and errors as
+ * nnca_matvec.                                                           */
 nnca_status nnca_matvec_adjoint(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                                 int32_t dtype, int32_t precision, void *stream);
 
@@ -295,6 +329,18 @@ nnca_status nnca_export_pivots(nnca_handle h, int32_t level, int64_t *ptr, int64
                                int64_t *cols);
 nnca_status nnca_export_operator(nnca_handle h, int32_t level, int64_t cell, double *C,
                                  int64_t cap, int64_t *m, int64_t *k);
+/* The same per half of a cell (half 0: incoming, half 1: outgoing; both are
+ * the one ACA when P = Q).  Half 0: rows = t^{B,i} (indices into P), cols =
+ * s^{B,i} (into Q), C = U_B or the stacked C_{B_c B}.  Half 1: rows = s^{B,o}
+ * (into Q), cols = t^{B,o} (into P), C = V_B (|s^B| x k) or the stacked
+ * T_{B B_c}^T.  For a handle of nnca_build, P = Q and the export of either
+ * half equals nnca_export_pivots / nnca_export_operator.  In the general
+ * case nnca_export_cells' first/count are P's ranges in P's tree order and
+ * nnca_export_order gives P's order.                                      */
+nnca_status nnca_export_half(nnca_handle h, int32_t level, int32_t half, int64_t *ptr, int64_t *rows,
+                             int64_t *cols);
+nnca_status nnca_export_half_operator(nnca_handle h, int32_t level, int32_t half, int64_t cell, double *C,
+                                      int64_t cap, int64_t *m, int64_t *k);
 
 /* Evaluate the method's FP64 kernel on the device for `count` pairs
  * (a[i], b[i]); a, b: host, dim x count SoA; out: host, count values.

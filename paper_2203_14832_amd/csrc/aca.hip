@@ -530,22 +530,53 @@ void debug_kernel_eval(int kind, double hparam, int dim, const double *a, const 
     dfree(dout);
 }
 
-// Pivots of one level (all of its cells), bottom-up order guaranteed by the caller.
-static void build_level(nnca_h2 *H, int l)
+// One half of the cells' pivots.  The symmetric case has one: the rows are
+// the cell's own points (or the children's pivots), the columns those of the
+// interaction list.  The general case P != Q has two, whose candidate sets
+// are crossed (Sec. 2.3.2): the incoming half's rows are targets (P) and its
+// columns the IL region's rows of the outgoing half (sources: a leaf's Q
+// points, else the IL children's s^{B'',o}); the outgoing half's rows are
+// sources and its columns the IL region's rows of the incoming half (targets:
+// a leaf's P points, else t^{B'',i}).  The outgoing ACA therefore runs on the
+// transposed block, its first pivot among the cell's own sources, and its
+// C = U~ L^{-1} is V_B (leaf) or the stacked T_{B B_c}^T.  Its entries are
+// evaluated as K(q, p); for the radial kernels here that is K(p, q) bit for
+// bit (the coordinate differences change sign exactly).
+struct Half {
+    std::vector<Level> *lv;
+    const double *pts;   // 3 x n, this half's tree order
+    int64_t n;
+};
+
+// step 1 of Sec. 2.3.2 for one half: m_B and the start of t~
+static void level_sizes(nnca_h2 *H, std::vector<Level> &lv, int l)
 {
     hipStream_t s = H->stream;
-    Level &L = H->lev[l];
+    Level &L = lv[l];
     const int64_t nc = L.ncell;
     const bool leaf = (l == H->kappa);
-    Level *Cl = leaf ? nullptr : &H->lev[l + 1];
-    const int32_t *tsrc = leaf ? nullptr : Cl->piv_id;
-
     L.m = dalloc<int32_t>(nc);
     L.tt_off = dalloc<int32_t>(nc);
     k_level_m<<<grid_for(nc, 256), 256, 0, s>>>(nc, leaf, L.first, L.count, L.child_first, L.child_count,
-                                               leaf ? nullptr : Cl->piv_ptr, L.m, L.tt_off);
+                                               leaf ? nullptr : lv[l + 1].piv_ptr, L.m, L.tt_off);
+    HIPCHECK(hipGetLastError());
+}
+
+// Step 2 of Sec. 2.3.2 for one half of a level (all of its cells): the rows
+// of `own`, the columns gathered from the interaction lists' rows of `far`
+// (the same half in the symmetric case).  level_sizes has run for both.
+static void build_level(nnca_h2 *H, int l, const Half &own, const Half &far)
+{
+    hipStream_t s = H->stream;
+    Level &L = (*own.lv)[l];
+    const Level &Lf = (*far.lv)[l];
+    const int64_t nc = L.ncell;
+    const bool leaf = (l == H->kappa);
+    const int32_t *tsrc = leaf ? nullptr : (*own.lv)[l + 1].piv_id;
+    const int32_t *ftsrc = leaf ? nullptr : (*far.lv)[l + 1].piv_id;
+
     int64_t *nn = dalloc<int64_t>(nc);
-    k_level_n<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.il_ptr, L.il, L.m, nn);
+    k_level_n<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.il_ptr, L.il, Lf.m, nn);
     HIPCHECK(hipGetLastError());
     std::vector<int32_t> hm(nc), htt(nc);
     std::vector<int64_t> hn(nc);
@@ -629,10 +660,10 @@ static void build_level(nnca_h2 *H, int l)
         double *V = dalloc<double>(vo);
         uint8_t *fl = dalloc<uint8_t>(fo);
         int32_t *rowmap = dalloc<int32_t>(ro);
-        k_gather_cand<<<(int)cn, 256, 0, s>>>(dcells, (int32_t)c0, L.il_ptr, L.il, L.m, L.tt_off, tsrc, H->pts64,
-                                              H->n, H->dim, sid, sc, so);
+        k_gather_cand<<<(int)cn, 256, 0, s>>>(dcells, (int32_t)c0, L.il_ptr, L.il, Lf.m, Lf.tt_off, ftsrc, far.pts,
+                                              far.n, H->dim, sid, sc, so);
         HIPCHECK(hipGetLastError());
-        k_aca<<<(int)cn, NT, 0, s>>>(dcells, (int32_t)c0, H->pts64, H->n, H->dim, tsrc, sid, sc, so, U, V, fl,
+        k_aca<<<(int)cn, NT, 0, s>>>(dcells, (int32_t)c0, own.pts, own.n, H->dim, tsrc, sid, sc, so, U, V, fl,
                                      H->kind, aca_param(H->kind, H->hparam), H->tol, L.k, ipos_cap, jid_cap);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(hk.data() + c0, L.k + c0, sizeof(int32_t) * cn, hipMemcpyDeviceToHost, s));
@@ -733,7 +764,21 @@ static void build_level(nnca_h2 *H, int l)
 
 void build_pivots(nnca_h2 *H)
 {
-    for (int l = H->kappa; l >= H->lmin; l--) build_level(H, l);
+    if (!H->general) {
+        const Half one{&H->lev, H->pts64, H->n};
+        for (int l = H->kappa; l >= H->lmin; l--) {
+            level_sizes(H, H->lev, l);
+            build_level(H, l, one, one);
+        }
+        return;
+    }
+    const Half in{&H->lev, H->pts64, H->n}, out{&H->lev_o, H->qpts64, H->nq};
+    for (int l = H->kappa; l >= H->lmin; l--) {
+        level_sizes(H, H->lev, l);
+        level_sizes(H, H->lev_o, l);
+        build_level(H, l, in, out);
+        build_level(H, l, out, in);
+    }
 }
 
 }  // namespace nnca

@@ -110,18 +110,23 @@ void nnca::destroy_handle(nnca_h2 *H)
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->ev_leafk) (void)hipEventDestroy(H->ev_leafk);
     if (H->ev_done) (void)hipEventDestroy(H->ev_done);
-    for (auto &L : H->lev) {
-        void *ps[] = {L.key, L.coord, L.first, L.count, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb,
-                      L.il_ptr, L.il, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
-                      L.rem_pos, L.crem_off, L.crem64, L.crem_t, L.piv_cell, L.rem_cell, L.pc64, L.pc32,
-                      L.ilpre, L.ilsum, L.w64, L.u64, L.hcell, L.own_ptr, L.own_il, L.own_pre, L.own_sum,
-                      L.own_slot, L.non_ptr, L.non_slot, L.col64};   // col32 aliases col64
-        for (void *p : ps) dfree(p);
-    }
+    for (auto *lv : {&H->lev, &H->lev_o})
+        for (auto &L : *lv) {
+            if (!L.shares_tree) {
+                void *ts[] = {L.key, L.coord, L.parent, L.child_first, L.child_count, L.nb_ptr, L.nb, L.il_ptr, L.il};
+                for (void *p : ts) dfree(p);
+            }
+            void *ps[] = {L.first, L.count, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
+                          L.rem_pos, L.crem_off, L.crem64, L.crem_t, L.piv_cell, L.rem_cell, L.pc64, L.pc32,
+                          L.ilpre, L.ilsum, L.w64, L.u64, L.hcell, L.own_ptr, L.own_il, L.own_pre, L.own_sum,
+                          L.own_slot, L.non_ptr, L.non_slot, L.col64};   // col32 aliases col64
+            for (void *p : ps) dfree(p);
+        }
     void *ps[] = {H->pts64,    H->order,    H->keys,     H->nbpre,    H->nbsum,     H->xs64,
                   H->far64,    H->xhi,      H->xlo,      H->m2l_part, H->pown_ptr,  H->pown_nb,
                   H->pown_pre, H->pown_sum, H->pown_slot, H->pnon_ptr, H->pnon_slot, H->pcell,
-                  H->pcol_hi,  H->pcol_lo,  H->prow,     H->near64,   H->rank};
+                  H->pcol_hi,  H->pcol_lo,  H->prow,     H->near64,   H->rank,      H->qpts64,
+                  H->qorder,   H->qrank,    H->nbpre_o,  H->nbsum_o};
     for (void *p : ps) dfree(p);
     delete H;
 }
@@ -162,18 +167,66 @@ static void d2h_convert(const S *dev, int64_t cnt, D *host)
 // Checks shared by the matvec entry points (nnca_matvec, its adjoint and the
 // allocation-free variant).
 void nnca::check_matvec_args(nnca_handle h, const void *X, const void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                             int32_t dtype, int32_t precision)
+                             int32_t dtype, int32_t precision, bool adjoint)
 {
     if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
     if (!X || !Y) fail(NNCA_ERR_INVALID_ARG, "X or Y is NULL");
     if (nrhs < 1) fail(NNCA_ERR_INVALID_ARG, "nrhs < 1");
-    if (ldx < h->n || ldy < h->n) fail(NNCA_ERR_INVALID_ARG, "leading dimension < n");
+    // rows of X and Y: n for P = Q; for P != Q the product maps Q to P and
+    // its transpose P to Q
+    const int64_t nx = h->general ? (adjoint ? h->n : h->nq) : h->n;
+    const int64_t ny = h->general ? (adjoint ? h->nq : h->n) : h->n;
+    if (ldx < nx || ldy < ny) fail(NNCA_ERR_INVALID_ARG, "leading dimension < rows");
     if (dtype != NNCA_F32 && dtype != NNCA_F64) fail(NNCA_ERR_INVALID_ARG, "bad dtype");
     if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
     const int64_t es = dtype == NNCA_F32 ? 4 : 8;
-    const char *xb = (const char *)X, *xe = xb + ((nrhs - 1) * ldx + h->n) * es;
-    const char *yb = (const char *)Y, *ye = yb + ((nrhs - 1) * ldy + h->n) * es;
+    const char *xb = (const char *)X, *xe = xb + ((nrhs - 1) * ldx + nx) * es;
+    const char *yb = (const char *)Y, *ye = yb + ((nrhs - 1) * ldy + ny) * es;
     if (xb < ye && yb < xe) fail(NNCA_ERR_INVALID_ARG, "X and Y overlap");
+}
+
+// entry points that cover the symmetric case only
+static void require_square(nnca_handle h, const char *what)
+{
+    if (h && h->general) fail(NNCA_ERR_NOT_SUPPORTED, std::string(what) + " covers P = Q only (a handle of nnca_build)");
+}
+
+// dense m x k operator C of one cell (the identity rows at the pivots)
+static void export_operator(const Level &L, int64_t cell, double *C, int64_t cap, int64_t *m, int64_t *k)
+{
+    {
+        if (cell < 0 || cell >= L.ncell) fail(NNCA_ERR_INVALID_ARG, "cell out of range");
+        int64_t mm = L.h_m[cell], kk = L.h_k[cell];
+        if (m) *m = mm;
+        if (k) *k = kk;
+        if (!C) return;
+        if (cap < mm * kk) fail(NNCA_ERR_INVALID_ARG, "C too small");
+        int32_t pp[2], rp[2];
+        int64_t co[2];
+        HIPCHECK(hipMemcpy(pp, L.piv_ptr + cell, sizeof(pp), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(rp, L.rem_ptr + cell, sizeof(rp), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(co, L.crem_off + cell, sizeof(co), hipMemcpyDeviceToHost));
+        std::vector<int32_t> ip(kk > 0 ? kk : 1), rpos(rp[1] - rp[0] > 0 ? rp[1] - rp[0] : 1);
+        std::vector<double> cr(co[1] - co[0] > 0 ? co[1] - co[0] : 1);
+        if (kk) HIPCHECK(hipMemcpy(ip.data(), L.ipos + pp[0], sizeof(int32_t) * kk, hipMemcpyDeviceToHost));
+        if (rp[1] > rp[0])
+            HIPCHECK(hipMemcpy(rpos.data(), L.rem_pos + rp[0], sizeof(int32_t) * (rp[1] - rp[0]), hipMemcpyDeviceToHost));
+        if (co[1] > co[0])
+            HIPCHECK(hipMemcpy(cr.data(), L.crem64 + co[0], sizeof(double) * (co[1] - co[0]), hipMemcpyDeviceToHost));
+        std::memset(C, 0, sizeof(double) * mm * kk);
+        for (int64_t q = 0; q < kk; q++) C[(int64_t)ip[q] * kk + q] = 1.0;
+        for (int64_t r = 0; r < rp[1] - rp[0]; r++)
+            for (int64_t q = 0; q < kk; q++) C[(int64_t)rpos[r] * kk + q] = cr[r * kk + q];
+    }
+}
+
+// the level of one half: 0 incoming, 1 outgoing (the same level when P = Q)
+static const Level &half_level(nnca_handle h, int32_t level, int32_t half)
+{
+    const Level &L = level_of(h, level);
+    if (half != 0 && half != 1) fail(NNCA_ERR_INVALID_ARG, "half must be 0 or 1");
+    if (!L.has_piv) fail(NNCA_ERR_INVALID_ARG, "level carries no pivots");
+    return half == 1 && h->general ? h->lev_o[level] : L;
 }
 
 // Calls on one handle share its workspace: each waits for the end of the
@@ -183,6 +236,54 @@ void nnca::order_call_end(nnca_handle h, hipStream_t s) { HIPCHECK(hipEventRecor
 
 extern "C" {
 
+// A handle with its options set, not yet built: checks every argument that
+// is not a point array.
+static nnca_h2 *new_handle(int64_t n, int32_t dim, int32_t kernel_kind, double length_scale, double tol,
+                           int32_t leaf_size, const nnca_build_options *opts, void *stream)
+{
+    if (dim != 2 && dim != 3) fail(NNCA_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (leaf_size < 1) fail(NNCA_ERR_INVALID_ARG, "leaf_size < 1");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) fail(NNCA_ERR_INVALID_ARG, "tol must be finite and >= 0");
+    check_kernel(kernel_kind, dim, length_scale);
+    nnca_build_options o{};
+    o.struct_size = sizeof(o);
+    o.exhausted_policy = 1;
+    if (opts) {
+        // callers built against the first version of the struct end at
+        // `reserved`; the fields after it keep their defaults
+        const size_t v1 = offsetof(nnca_build_options, max_rhs);
+        if (opts->struct_size != v1 && opts->struct_size < sizeof(nnca_build_options))
+            fail(NNCA_ERR_INVALID_ARG, "bad struct_size");
+        std::memcpy(&o, opts, opts->struct_size < sizeof(o) ? opts->struct_size : sizeof(o));
+        o.struct_size = sizeof(o);
+    }
+    if ((o.alloc == nullptr) != (o.free == nullptr))
+        fail(NNCA_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+    if (o.max_rhs < 0) fail(NNCA_ERR_INVALID_ARG, "max_rhs < 0");
+    if ((o.eta2_num == 0) != (o.eta2_den == 0) || o.eta2_num < 0 || o.eta2_den < 0)
+        fail(NNCA_ERR_INVALID_ARG, "eta2 must be a positive fraction or 0/0");
+    if (o.exhausted_policy != 0 && o.exhausted_policy != 1) fail(NNCA_ERR_INVALID_ARG, "bad exhausted_policy");
+    if (o.rank_reserve < 0) fail(NNCA_ERR_INVALID_ARG, "rank_reserve < 0");
+    nnca_h2 *H = new nnca_h2();
+    H->n = n;
+    H->dim = dim;
+    H->kind = kernel_kind;
+    H->hparam = uses_length_scale(kernel_kind) ? length_scale : 1.0;
+    H->tol = tol;
+    H->leaf = leaf_size;
+    H->eta_num = o.eta2_num ? o.eta2_num : dim;
+    H->eta_den = o.eta2_num ? o.eta2_den : 1;
+    H->policy = o.exhausted_policy;
+    H->ws_budget = o.workspace_bytes;
+    H->rank_reserve = o.rank_reserve > 0 ? o.rank_reserve : 256;
+    H->stream = (hipStream_t)stream;
+    H->alloc.alloc = o.alloc;
+    H->alloc.free = o.free;
+    H->alloc.ctx = o.alloc_ctx;
+    H->max_rhs = o.max_rhs == 0 ? 16 : (o.max_rhs > 64 ? 64 : o.max_rhs);
+    return H;
+}
+
 nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld, int32_t points_on_device,
                        int32_t kernel_kind, double length_scale, double tol, int32_t leaf_size,
                        const nnca_build_options *opts, void *stream, nnca_handle *out)
@@ -191,49 +292,9 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
         if (!out) fail(NNCA_ERR_INVALID_ARG, "out is NULL");
         if (!points) fail(NNCA_ERR_INVALID_ARG, "points is NULL");
         if (n < 1 || n > (int64_t)INT32_MAX / 2) fail(NNCA_ERR_INVALID_ARG, "n out of range");
-        if (dim != 2 && dim != 3) fail(NNCA_ERR_INVALID_ARG, "dim must be 2 or 3");
         if (ld < n) fail(NNCA_ERR_INVALID_ARG, "ld < n");
-        if (leaf_size < 1) fail(NNCA_ERR_INVALID_ARG, "leaf_size < 1");
-        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(NNCA_ERR_INVALID_ARG, "tol must be finite and >= 0");
-        check_kernel(kernel_kind, dim, length_scale);
-        nnca_build_options o{};
-        o.struct_size = sizeof(o);
-        o.exhausted_policy = 1;
-        if (opts) {
-            // callers built against the first version of the struct end at
-            // `reserved`; the fields after it keep their defaults
-            const size_t v1 = offsetof(nnca_build_options, max_rhs);
-            if (opts->struct_size != v1 && opts->struct_size < sizeof(nnca_build_options))
-                fail(NNCA_ERR_INVALID_ARG, "bad struct_size");
-            std::memcpy(&o, opts, opts->struct_size < sizeof(o) ? opts->struct_size : sizeof(o));
-            o.struct_size = sizeof(o);
-        }
-        if ((o.alloc == nullptr) != (o.free == nullptr))
-            fail(NNCA_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
-        if (o.max_rhs < 0) fail(NNCA_ERR_INVALID_ARG, "max_rhs < 0");
-        if ((o.eta2_num == 0) != (o.eta2_den == 0) || o.eta2_num < 0 || o.eta2_den < 0)
-            fail(NNCA_ERR_INVALID_ARG, "eta2 must be a positive fraction or 0/0");
-        if (o.exhausted_policy != 0 && o.exhausted_policy != 1) fail(NNCA_ERR_INVALID_ARG, "bad exhausted_policy");
-
         auto t0 = std::chrono::steady_clock::now();
-        nnca_h2 *H = new nnca_h2();
-        H->n = n;
-        H->dim = dim;
-        H->kind = kernel_kind;
-        H->hparam = uses_length_scale(kernel_kind) ? length_scale : 1.0;
-        H->tol = tol;
-        H->leaf = leaf_size;
-        H->eta_num = o.eta2_num ? o.eta2_num : dim;
-        H->eta_den = o.eta2_num ? o.eta2_den : 1;
-        H->policy = o.exhausted_policy;
-        H->ws_budget = o.workspace_bytes;
-        if (o.rank_reserve < 0) fail(NNCA_ERR_INVALID_ARG, "rank_reserve < 0");
-        H->rank_reserve = o.rank_reserve > 0 ? o.rank_reserve : 256;
-        H->stream = (hipStream_t)stream;
-        H->alloc.alloc = o.alloc;
-        H->alloc.free = o.free;
-        H->alloc.ctx = o.alloc_ctx;
-        H->max_rhs = o.max_rhs == 0 ? 16 : (o.max_rhs > 64 ? 64 : o.max_rhs);
+        nnca_h2 *H = new_handle(n, dim, kernel_kind, length_scale, tol, leaf_size, opts, stream);
         AllocScope as(H->alloc);
         try {
             double *pin = nullptr;
@@ -270,15 +331,62 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
     });
 }
 
-static nnca_status matvec_common(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                                 int32_t dtype, int32_t precision, void *stream)
+nnca_status nnca_build_general(const double *targets, int64_t np, int64_t ldp, const double *sources, int64_t nq,
+                               int64_t ldq, int32_t dim, int32_t points_on_device, int32_t kernel_kind,
+                               double length_scale, double tol, int32_t leaf_size, const nnca_build_options *opts,
+                               void *stream, nnca_handle *out)
 {
     return guarded([&] {
-        check_matvec_args(h, X, Y, nrhs, ldx, ldy, dtype, precision);
+        if (!out) fail(NNCA_ERR_INVALID_ARG, "out is NULL");
+        if (!targets || !sources) fail(NNCA_ERR_INVALID_ARG, "targets or sources is NULL");
+        if (np < 1 || nq < 1 || np + nq > (int64_t)INT32_MAX / 2) fail(NNCA_ERR_INVALID_ARG, "np or nq out of range");
+        if (ldp < np || ldq < nq) fail(NNCA_ERR_INVALID_ARG, "leading dimension < point count");
+        auto t0 = std::chrono::steady_clock::now();
+        const int64_t n = np + nq;
+        nnca_h2 *H = new_handle(n, dim, kernel_kind, length_scale, tol, leaf_size, opts, stream);
+        AllocScope as(H->alloc);
+        try {
+            // the union Z = [P, Q] as one dim x (np + nq) array on the device
+            double *Z = dalloc<double>((size_t)dim * n);
+            try {
+                const hipMemcpyKind kd = points_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+                HIPCHECK(hipMemcpy2DAsync(Z, sizeof(double) * n, targets, sizeof(double) * ldp, sizeof(double) * np,
+                                          dim, kd, H->stream));
+                HIPCHECK(hipMemcpy2DAsync(Z + np, sizeof(double) * n, sources, sizeof(double) * ldq,
+                                          sizeof(double) * nq, dim, kd, H->stream));
+                build_tree(H, Z, n, np);
+                split_general(H, Z, n, np);
+            } catch (...) {
+                (void)hipStreamSynchronize(H->stream);
+                dfree(Z);
+                throw;
+            }
+            HIPCHECK(hipStreamSynchronize(H->stream));
+            dfree(Z);
+            build_pivots(H);
+            prepare_general(H);
+            HIPCHECK(hipEventCreateWithFlags(&H->ev_done, hipEventDisableTiming));
+            HIPCHECK(hipStreamSynchronize(H->stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(H->stream);
+            destroy_handle(H);
+            throw;
+        }
+        H->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = H;
+    });
+}
+
+static nnca_status matvec_common(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                                 int32_t dtype, int32_t precision, bool adjoint, void *stream)
+{
+    return guarded([&] {
+        check_matvec_args(h, X, Y, nrhs, ldx, ldy, dtype, precision, adjoint);
         AllocScope as(h->alloc);
         const hipStream_t s = (hipStream_t)stream;
         order_call_begin(h, s);
-        run_matvec(h, X, Y, nrhs, ldx, ldy, dtype, precision, s);
+        if (h->general) run_matvec_general(h, X, Y, nrhs, ldx, ldy, dtype, precision, adjoint, s);
+        else run_matvec(h, X, Y, nrhs, ldx, ldy, dtype, precision, s);
         order_call_end(h, s);
     });
 }
@@ -286,18 +394,19 @@ static nnca_status matvec_common(nnca_handle h, const void *X, void *Y, int64_t 
 nnca_status nnca_matvec(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                         int32_t dtype, int32_t precision, void *stream)
 {
-    return matvec_common(h, X, Y, nrhs, ldx, ldy, dtype, precision, stream);
+    return matvec_common(h, X, Y, nrhs, ldx, ldy, dtype, precision, false, stream);
 }
 
 // In the symmetric case of Sec. 5 (P = Q, K(x,y) = K(y,x), V_B = U_B,
 // T_{B B_c} = C_{B_c B}^T) the transposed passes coincide with the forward
 // ones: P2M^T = L2P, M2M^T = L2L, and every block S_{B,B'}^T = S_{B',B} with
 // B' in IL(B) <=> B in IL(B'), near blocks likewise.  The adjoint therefore
-// runs the same kernels.
+// runs the same kernels.  In the general case it runs them with the two
+// halves exchanged.
 nnca_status nnca_matvec_adjoint(nnca_handle h, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
                                 int32_t dtype, int32_t precision, void *stream)
 {
-    return matvec_common(h, X, Y, nrhs, ldx, ldy, dtype, precision, stream);
+    return matvec_common(h, X, Y, nrhs, ldx, ldy, dtype, precision, true, stream);
 }
 
 nnca_status nnca_set_apply_flags(nnca_handle h, int32_t flags)
@@ -315,6 +424,7 @@ nnca_status nnca_matvec_backward(nnca_handle h, const double *X, const double *G
 {
     return guarded([&] {
         if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        require_square(h, "nnca_matvec_backward");
         if (!G) fail(NNCA_ERR_INVALID_ARG, "G is NULL");
         if (!DX && !dLdh) fail(NNCA_ERR_INVALID_ARG, "neither DX nor dLdh requested");
         if (dLdh && !X) fail(NNCA_ERR_INVALID_ARG, "X is NULL");
@@ -353,8 +463,10 @@ nnca_status nnca_batch_create(const nnca_handle *handles, int32_t count, int32_t
         if (!handles || !out) fail(NNCA_ERR_INVALID_ARG, "NULL argument");
         if (count < 1) fail(NNCA_ERR_INVALID_ARG, "count < 1");
         if (flags & ~(NNCA_BATCH_GRAPH | NNCA_BATCH_AUTOTUNE)) fail(NNCA_ERR_INVALID_ARG, "unknown flags");
-        for (int32_t b = 0; b < count; b++)
+        for (int32_t b = 0; b < count; b++) {
             if (!handles[b]) fail(NNCA_ERR_INVALID_ARG, "a handle is NULL");
+            require_square(handles[b], "nnca_batch_create");
+        }
         AllocScope as(handles[0]->alloc);
         *out = create_batch(handles, count, flags);
     });
@@ -445,6 +557,43 @@ nnca_status nnca_query(nnca_handle h, nnca_info *info)
     });
 }
 
+nnca_status nnca_query_shape(nnca_handle h, int64_t *rows, int64_t *cols, int32_t *general)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        if (rows) *rows = h->n;
+        if (cols) *cols = h->general ? h->nq : h->n;
+        if (general) *general = h->general ? 1 : 0;
+    });
+}
+
+nnca_status nnca_export_half(nnca_handle h, int32_t level, int32_t half, int64_t *ptr, int64_t *rows,
+                             int64_t *cols)
+{
+    return guarded([&] {
+        const Level &L = half_level(h, level, half);
+        // rows index the half's own set, columns the other set
+        const bool q_rows = h->general && half == 1, q_cols = h->general && half == 0;
+        auto order_of = [&](bool q) {
+            std::vector<int32_t> o(q ? h->nq : h->n);
+            HIPCHECK(hipMemcpy(o.data(), q ? h->qorder : h->order, sizeof(int32_t) * o.size(), hipMemcpyDeviceToHost));
+            return o;
+        };
+        if (ptr) d2h_convert(L.piv_ptr, L.ncell + 1, ptr);
+        std::vector<int32_t> tmp(L.npiv > 0 ? L.npiv : 1);
+        if (rows) {
+            const std::vector<int32_t> o = order_of(q_rows);
+            if (L.npiv) HIPCHECK(hipMemcpy(tmp.data(), L.piv_id, sizeof(int32_t) * L.npiv, hipMemcpyDeviceToHost));
+            for (int64_t q = 0; q < L.npiv; q++) rows[q] = o[tmp[q]];
+        }
+        if (cols) {
+            const std::vector<int32_t> o = order_of(q_cols);
+            if (L.npiv) HIPCHECK(hipMemcpy(tmp.data(), L.jid, sizeof(int32_t) * L.npiv, hipMemcpyDeviceToHost));
+            for (int64_t q = 0; q < L.npiv; q++) cols[q] = tmp[q] < 0 ? -1 : o[tmp[q]];
+        }
+    });
+}
+
 nnca_status nnca_export_order(nnca_handle h, int64_t *order)
 {
     return guarded([&] {
@@ -500,29 +649,14 @@ nnca_status nnca_export_operator(nnca_handle h, int32_t level, int64_t cell, dou
     return guarded([&] {
         const Level &L = level_of(h, level);
         if (!L.has_piv) fail(NNCA_ERR_INVALID_ARG, "level carries no pivots");
-        if (cell < 0 || cell >= L.ncell) fail(NNCA_ERR_INVALID_ARG, "cell out of range");
-        int64_t mm = L.h_m[cell], kk = L.h_k[cell];
-        if (m) *m = mm;
-        if (k) *k = kk;
-        if (!C) return;
-        if (cap < mm * kk) fail(NNCA_ERR_INVALID_ARG, "C too small");
-        int32_t pp[2], rp[2];
-        int64_t co[2];
-        HIPCHECK(hipMemcpy(pp, L.piv_ptr + cell, sizeof(pp), hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(rp, L.rem_ptr + cell, sizeof(rp), hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(co, L.crem_off + cell, sizeof(co), hipMemcpyDeviceToHost));
-        std::vector<int32_t> ip(kk > 0 ? kk : 1), rpos(rp[1] - rp[0] > 0 ? rp[1] - rp[0] : 1);
-        std::vector<double> cr(co[1] - co[0] > 0 ? co[1] - co[0] : 1);
-        if (kk) HIPCHECK(hipMemcpy(ip.data(), L.ipos + pp[0], sizeof(int32_t) * kk, hipMemcpyDeviceToHost));
-        if (rp[1] > rp[0])
-            HIPCHECK(hipMemcpy(rpos.data(), L.rem_pos + rp[0], sizeof(int32_t) * (rp[1] - rp[0]), hipMemcpyDeviceToHost));
-        if (co[1] > co[0])
-            HIPCHECK(hipMemcpy(cr.data(), L.crem64 + co[0], sizeof(double) * (co[1] - co[0]), hipMemcpyDeviceToHost));
-        std::memset(C, 0, sizeof(double) * mm * kk);
-        for (int64_t q = 0; q < kk; q++) C[(int64_t)ip[q] * kk + q] = 1.0;
-        for (int64_t r = 0; r < rp[1] - rp[0]; r++)
-            for (int64_t q = 0; q < kk; q++) C[(int64_t)rpos[r] * kk + q] = cr[r * kk + q];
+        export_operator(L, cell, C, cap, m, k);
     });
+}
+
+nnca_status nnca_export_half_operator(nnca_handle h, int32_t level, int32_t half, int64_t cell, double *C,
+                                      int64_t cap, int64_t *m, int64_t *k)
+{
+    return guarded([&] { export_operator(half_level(h, level, half), cell, C, cap, m, k); });
 }
 
 nnca_status nnca_debug_kernel_eval(int32_t kernel_kind, double length_scale, int32_t dim, const double *a,
@@ -542,6 +676,7 @@ nnca_status nnca_gmres(nnca_handle h, double alpha, double beta, const double *F
 {
     return guarded([&] {
         if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        require_square(h, "nnca_gmres");
         if (!F || !X) fail(NNCA_ERR_INVALID_ARG, "F or X is NULL");
         if (F == X) fail(NNCA_ERR_INVALID_ARG, "F and X are the same buffer");
         {

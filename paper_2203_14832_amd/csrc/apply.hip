@@ -232,7 +232,10 @@ template <> struct M2LTypes<M_F64R> { using C = double; using V = double4; };
 
 constexpr int ET = 256;   // interaction-list entries staged in LDS at a time
 
-// transverse pass at one level: u^{B,i} = sum_{B' in IL(B)} K(t^{B,i}, t^{B',i}) w^{B',o}.
+// transverse pass at one level: u^{B,i} = sum_{B' in IL(B)} K(t^{B,i}, s^{B',o}) w^{B',o}.
+// Targets: the pivots of cell B (pc, piv_ptr); sources: the pivots of the IL
+// cells (pcs, piv_ptr_s), which are the same arrays in the symmetric case
+// (s^{B',o} = t^{B',i}) and the outgoing half's in the general case.
 // Launched with nc * P workgroups: part p of a cell takes the p-th of P equal
 // slices of its source list; with P > 1 the partial vectors go to `part_out`
 // (P x npiv) and are added in a fixed order by k_sum_parts.
@@ -241,6 +244,8 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
                                             const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                             const int32_t *ilsum,
                                             const typename M2LTypes<MODE>::C *pc, int64_t npiv,
+                                            const typename M2LTypes<MODE>::C *pcs, int64_t npivs,
+                                            const int32_t *piv_ptr_s,
                                             const int32_t *coord, const float *hc, float h0, int d,
                                             const double *w, double *u, double *part_out, double prm64)
 {
@@ -298,7 +303,7 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
             for (int32_t j = t; j < wn; j += NT) {
                 const int32_t e = w0 + j, b = il[e], pre = ilpre[e];
                 est[j] = pre;
-                ebase[j] = piv_ptr[b] - pre;
+                ebase[j] = piv_ptr_s[b] - pre;
                 if (MODE == M_F32) {
                     esh[0][j] = (float)(coord[b] - cc[0]) * h;
                     esh[1][j] = (float)(coord[nc + b] - cc[1]) * h;
@@ -330,9 +335,9 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
                 if (s < send) {
                     while (est[ej + 1] <= s) ej++;
                     const int32_t idx = ebase[ej] + s;
-                    v[q].x = pc[idx];
-                    v[q].y = pc[npiv + idx];
-                    v[q].z = d == 3 ? pc[2 * npiv + idx] : T(0);
+                    v[q].x = pcs[idx];
+                    v[q].y = pcs[npivs + idx];
+                    v[q].z = d == 3 ? pcs[2 * npivs + idx] : T(0);
                     v[q].w = (T)w[idx];
                     if (MODE == M_F32) {
                         v[q].x += esh[0][ej];
@@ -411,10 +416,14 @@ __global__ void k_sum_parts(int64_t npiv, int P, const double *part, double *u)
 // on the split weights x_hi, x_lo (close pairs would otherwise lose their
 // relative accuracy to the rounding of the coordinates themselves).  The far
 // field and the partial results are added in FP64.
+// Targets: the cell's points (first, count, pts); sources: the neighbours'
+// points at sfirst in spts (the same arrays in the symmetric case; Q's in the
+// general case).
 template <typename T, int KIND>
 __global__ __launch_bounds__(NT) void k_p2p(int64_t c0, const int32_t *first, const int32_t *count,
                                             const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
-                                            const int32_t *nbsum, const double *pts, int64_t n, int d,
+                                            const int32_t *nbsum, const double *pts, int64_t n,
+                                            const int32_t *sfirst, const double *spts, int64_t sn, int d,
                                             const T *xw, const T *xw2, const double *far,
                                             const int32_t *order, double *y, T prm)
 {
@@ -456,7 +465,7 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t c0, const int32_t *first, co
             for (int32_t j = t; j < wn; j += NT) {
                 const int32_t e = w0 + j, pre = nbpre[e];
                 est[j] = pre;
-                ebase[j] = first[nb[e]] - pre;
+                ebase[j] = sfirst[nb[e]] - pre;
             }
             if (t == 0) est[wn] = w0 + wn < e1 ? nbpre[w0 + wn] : S;
             __syncthreads();
@@ -472,9 +481,9 @@ __global__ __launch_bounds__(NT) void k_p2p(int64_t c0, const int32_t *first, co
                     if (est[mid] <= s) lo = mid; else hi = mid - 1;
                 }
                 int32_t idx = ebase[lo] + s;
-                v.x = pts[idx];
-                v.y = pts[n + idx];
-                v.z = d == 3 ? pts[2 * n + idx] : 0.0;
+                v.x = spts[idx];
+                v.y = spts[sn + idx];
+                v.z = d == 3 ? spts[2 * sn + idx] : 0.0;
                 v.w = xw[idx];
                 if (mixed) v.w2 = xw2[idx];
             }
@@ -1010,9 +1019,12 @@ static int m2l_parts(const nnca::Level &L)
     return P < 1 ? 1 : (int)P;
 }
 
+// transverse pass of level L with the sources of level S (S = L in the
+// symmetric case; the other half in the general case): targets at pc,
+// sources at pcs, local vectors into L.u64 from the multipole vectors S.w64
 template <int MODE, typename C>
-static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C *pc, double prm, hipStream_t s,
-                            hipEvent_t after = nullptr)
+static void launch_m2l_pair(int kind, nnca_h2 *H, const nnca::Level &L, const nnca::Level &S, const C *pc,
+                            const C *pcs, double prm, hipStream_t s, hipEvent_t after = nullptr)
 {
     const int64_t nc = L.ncell;
     const int P = m2l_parts(L);
@@ -1022,7 +1034,7 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
         part = H->m2l_part;
     }
     const int g = (int)(nc * P);
-#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, L.w64, L.u64, part, prm
+#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, pcs, S.npiv, S.piv_ptr, L.coord, L.hcell, (float)L.h, H->dim, S.w64, L.u64, part, prm
 #define M2L_CASE(K) k_m2l<K, MODE, M2L_TILE><<<g, NT, 0, s>>>(M2L_ARGS);
     if (kind == NNCA_K_INV_R) { M2L_CASE(NNCA_K_INV_R) }
     else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }
@@ -1038,6 +1050,13 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
         k_sum_parts<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, P, part, L.u64);
         HIPCHECK(hipGetLastError());
     }
+}
+
+template <int MODE, typename C>
+static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C *pc, double prm, hipStream_t s,
+                            hipEvent_t after = nullptr)
+{
+    launch_m2l_pair<MODE, C>(kind, H, L, L, pc, pc, prm, s, after);
 }
 
 // event pair around one launch when the handle is profiling
@@ -1360,7 +1379,7 @@ void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *f
     if (c1 < 0) c1 = L.ncell;
     const int64_t nc = c1 - c0;
     if (nc <= 0) return;
-#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(c0, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, H->dim, xw, xw2, far, order, y, prm)
+#define P2P_CASE(K) k_p2p<T, K><<<(int)nc, NT, 0, s>>>(c0, L.first, L.count, L.nb_ptr, L.nb, H->nbpre, H->nbsum, H->pts64, H->n, L.first, H->pts64, H->n, H->dim, xw, xw2, far, order, y, prm)
     if (kind == NNCA_K_INV_R) P2P_CASE(NNCA_K_INV_R);
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
     else if (kind == NNCA_K_LOG_REG) P2P_CASE(NNCA_K_LOG_REG);
@@ -1857,6 +1876,228 @@ void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, dou
         else if (kind == NNCA_K_INV_REG) k_direct<NNCA_K_INV_REG><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         else k_direct<NNCA_K_GAUSS><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         HIPCHECK(hipGetLastError());
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General case P != Q (Sec. 2.3, Sec. 4).  The product y = A~ x runs
+//   upward     on the outgoing half (sources): w^{B,o} = V_B^T x^B at a leaf,
+//              the stacked T_{B B_c} applied to the children's w above;
+//   transverse targets t^{B,i} of the incoming half, sources s^{B',o} of
+//              the outgoing half: u^{B,i} = sum_{IL} K(t^{B,i}, s^{B',o}) w^{B',o};
+//   downward   on the incoming half: U_B / C_{B_c B} as in the symmetric case;
+//   near field K(t^B, s^{B'}) x^{B'} over N(B), targets P, sources Q.
+// The transposed product A~^T g runs the same kernels with the halves and
+// the point sets exchanged: up with U_B^T and C_{B_c B}^T over P, across with
+// K(t^{B',i}, s^{B,o})^T (the kernels are radial, so K(q, p) = K(p, q)), down
+// with V_B and T_{B B_c}^T over Q, near field over the neighbours' targets.
+// The transverse pass has no symmetric form here (its blocks are not
+// shared between the two directions); the near field neither.
+
+namespace {
+
+// per-level apply data of one half: pivot coordinates in that half's point
+// array, owners, transposed blocks, multipole and local vectors, and for
+// every interaction list the prefix of the other half's ranks (its sources)
+void prepare_half(nnca_h2 *H, std::vector<Level> &lv, const std::vector<Level> &other, const double *pts,
+                  int64_t n, int64_t &m2l, int64_t &trans)
+{
+    hipStream_t s = H->stream;
+    const int d = H->dim;
+    m2l = 0;
+    trans = 0;
+    for (int l = H->lmin; l <= H->kappa; l++) {
+        Level &L = lv[l];
+        const Level &O = other[l];
+        const int64_t nc = L.ncell;
+        L.pc64 = dalloc<double>(3 * L.npiv);
+        L.pc32 = dalloc<float>(3 * L.npiv);
+        k_pivot_coords<<<(int)nc, 64, 0, s>>>(nc, L.piv_ptr, L.piv_id, pts, n, d, L.coord, H->lo[0], H->lo[1],
+                                              H->lo[2], L.h, L.npiv, L.pc64, L.pc32);
+        int32_t nrem = 0;
+        HIPCHECK(hipMemcpy(&nrem, L.rem_ptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost));
+        L.nrem = nrem;
+        L.piv_cell = dalloc<int32_t>(L.npiv);
+        L.rem_cell = dalloc<int32_t>(L.nrem);
+        k_fill_owner<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.piv_ptr, L.piv_cell);
+        k_fill_owner<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.rem_ptr, L.rem_cell);
+        L.crem_t = dalloc<double>(L.ncrem);
+        if (L.ncrem) k_transpose_blocks<<<(int)nc, 256, 0, s>>>(nc, L.piv_ptr, L.rem_ptr, L.crem_off, L.crem64, L.crem_t);
+        L.ilpre = dalloc<int32_t>(L.nil);
+        L.ilsum = dalloc<int32_t>(nc);
+        k_list_prefix<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.il_ptr, L.il, O.k, L.ilpre, L.ilsum);
+        L.w64 = dalloc<double>(L.npiv);
+        L.u64 = dalloc<double>(L.npiv);
+        HIPCHECK(hipGetLastError());
+        std::vector<int32_t> ils(nc);
+        HIPCHECK(hipMemcpyAsync(ils.data(), L.ilsum, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        L.max_ilsum = 0;
+        L.m2l_inter = 0;
+        for (int64_t c = 0; c < nc; c++) {
+            L.m2l_inter += (int64_t)L.h_k[c] * ils[c];
+            L.max_ilsum = std::max(L.max_ilsum, ils[c]);
+        }
+        m2l += L.m2l_inter;
+        trans += L.ncrem;
+    }
+}
+
+// one column of the general product (adj: the transposed product)
+template <typename T>
+void one_column_general(nnca_h2 *H, bool adj, const T *xhi, const T *xlo, void *y, bool y32, hipStream_t s)
+{
+    const bool f32 = sizeof(T) == 4;
+    const int kind = H->kind, kap = H->kappa, lmin = H->lmin;
+    std::vector<Level> &tl = adj ? H->lev_o : H->lev;   // targets' half: local vectors, downward pass
+    std::vector<Level> &sl = adj ? H->lev : H->lev_o;   // sources' half: multipole vectors, upward pass
+    const double *tpts = adj ? H->qpts64 : H->pts64, *spts = adj ? H->pts64 : H->qpts64;
+    const int64_t nt = adj ? H->nq : H->n, ns = adj ? H->n : H->nq;
+    const int32_t *trank = adj ? H->qrank : H->rank;
+    const int32_t *nbpre = adj ? H->nbpre_o : H->nbpre, *nbsum = adj ? H->nbsum_o : H->nbsum;
+    const T prm = f32 ? (T)kernel_prm32(kind, H->hparam) : (T)kernel_prm64(kind, H->hparam);
+    const double prm64 = kernel_prm64(kind, H->hparam);
+    const double *xs64 = H->xs64;
+    double *far = nullptr;
+    if (kap >= lmin) {
+        for (int l = kap; l >= lmin; l--) {
+            Level &L = sl[l];
+            const double *src = (l == kap) ? xs64 : sl[l + 1].w64;
+            Span sp(H, s, PASS_UP, l);
+            if (L.nrem == 0 || l == kap)
+                k_up<<<grid_for(L.npiv, 256), 256, 0, s>>>(L.npiv, L.piv_cell, L.piv_ptr, L.tt_off, L.ipos,
+                                                           L.rem_ptr, L.rem_pos, L.crem_off, L.crem64, src, L.w64);
+            else {
+                const int32_t colw = L.ncell < 2048 ? 32 : INT32_MAX;
+                const unsigned gy = L.ncell < 2048 ? (unsigned)((L.max_k + 31) / 32) : 1u;
+                k_up_cell<<<dim3((unsigned)L.ncell, gy > 0 ? gy : 1u), 256, 0, s>>>(
+                    L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos, L.crem_off, L.crem64, src, L.w64, colw);
+            }
+            HIPCHECK(hipGetLastError());
+        }
+        const int lf64 = kap - H->fp32_levels;
+        for (int l = lmin; l <= kap; l++) {
+            Level &L = tl[l];
+            const Level &S = sl[l];
+            Span sp(H, s, PASS_M2L, l);
+            if (!f32) launch_m2l_pair<M_F64>(kind, H, L, S, L.pc64, S.pc64, prm64, s);
+            else if (l <= lf64) launch_m2l_pair<M_F64R>(kind, H, L, S, L.pc64, S.pc64, prm64, s);
+            else launch_m2l_pair<M_F32>(kind, H, L, S, L.pc32, S.pc32, (double)prm, s);
+        }
+        far = H->far64;
+        for (int l = lmin; l <= kap; l++) {
+            Level &L = tl[l];
+            const bool leaf = l == kap;
+            double *out = leaf ? far : tl[l + 1].u64;
+            Span sp(H, s, PASS_DOWN, l);
+            k_down<<<grid_for(L.npiv + L.nrem, 256), 256, 0, s>>>(
+                L.npiv, L.nrem, L.piv_cell, L.rem_cell, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr, L.rem_pos,
+                L.crem_off, L.crem_t, L.u64, out, leaf ? 0 : 1, nullptr);
+            HIPCHECK(hipGetLastError());
+        }
+    }
+    // near field plus the far field, in the targets' tree order, then y
+    Span sp(H, s, PASS_P2P, kap);
+    const Level &F = tl[kap], &G = sl[kap];
+    const T *xw = f32 ? xhi : (const T *)xs64;
+    const T *xw2 = f32 ? xlo : nullptr;
+#define P2PG_CASE(K) k_p2p<T, K><<<(int)F.ncell, NT, 0, s>>>(0, F.first, F.count, F.nb_ptr, F.nb, nbpre, nbsum, tpts, nt, G.first, spts, ns, H->dim, xw, xw2, far, nullptr, H->near64, prm)
+    if (kind == NNCA_K_INV_R) P2PG_CASE(NNCA_K_INV_R);
+    else if (kind == NNCA_K_LOG_R) P2PG_CASE(NNCA_K_LOG_R);
+    else if (kind == NNCA_K_LOG_REG) P2PG_CASE(NNCA_K_LOG_REG);
+    else if (kind == NNCA_K_INV_REG) P2PG_CASE(NNCA_K_INV_REG);
+    else P2PG_CASE(NNCA_K_GAUSS);
+#undef P2PG_CASE
+    HIPCHECK(hipGetLastError());
+    if (y32) k_near_far_out<<<grid_for(nt, 256), 256, 0, s>>>(nt, trank, H->near64, nullptr, (float *)y);
+    else k_near_far_out<<<grid_for(nt, 256), 256, 0, s>>>(nt, trank, H->near64, nullptr, (double *)y);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace
+
+void prepare_general(nnca_h2 *H)
+{
+    hipStream_t s = H->stream;
+    int64_t m2l = 0, trans = 0, m2l_o = 0, trans_o = 0;
+    prepare_half(H, H->lev, H->lev_o, H->pts64, H->n, m2l, trans);
+    prepare_half(H, H->lev_o, H->lev, H->qpts64, H->nq, m2l_o, trans_o);
+    // near field: targets P with the neighbours' Q points, and the other way
+    const Level &F = H->lev[H->kappa], &G = H->lev_o[H->kappa];
+    const int64_t nc = F.ncell;
+    H->nbpre = dalloc<int32_t>(F.nnb);
+    H->nbsum = dalloc<int32_t>(nc);
+    H->nbpre_o = dalloc<int32_t>(F.nnb);
+    H->nbsum_o = dalloc<int32_t>(nc);
+    k_list_prefix<<<grid_for(nc, 256), 256, 0, s>>>(nc, F.nb_ptr, F.nb, G.count, H->nbpre, H->nbsum);
+    k_list_prefix<<<grid_for(nc, 256), 256, 0, s>>>(nc, F.nb_ptr, F.nb, F.count, H->nbpre_o, H->nbsum_o);
+    HIPCHECK(hipGetLastError());
+    std::vector<int32_t> nbs(nc), hc(nc), hq(nc);
+    HIPCHECK(hipMemcpyAsync(nbs.data(), H->nbsum, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(hc.data(), F.count, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(hq.data(), G.count, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    int64_t p2p = 0;
+    H->max_leaf = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        p2p += (int64_t)hc[c] * nbs[c];
+        H->max_leaf = std::max(H->max_leaf, std::max(hc[c], hq[c]));
+    }
+    H->fp32_levels = mixed_fp32_levels(H->kind);
+    H->m2l_inter = m2l;
+    H->p2p_inter = p2p;
+    H->transfer_entries = trans + trans_o;
+    // per-call buffers, sized for the larger of the two sets
+    H->io_cap = std::max(H->n, H->nq);
+    H->xs64 = dalloc<double>(H->io_cap);
+    H->far64 = dalloc<double>(H->io_cap);
+    H->near64 = dalloc<double>(H->io_cap);
+    H->xhi = dalloc<float>(H->io_cap);
+    H->xlo = dalloc<float>(H->io_cap);
+    H->rank = dalloc<int32_t>(H->n);
+    H->qrank = dalloc<int32_t>(H->nq);
+    k_invert_order<<<grid_for(H->n, 256), 256, 0, s>>>(H->n, H->order, H->rank);
+    k_invert_order<<<grid_for(H->nq, 256), 256, 0, s>>>(H->nq, H->qorder, H->qrank);
+    HIPCHECK(hipGetLastError());
+    // split partial vectors of the transverse pass, for either direction
+    int64_t part = 0;
+    for (int l = H->lmin; l <= H->kappa; l++)
+        for (const Level *L : {&H->lev[l], &H->lev_o[l]}) {
+            const int P = m2l_parts(*L);
+            if (P > 1) part = std::max(part, (int64_t)P * L->npiv);
+        }
+    if (part > 0) {
+        H->m2l_part = dalloc<double>(part);
+        H->m2l_part_cap = part;
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void run_matvec_general(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
+                        int precision, bool adjoint, hipStream_t s)
+{
+    const bool f32 = dtype == NNCA_F32;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    const int64_t ns = adjoint ? H->n : H->nq;
+    const int32_t *sorder = adjoint ? H->order : H->qorder;
+    const bool mixed = precision == NNCA_PREC_MIXED;
+    for (int64_t col = 0; col < nrhs; col++) {
+        const char *x = (const char *)X + col * ldx * es;
+        char *y = (char *)Y + col * ldy * es;
+        {
+            Span sp(H, s, PASS_GATHER, -1);
+            if (mixed && f32)
+                k_gather_split<float><<<grid_for(ns, 256), 256, 0, s>>>(ns, sorder, (const float *)x, H->xs64, H->xhi, H->xlo);
+            else if (mixed)
+                k_gather_split<double><<<grid_for(ns, 256), 256, 0, s>>>(ns, sorder, (const double *)x, H->xs64, H->xhi, H->xlo);
+            else if (f32)
+                k_gather64<float><<<grid_for(ns, 256), 256, 0, s>>>(ns, sorder, (const float *)x, H->xs64);
+            else
+                k_gather64<double><<<grid_for(ns, 256), 256, 0, s>>>(ns, sorder, (const double *)x, H->xs64);
+            HIPCHECK(hipGetLastError());
+        }
+        if (mixed) one_column_general<float>(H, adjoint, H->xhi, H->xlo, y, f32, s);
+        else one_column_general<double>(H, adjoint, nullptr, nullptr, y, f32, s);
     }
 }
 

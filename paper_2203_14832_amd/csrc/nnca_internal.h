@@ -111,6 +111,10 @@ struct Level {
 
     // apply state (one right-hand side at a time): multipole / local vectors
     double *w64 = nullptr, *u64 = nullptr;
+
+    // general case: the outgoing half's levels share the tree fields (key,
+    // coord, parent, children, lists) of the incoming half's levels
+    bool shares_tree = false;
 };
 
 struct ChunkInfo;
@@ -137,6 +141,22 @@ struct nnca_h2 {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_leafk = nullptr;           // after the leaf level's transverse kernel
     double build_seconds = 0.0;
+
+    // General case P != Q (Sec. 2.1, 2.3): n is |P| (the rows), nq = |Q| (the
+    // columns).  lev holds the incoming half of every cell (targets: first /
+    // count are ranges of P in P's tree order; pivots t^{B,i}, operators U_B /
+    // C_{B_c B}), lev_o the outgoing half (sources: ranges of Q in Q's tree
+    // order; pivots s^{B,o}, operators V_B / T_{B B_c}^T).  With P = Q
+    // (general == false) lev_o is empty and lev serves both halves.
+    bool general = false;
+    int64_t nq = 0;
+    std::vector<nnca::Level> lev_o;
+    double *qpts64 = nullptr;     // 3 x nq, Q's tree order
+    int32_t *qorder = nullptr;    // Q's tree position -> index into Q
+    int32_t *qrank = nullptr;     // inverse of qorder
+    int32_t *nbpre_o = nullptr;   // leaf level, transposed product: per N entry, targets before it
+    int32_t *nbsum_o = nullptr;   //   and per cell the near-field targets
+    int64_t io_cap = 0;           // entries of xs64, far64, near64, xhi, xlo
 
     double *pts64 = nullptr;      // 3 x n, tree order
     int32_t *order = nullptr;     // tree position -> original index
@@ -212,14 +232,22 @@ struct nnca_h2 {
 
 namespace nnca {
 
-// tree.hip
-void build_tree(nnca_h2 *H, const double *pts_dev, int64_t ld);
+// tree.hip.  With split >= 0 the points are the union of P (indices <
+// split) and Q, and the depth counts each set on its own.
+void build_tree(nnca_h2 *H, const double *pts_dev, int64_t ld, int64_t split = -1);
+// after build_tree over the union: the general layout (lev / lev_o ranges,
+// pts64 / qpts64, order / qorder); H->n becomes |P|
+void split_general(nnca_h2 *H, const double *Z, int64_t ldz, int64_t split);
 // aca.hip
 void build_pivots(nnca_h2 *H);
 void debug_kernel_eval(int kind, double hparam, int dim, const double *a, const double *b,
                        int64_t count, double *out, hipStream_t s);
 // apply.hip
 void prepare_apply(nnca_h2 *H);
+void prepare_general(nnca_h2 *H);
+// general case: Y = A~ X (X: nq rows, Y: n rows) or, with adjoint, A~^T X
+void run_matvec_general(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
+                        int precision, bool adjoint, hipStream_t s);
 // X, Y of element type dtype (NNCA_F32 / NNCA_F64)
 void run_matvec(nnca_h2 *H, const void *X, void *Y, int64_t nrhs, int64_t ldx, int64_t ldy, int dtype,
                 int precision, hipStream_t s);
@@ -246,7 +274,7 @@ void free_grad(nnca_h2 *H);
 // api.hip
 void destroy_handle(nnca_h2 *H);
 void check_matvec_args(nnca_h2 *h, const void *X, const void *Y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                       int32_t dtype, int32_t precision);
+                       int32_t dtype, int32_t precision, bool adjoint = false);
 void order_call_begin(nnca_h2 *h, hipStream_t s);
 void order_call_end(nnca_h2 *h, hipStream_t s);
 // batch.hip

@@ -131,6 +131,7 @@ extern "C" nnca_status nnca_matvec_noalloc(nnca_handle h, const void *X, void *Y
 {
     try {
         check_matvec_args(h, X, Y, nrhs, ldx, ldy, dtype, precision);
+        if (h->general) fail(NNCA_ERR_NOT_SUPPORTED, "nnca_matvec_noalloc covers P = Q only (a handle of nnca_build)");
         if (h->lev.size() > (size_t)NNCA_MAX_LEVELS) fail(NNCA_ERR_INTERNAL, "too many levels");
         Slots slots;
         per_call_buffers(h, slots);

@@ -121,6 +121,47 @@ __global__ void k_depth(const uint64_t *key, int64_t n, int64_t nu, int d, int k
     atomicMax(kappa, need);
 }
 
+// general case: flag[i] = 1 when the sorted point i belongs to P
+__global__ void k_class_flag(const int32_t *order, int64_t n, int64_t split, int32_t *flag)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = order[i] < split ? 1 : 0;
+}
+
+// stable split of the sorted union into P's and Q's tree orders (pre: the
+// exclusive count of P points before each sorted position); the keys of
+// each set, and their original indices (Q's relative to split)
+__global__ void k_split_sorted(const uint64_t *key, const int32_t *order, int64_t n, int64_t split,
+                               const int32_t *pre, uint64_t *pkey, uint64_t *qkey, int32_t *porder,
+                               int32_t *qorder)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t o = order[i];
+    if (o < split) {
+        if (pkey) pkey[pre[i]] = key[i];
+        if (porder) porder[pre[i]] = o;
+    } else {
+        const int64_t q = i - pre[i];
+        if (qkey) qkey[q] = key[i];
+        if (qorder) qorder[q] = (int32_t)(o - split);
+    }
+}
+
+// per cell: its range of P points and of Q points in the two tree orders
+__global__ void k_split_ranges(int64_t nc, const int32_t *first, const int32_t *count, const int32_t *pre,
+                               int32_t *pfirst, int32_t *pcount, int32_t *qfirst, int32_t *qcount)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int32_t f = first[c], e = f + count[c];
+    const int32_t a = pre[f], b = pre[e];
+    pfirst[c] = a;
+    pcount[c] = b - a;
+    qfirst[c] = f - a;
+    qcount[c] = (e - b) - (f - a);
+}
+
 __global__ void k_gather_pts(const double *p, int64_t n, int d, int64_t ld, const int32_t *order, double *out)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -310,7 +351,22 @@ static void build_list(nnca_h2 *H, int l, int which, int R)
     else { L.il_ptr = ptr; L.il = idx; L.nil = total; }
 }
 
-void build_tree(nnca_h2 *H, const double *pin, int64_t ld)
+// exclusive count of P points before every sorted position, n + 1 entries
+static int32_t *class_prefix(nnca_h2 *H, int64_t split)
+{
+    hipStream_t s = H->stream;
+    const int64_t n = H->n;
+    int32_t *flag = dalloc<int32_t>(n + 1);
+    int32_t *pre = dalloc<int32_t>(n + 1);
+    HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int32_t) * (n + 1), s));
+    k_class_flag<<<grid_for(n, 256), 256, 0, s>>>(H->order, n, split, flag);
+    HIPCHECK(hipGetLastError());
+    scan<int32_t>(flag, pre, n + 1, false, s);
+    dfree(flag);
+    return pre;
+}
+
+void build_tree(nnca_h2 *H, const double *pin, int64_t ld, int64_t split)
 {
     hipStream_t s = H->stream;
     const int64_t n = H->n;
@@ -367,13 +423,31 @@ void build_tree(nnca_h2 *H, const double *pin, int64_t ld)
     dfree(k_in);
     dfree(i_in);
 
-    // depth
+    // depth: the first level with at most nu points in every cell; in the
+    // general case at most nu points of P and at most nu of Q (Sec. 2.1),
+    // found on each set's sorted keys
     int kap = 0;
     if (H->L > 0.0 && n > H->leaf) {
         int *dk = dalloc<int>(1);
         HIPCHECK(hipMemsetAsync(dk, 0, sizeof(int), s));
-        k_depth<<<grid_for(n, 256), 256, 0, s>>>(H->keys, n, H->leaf, d, H->kmax, dk);
-        HIPCHECK(hipGetLastError());
+        if (split < 0) {
+            k_depth<<<grid_for(n, 256), 256, 0, s>>>(H->keys, n, H->leaf, d, H->kmax, dk);
+            HIPCHECK(hipGetLastError());
+        } else {
+            int32_t *pre = class_prefix(H, split);
+            uint64_t *pk = dalloc<uint64_t>(split), *qk = dalloc<uint64_t>(n - split);
+            k_split_sorted<<<grid_for(n, 256), 256, 0, s>>>(H->keys, H->order, n, split, pre, pk, qk, nullptr,
+                                                             nullptr);
+            HIPCHECK(hipGetLastError());
+            if (split > H->leaf) k_depth<<<grid_for(split, 256), 256, 0, s>>>(pk, split, H->leaf, d, H->kmax, dk);
+            if (n - split > H->leaf)
+                k_depth<<<grid_for(n - split, 256), 256, 0, s>>>(qk, n - split, H->leaf, d, H->kmax, dk);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipStreamSynchronize(s));
+            dfree(pre);
+            dfree(pk);
+            dfree(qk);
+        }
         HIPCHECK(hipMemcpyAsync(&kap, dk, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         dfree(dk);
@@ -437,6 +511,56 @@ void build_tree(nnca_h2 *H, const double *pin, int64_t ld)
     H->lmin = kap + 1;
     for (int l = 1; l <= kap; l++)
         if (H->lev[l].nil > 0) { H->lmin = l; break; }
+}
+
+void split_general(nnca_h2 *H, const double *Z, int64_t ldz, int64_t split)
+{
+    hipStream_t s = H->stream;
+    const int64_t n = H->n, np = split, nq = n - split;
+    const int d = H->dim;
+    int32_t *pre = class_prefix(H, split);
+    int32_t *porder = dalloc<int32_t>(np);
+    H->qorder = dalloc<int32_t>(nq);
+    k_split_sorted<<<grid_for(n, 256), 256, 0, s>>>(H->keys, H->order, n, split, pre, nullptr, nullptr, porder,
+                                                     H->qorder);
+    HIPCHECK(hipGetLastError());
+    H->lev_o.assign(H->lev.size(), Level());
+    for (size_t l = 0; l < H->lev.size(); l++) {
+        Level &L = H->lev[l];
+        Level &O = H->lev_o[l];
+        const int64_t nc = L.ncell;
+        int32_t *pf = dalloc<int32_t>(nc), *pc = dalloc<int32_t>(nc);
+        int32_t *qf = dalloc<int32_t>(nc), *qc = dalloc<int32_t>(nc);
+        k_split_ranges<<<grid_for(nc, 256), 256, 0, s>>>(nc, L.first, L.count, pre, pf, pc, qf, qc);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(s));
+        dfree(L.first);
+        dfree(L.count);
+        L.first = pf;
+        L.count = pc;
+        O = L;   // the tree fields, shared
+        O.shares_tree = true;
+        O.first = qf;
+        O.count = qc;
+    }
+    // the points of each set in its own tree order
+    dfree(H->pts64);
+    H->pts64 = nullptr;
+    double *pp = dalloc<double>(3 * np), *qp = dalloc<double>(3 * nq);
+    HIPCHECK(hipMemsetAsync(pp, 0, sizeof(double) * 3 * np, s));
+    HIPCHECK(hipMemsetAsync(qp, 0, sizeof(double) * 3 * nq, s));
+    k_gather_pts<<<grid_for(np, 256), 256, 0, s>>>(Z, np, d, ldz, porder, pp);
+    k_gather_pts<<<grid_for(nq, 256), 256, 0, s>>>(Z + split, nq, d, ldz, H->qorder, qp);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(pre);
+    dfree(H->order);
+    H->order = porder;
+    H->pts64 = pp;
+    H->qpts64 = qp;
+    H->n = np;
+    H->nq = nq;
+    H->general = true;
 }
 
 }  // namespace nnca

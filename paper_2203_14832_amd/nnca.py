@@ -135,6 +135,10 @@ def lib():
             "nnca_batch_destroy": [P],
             "nnca_probe_rates": [P, i32, P],
             "nnca_gmres": [P, f64, f64, P, P, f64, i32, i32, i32, P, P, P],
+            "nnca_build_general": [P, i64, i64, P, i64, i64, i32, i32, i32, f64, f64, i32, P, P, P],
+            "nnca_query_shape": [P, P, P, P],
+            "nnca_export_half": [P, i32, i32, P, P, P],
+            "nnca_export_half_operator": [P, i32, i32, i64, P, i64, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -375,6 +379,89 @@ class H2Matrix:
         _check(lib().nnca_export_operator(self._h, level, cell, None, 0, C.byref(m), C.byref(k)))
         Cm = np.zeros(max(m.value * k.value, 1))
         _check(lib().nnca_export_operator(self._h, level, cell, _np_ptr(Cm), Cm.size, C.byref(m), C.byref(k)))
+        return Cm[: m.value * k.value].reshape(m.value, k.value)
+
+
+class H2General(H2Matrix):
+    """H2 representation of the general case A_ij = K(p_i, q_j), targets P
+    and sources Q (``nnca_build_general``): ``matvec`` maps (nq,) or (nq, r)
+    to (np,) or (np, r), ``rmatvec`` the other way."""
+
+    def __init__(self, targets, sources, kernel: str = "inv_r", tol: float = 1e-6, leaf_size: int = 64,
+                 length_scale: float = 1.0, eta2=None, policy: int = 1, workspace_bytes: int = 0,
+                 rank_reserve: int = 0, device="cuda:0", allocator: str | None = "torch"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        P = torch.as_tensor(targets, dtype=torch.float64)
+        Q = torch.as_tensor(sources, dtype=torch.float64)
+        npt, d = P.shape
+        nq = Q.shape[0]
+        if Q.shape[1] != d:
+            raise ValueError("targets and sources differ in dimension")
+        self.n, self.nq, self.dim, self.kernel = npt, nq, d, kernel
+        self.length_scale = float(length_scale)
+        ps = P.t().contiguous().to(self.device)
+        qs = Q.t().contiguous().to(self.device)
+        opts = BuildOptions(C.sizeof(BuildOptions), 0, 0, int(policy), int(workspace_bytes), int(rank_reserve), 0,
+                            1, 0)
+        if eta2 is not None:
+            opts.eta2_num, opts.eta2_den = int(eta2[0]), int(eta2[1])
+        self.alloc_record = None
+        if allocator == "torch":
+            ctx = len(_alloc_records) + 1
+            self.alloc_record = _alloc_records[ctx] = AllocRecord(self.device)
+            opts.alloc, opts.free, opts.alloc_ctx = _TORCH_ALLOC, _TORCH_FREE, ctx
+        elif allocator is not None:
+            raise ValueError("allocator must be 'torch' or None")
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_build_general(C.c_void_p(ps.data_ptr()), npt, npt, C.c_void_p(qs.data_ptr()), nq, nq,
+                                            d, 1, KINDS[kernel], float(length_scale), float(tol), int(leaf_size),
+                                            C.byref(opts), _stream(torch), C.byref(h)))
+        self._h = h
+        self._soa = (ps, qs)
+        self._destroy = lib().nnca_destroy
+        _live.add(self)
+
+    def shape(self):
+        r, c, g = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().nnca_query_shape(self._h, C.byref(r), C.byref(c), C.byref(g)))
+        return r.value, c.value, bool(g.value)
+
+    def _apply(self, X, precision: str, adjoint: bool, out=None, fn=None):
+        torch = self.torch
+        nin, nout = (self.n, self.nq) if adjoint else (self.nq, self.n)
+        Xc, r, vec = _as_columns(torch, X, nin, self.device, keep_f32=True)
+        Y = torch.empty((r, nout), dtype=Xc.dtype, device=self.device) if out is None else out
+        dt = DTYPE_F32 if Xc.dtype == torch.float32 else DTYPE_F64
+        if fn is None:
+            fn = lib().nnca_matvec_adjoint if adjoint else lib().nnca_matvec
+        with torch.cuda.device(self.device):
+            _check(fn(self._h, C.c_void_p(Xc.data_ptr()), C.c_void_p(Y.data_ptr()), r, nin, nout, dt,
+                      PRECISION[precision], _stream(torch)))
+        return Y.reshape(nout) if vec else Y.t()
+
+    def half_pivots(self, level: int, half: str):
+        """(ptr, rows, cols): half "in" rows t^{B,i} (into P), cols s^{B,i}
+        (into Q); half "out" rows s^{B,o} (into Q), cols t^{B,o} (into P)."""
+        hf = 0 if half == "in" else 1
+        ptr = np.zeros(self.info()["ncell"][level] + 1, np.int64)
+        _check(lib().nnca_export_half(self._h, level, hf, _np_ptr(ptr), None, None))
+        npv = int(ptr[-1])
+        rows = np.zeros(max(npv, 1), np.int64)
+        cols = np.zeros(max(npv, 1), np.int64)
+        _check(lib().nnca_export_half(self._h, level, hf, _np_ptr(ptr), _np_ptr(rows), _np_ptr(cols)))
+        return ptr, rows[:npv], cols[:npv]
+
+    def half_operator(self, level: int, half: str, cell: int):
+        hf = 0 if half == "in" else 1
+        m = C.c_int64()
+        k = C.c_int64()
+        _check(lib().nnca_export_half_operator(self._h, level, hf, cell, None, 0, C.byref(m), C.byref(k)))
+        Cm = np.zeros(max(m.value * k.value, 1))
+        _check(lib().nnca_export_half_operator(self._h, level, hf, cell, _np_ptr(Cm), Cm.size, C.byref(m),
+                                               C.byref(k)))
         return Cm[: m.value * k.value].reshape(m.value, k.value)
 
 

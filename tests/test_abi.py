@@ -65,6 +65,32 @@ def test_invalid_arguments(lib):
     assert lib.nnca_matvec_backward(None, None, None, 1, 1, 1, 0, None, 1, None, None) == 1
 
 
+def test_general_build_invalid_arguments(lib):
+    p = np.zeros((3, 10))
+    q = np.zeros((3, 12))
+    P, Q = p.ctypes.data_as(C.c_void_p), q.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+
+    def bg(Pp, np_, ldp, Qp, nq, ldq, dim=3, kind=2, hh=1.0, tol=1e-6, leaf=64, out=True):
+        return lib.nnca_build_general(Pp, np_, ldp, Qp, nq, ldq, dim, 0, kind, hh, tol, leaf, None, None,
+                                      C.byref(h) if out else None)
+    assert bg(None, 10, 10, Q, 12, 12) == 1
+    assert bg(P, 10, 10, None, 12, 12) == 1
+    assert bg(P, 10, 10, Q, 12, 12, out=False) == 1
+    assert bg(P, 0, 10, Q, 12, 12) == 1
+    assert bg(P, 10, 10, Q, 0, 12) == 1
+    assert bg(P, 10, 5, Q, 12, 12) == 1
+    assert bg(P, 10, 10, Q, 12, 11) == 1
+    assert bg(P, 10, 10, Q, 12, 12, dim=4) == 1
+    assert bg(P, 10, 10, Q, 12, 12, tol=-1.0) == 1
+    assert bg(P, 10, 10, Q, 12, 12, kind=1) == 4   # log only in 2D
+    assert bg(P, 10, 10, Q, 12, 12, kind=3, hh=0.0) == 1
+    assert not h.value
+    assert lib.nnca_query_shape(None, None, None, None) == 1
+    assert lib.nnca_export_half(None, 0, 0, None, None, None) == 1
+    assert lib.nnca_export_half_operator(None, 0, 0, 0, None, 0, None, None) == 1
+
+
 def test_build_options_layout(lib):
     # the struct grew at its end: the first version ends at `reserved` (32
     # bytes); the allocator fields follow the column-workspace size
