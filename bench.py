@@ -116,7 +116,7 @@ def main():
                          "mixed matvecs of the workload, no timing")
     ap.add_argument("--rates", action="store_true",
                     help="print the device's attainable rates (copy, FMA, rsq, the symmetric pass's inner loop)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie", "exp"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie", "exp", "general"],
                     help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
                          "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
     args = ap.parse_args()
@@ -146,6 +146,8 @@ def main():
         return bench_integral_equation(args)
     if args.config == "exp":
         return bench_experiments(args)
+    if args.config == "general":
+        return bench_general(args)
     dev = torch.device("cuda:0")
     p, x = workload("c2", n=args.n)
     n = p.shape[0]
@@ -339,6 +341,66 @@ def bench_experiments(args):
     for na in (32, 40, 50, 64, 80, 100):
         one(4, "Chebyshev 3D", "inv_reg", chebyshev_grid(na, 3), 1e-7)
     print(json.dumps({"config": "exp", "a": a, "rows": rows}), flush=True)
+
+
+def bench_general(args):
+    """The general case P != Q (Sec. 2.3): 3D 1/r, tol 1e-6, leaf 64, sources
+    Q = 2^20 points uniform in [-1,1]^3, targets P either 2^20 other points
+    uniform in the same cube (evaluation at new points) or 2^19 points in the
+    shifted cube 0.3 + 0.8 [-1,1]^3.  Build time, the forward (Q -> P) and
+    transposed (P -> Q) products in FP64 and mixed precision, interactions
+    per second, and the error against the FP64 direct sum on 16384 sampled
+    targets (nnca_direct over the sampled targets and the sources with zero
+    weights on the targets: K is 0 only at r = 0, as in the method)."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    dev = torch.device("cuda:0")
+    rows = []
+    steps = max(1, args.steps // 4)
+    for name in ("same_cube", "shifted"):
+        rng = np.random.default_rng(1012)
+        Q = rng.uniform(-1, 1, (1 << 20, 3))
+        if name == "same_cube":
+            P = rng.uniform(-1, 1, (1 << 20, 3))
+        else:
+            P = rng.uniform(-1, 1, (1 << 19, 3)) * 0.8 + 0.3
+        x = torch.tensor(rng.standard_normal(Q.shape[0]), device=dev)
+        g = torch.tensor(rng.standard_normal(P.shape[0]), device=dev)
+        t0 = time.perf_counter()
+        G = nnca.H2General(P, Q, "inv_r", 1e-6, 64, device=dev)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        inf = G.info()
+        inter = inf["m2l_interactions"] + inf["p2p_interactions"]
+        out = {"layout": name, "np": int(P.shape[0]), "nq": int(Q.shape[0]), "kappa": inf["kappa"],
+               "assembly_s": ta, "m2l_interactions": inf["m2l_interactions"],
+               "p2p_interactions": inf["p2p_interactions"]}
+        sample = np.sort(rng.choice(P.shape[0], 16384, replace=False))
+        Z = np.vstack([P[sample], Q])
+        xz = torch.cat([torch.zeros(len(sample), dtype=torch.float64, device=dev), x])
+        yd = nnca.direct(Z, xz, "inv_r", device=dev)[: len(sample)]
+        sd = torch.tensor(sample, device=dev)
+        for prec in ("fp64", "mixed"):
+            for tr, fn, v in (("forward", G.matvec, x), ("transposed", G.rmatvec, g)):
+                y = fn(v, prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    y = fn(v, prec)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / steps * 1e3
+                out[f"{tr}_ms_{prec}"] = ms
+                if tr == "forward":
+                    out[f"interactions_per_s_{prec}"] = inter / (ms * 1e-3)
+                    out[f"eps_m_{prec}"] = float(torch.linalg.norm(y[sd] - yd) / torch.linalg.norm(yd))
+        rows.append(out)
+        print(json.dumps(out), file=sys.stderr, flush=True)
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    print(json.dumps({"config": "general", "workload": "3D 1/r, tol 1e-6, leaf 64, 2^20 uniform sources; targets "
+                                                       "2^20 uniform in the same cube, or 2^19 in a shifted cube",
+                      "rows": rows}), flush=True)
 
 
 def bench_integral_equation(args):

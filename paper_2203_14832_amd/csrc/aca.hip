@@ -32,7 +32,9 @@ namespace {
 constexpr int NT = 256;      // threads per cell
 constexpr int DOTB = 8;      // cross products reduced per pass
 constexpr int COEF = 2048;   // coefficients staged in LDS
-constexpr int RW = 4;        // residual columns per thread and pass
+constexpr int RW = 2;        // residual columns per thread and pass
+constexpr int LA = 4;        // panel rows loaded ahead in the row residual
+constexpr int LU = 8;        // panel columns loaded ahead in the column residual
 
 // log x from IEEE operations: x = m 2^e, m in (sqrt(1/2), sqrt(2)],
 // log m = 2 atanh(s) with s = (m-1)/(m+1) and the series of atanh(s)/s in s^2
@@ -231,7 +233,7 @@ __device__ inline void tree_argmax(double *v, int32_t *ix, int t)
 //  5. ||A^(k)||^2 = (||A^(k-1)||^2 + 2 sum_{l<k} (u_k.u_l)(v_l.v_k)) + |u_k|^2 |v_k|^2
 //  6. stop when |u_k| |v_k| <= tol ||A^(k)|| (the cross is kept) or k = min(m, n)
 //  7. i_{k+1} = argmax over unused rows of |u_k|
-__global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0, const double *P, int64_t np,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_aca(const AcaCell *cells, int32_t cell0, const double *P, int64_t np,
                                              int d, const int32_t *tsrc, const int32_t *sid,
                                              const double *sc, int64_t ntot, double *U, double *V,
                                              uint8_t *flags, int kind, double hh, double tol, int32_t *k_out,
@@ -251,7 +253,8 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
     __shared__ double sv[NT];
     __shared__ int32_t si[NT];
     __shared__ double su2[NT], sv2[NT];
-    __shared__ double du[DOTB][NT], dv[DOTB][NT];
+    __shared__ double red[DOTB][NT];   // cross-term partials: the u side, then the v side
+    __shared__ double ured[DOTB];
     __shared__ double coef[COEF];
     __shared__ int32_t s_row, s_k, s_stop, s_jk, s_over;
 
@@ -292,7 +295,25 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
             }
             const int nv = (n - j0 + NT - 1) / NT < RW ? (n - j0 + NT - 1) / NT : RW;
             if (nv == RW) {
-                for (int32_t l = 0; l < k; l++) {
+                // LA rows of the panel in flight: their loads are issued
+                // before the updates, which still run in ascending l for
+                // every column
+                int32_t l = 0;
+                for (; l + LA - 1 < k; l += LA) {
+                    double ul[LA], a[LA][RW];
+#pragma unroll
+                    for (int q = 0; q < LA; q++) {
+                        ul[q] = l + q < COEF ? coef[l + q] : Uc[(int64_t)(l + q) * m + i];
+                        const double *Vl = Vc + (int64_t)(l + q) * n + j0;
+#pragma unroll
+                        for (int c = 0; c < RW; c++) a[q][c] = Vl[c * NT];
+                    }
+#pragma unroll
+                    for (int q = 0; q < LA; q++)
+#pragma unroll
+                        for (int c = 0; c < RW; c++) r[c] = r[c] - ul[q] * a[q][c];
+                }
+                for (; l < k; l++) {
                     double ul = l < COEF ? coef[l] : Uc[(int64_t)l * m + i];
                     const double *Vl = Vc + (int64_t)l * n + j0;
 #pragma unroll
@@ -357,7 +378,18 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
             if (!rf[r]) {
                 int32_t rid = tsrc ? tsrc[C.tt_off + r] : C.tt_off + r;
                 u = kval(kind, hh, d, P[rid], P[np + rid], d == 3 ? P[2 * np + rid] : 0.0, bx, by, bz);
-                for (int32_t l = 0; l < k; l++) {
+                int32_t l = 0;
+                for (; l + LU - 1 < k; l += LU) {   // LU loads in flight, updates in ascending l
+                    double vl[LU], a[LU];
+#pragma unroll
+                    for (int q = 0; q < LU; q++) {
+                        vl[q] = l + q < COEF ? coef[l + q] : Vc[(int64_t)(l + q) * n + jk];
+                        a[q] = Uc[(int64_t)(l + q) * m + r];
+                    }
+#pragma unroll
+                    for (int q = 0; q < LU; q++) u = u - vl[q] * a[q];
+                }
+                for (; l < k; l++) {
                     double vl = l < COEF ? coef[l] : Vc[(int64_t)l * n + jk];
                     u = u - vl * Uc[(int64_t)l * m + r];
                 }
@@ -391,27 +423,43 @@ __global__ __launch_bounds__(NT) void k_aca(const AcaCell *cells, int32_t cell0,
         for (int32_t lb = 0; lb < k; lb += DOTB) {
             int nbat = k - lb < DOTB ? k - lb : DOTB;
             double au[DOTB], av[DOTB];
+#pragma unroll
             for (int q = 0; q < DOTB; q++) { au[q] = 0.0; av[q] = 0.0; }
             for (int32_t r = t; r < m; r += NT) {
                 double x = uk[r];
-                for (int q = 0; q < nbat; q++) au[q] = au[q] + x * Uc[(int64_t)(lb + q) * m + r];
+#pragma unroll
+                for (int q = 0; q < DOTB; q++)
+                    if (q < nbat) au[q] = au[q] + x * Uc[(int64_t)(lb + q) * m + r];
             }
-            for (int32_t j = t; j < n; j += NT) {
+            int32_t j = t;
+            for (; j < n; j += NT) {
                 double x = Rk[j];
-                for (int q = 0; q < nbat; q++) av[q] = av[q] + Vc[(int64_t)(lb + q) * n + j] * x;
+#pragma unroll
+                for (int q = 0; q < DOTB; q++)
+                    if (q < nbat) av[q] = av[q] + Vc[(int64_t)(lb + q) * n + j] * x;
             }
-            for (int q = 0; q < DOTB; q++) { du[q][t] = au[q]; dv[q][t] = av[q]; }
+            // the pairwise trees of the u partials, then of the v partials,
+            // in one LDS buffer
+#pragma unroll
+            for (int q = 0; q < DOTB; q++) red[q][t] = au[q];
             __syncthreads();
             for (int st = NT / 2; st > 0; st >>= 1) {
                 if (t < st)
-                    for (int q = 0; q < nbat; q++) {
-                        du[q][t] = du[q][t] + du[q][t + st];
-                        dv[q][t] = dv[q][t] + dv[q][t + st];
-                    }
+                    for (int q = 0; q < nbat; q++) red[q][t] = red[q][t] + red[q][t + st];
+                __syncthreads();
+            }
+            if (t < DOTB) ured[t] = red[t][0];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < DOTB; q++) red[q][t] = av[q];
+            __syncthreads();
+            for (int st = NT / 2; st > 0; st >>= 1) {
+                if (t < st)
+                    for (int q = 0; q < nbat; q++) red[q][t] = red[q][t] + red[q][t + st];
                 __syncthreads();
             }
             if (t == 0)
-                for (int q = 0; q < nbat; q++) s = s + du[q][0] * dv[q][0];
+                for (int q = 0; q < nbat; q++) s = s + ured[q] * red[q][0];
             __syncthreads();
         }
         // 6: bookkeeping and the stopping rule (thread 0)
