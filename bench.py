@@ -42,6 +42,9 @@ PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
 # the counters' reading of a 256 MiB copy: fetch + write MiB at kappa and
 # kappa-1.  Valid for one version of k_m2l_sym; None once the kernel changes.
 M2L_SYM_HBM_MIB = ((277.0, 339.9), (94.1, 117.0))
+# Dense FP32 matrix-core peak of MI355X (the many-column transverse pass and
+# near field multiply FP32 kernel tiles by weight tiles on the matrix cores)
+FP32_MFMA_PEAK = 157.3e12
 
 
 def cpu_model() -> str:
@@ -507,6 +510,35 @@ def bench_many_rhs(args):
             H.matvec_raw(X[col:col + 1], Yl[col:col + 1], 1, "mixed")
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t0) / reps * 1e3
+    # per-pass event timing of a few block matvecs: the transverse pass per
+    # level and the near field, for the matrix-core roofline of the block
+    H.profile(True)
+    for _ in range(3):
+        H.matvec_raw(X, Yb, R, "mixed")
+    torch.cuda.synchronize()
+    ps, lv, pm = H.profile_read()
+    H.profile(False)
+    kap = info["kappa"]
+    fl = max(info["lmin"], kap - info["mixed_fp32_levels"] + 1)
+    f32_levels = list(range(fl, kap + 1))
+    m2l32_ms = float(pm[(ps == 2) & (lv >= fl)].sum() / 3)
+    m2l64_ms = float(pm[(ps == 2) & (lv < fl)].sum() / 3)
+    p2p_ms = float(pm[ps == 4].sum() / 3)
+    f32_inter = sum(info["m2l_level"][l] for l in f32_levels)
+    # one FMA per column and interaction; the mixed near field multiplies
+    # x_hi and x_lo (two FMAs)
+    m2l_flops = 2.0 * R * f32_inter
+    p2p_flops = 4.0 * R * info["p2p_interactions"]
+    roof = {"bound": "mfma", "kernel": "k_m2l_mfma<1/r> (FP32 kernel tiles x weight tiles, levels %s)" % f32_levels,
+            "achieved": m2l_flops / (m2l32_ms * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": m2l_flops / (m2l32_ms * 1e-3) / FP32_MFMA_PEAK, "traffic": None,
+            "ms_per_block": m2l32_ms, "flops_per_block": m2l_flops,
+            "near_field": {"kernel": "k_p2p_mfma<1/r> (+ combine)", "ms_per_block": p2p_ms,
+                           "achieved": p2p_flops / (p2p_ms * 1e-3) / 1e12,
+                           "frac": p2p_flops / (p2p_ms * 1e-3) / FP32_MFMA_PEAK},
+            "coarse_fp64_refined_m2l_ms_per_block": m2l64_ms,
+            "pass_ms_per_block": {name: float(pm[ps == i].sum() / 3)
+                                  for i, name in enumerate(["gather", "up", "m2l", "down", "p2p"])}}
     err_block = float((torch.linalg.norm(Yb - Y64, dim=1) / torch.linalg.norm(Y64, dim=1)).max())
     err_loop = float((torch.linalg.norm(Yl - Y64, dim=1) / torch.linalg.norm(Y64, dim=1)).max())
     inter = info["m2l_interactions"] + info["p2p_interactions"]
@@ -518,7 +550,7 @@ def bench_many_rhs(args):
            "loop_ms_per_64_columns": loop_ms, "block_speedup": loop_ms / block_ms,
            "err_block_vs_fp64_max": err_block, "err_loop_vs_fp64_max": err_loop, "build_seconds": build_s,
            "interactions_per_column": inter,
-           "block_interaction_columns_per_s": inter * R / (block_ms * 1e-3)}
+           "block_interaction_columns_per_s": inter * R / (block_ms * 1e-3), "roofline": roof}
     print(json.dumps(out), flush=True)
 
 

@@ -1059,29 +1059,6 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
     launch_m2l_pair<MODE, C>(kind, H, L, L, pc, pc, prm, s, after);
 }
 
-// event pair around one launch when the handle is profiling
-struct Span {
-    nnca_h2 *H;
-    hipStream_t s;
-    bool on;
-    nnca_h2::ProfRec r;
-    Span(nnca_h2 *H_, hipStream_t s_, int pass, int level) : H(H_), s(s_), on(((H_->prof_mask >> pass) & 1) != 0)
-    {
-        if (!on) return;
-        r.pass = pass;
-        r.level = level;
-        HIPCHECK(hipEventCreate(&r.a));
-        HIPCHECK(hipEventCreate(&r.b));
-        HIPCHECK(hipEventRecord(r.a, s));
-    }
-    ~Span() noexcept(false)
-    {
-        if (!on) return;
-        HIPCHECK(hipEventRecord(r.b, s));
-        H->prof.push_back(r);
-    }
-};
-
 // split factor of the symmetric pass: as for the plain pass, on the owned sources
 static int sym_parts(const nnca::Level &L)
 {

@@ -936,9 +936,12 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
     const bool mixed = precision == NNCA_PREC_MIXED;
     const int kind = H->kind;
     auto &W = H->multi;
-    k_gather_multi<TI><<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, X, ldx, W.xs,
-                                                                 mixed ? W.xhi : nullptr, mixed ? W.xlo : nullptr);
-    HIPCHECK(hipGetLastError());
+    {
+        Span sp(H, s, PASS_GATHER, -1);
+        k_gather_multi<TI><<<(unsigned)((n + 63) / 64), 256, 0, s>>>(n, R, RP, H->rank, X, ldx, W.xs,
+                                                                     mixed ? W.xhi : nullptr, mixed ? W.xlo : nullptr);
+        HIPCHECK(hipGetLastError());
+    }
     const double prm64 = kernel_prm64(kind, H->hparam);
     const float prm32 = kernel_prm32(kind, H->hparam);
     double *far = nullptr;
@@ -948,6 +951,7 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
             const double *src = l == kap ? W.xs : W.w[l + 1];
             const int ipc = (int)((L.max_k + 63) / 64) * NCB;
             const unsigned nb = (unsigned)(L.ncell * ipc);
+            Span sp(H, s, PASS_UP, l);
             if (nb < SPLIT_BELOW)
                 k_up_multi_split<<<nb, 64 * SPLIT_WAVES, 0, s>>>(ipc, RP, L.piv_ptr, L.tt_off, L.ipos, L.rem_ptr,
                                                                  L.rem_pos, L.crem_off, L.crem64, src, W.w[l]);
@@ -972,7 +976,10 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
             tab = &it->second;
         }
         check_part(H, RP, tab);
-        for (int l = lmin; l <= kap; l++) m2l_level_multi<NCB>(H, l, tab ? (*tab)[l] : parts_for(H->lev[l]), mixed, s);
+        for (int l = lmin; l <= kap; l++) {
+            Span sp(H, s, PASS_M2L, l);   // the launch and, for split levels, the ordered sum of its parts
+            m2l_level_multi<NCB>(H, l, tab ? (*tab)[l] : parts_for(H->lev[l]), mixed, s);
+        }
         far = W.far;
         for (int l = lmin; l <= kap; l++) {
             Level &L = H->lev[l];
@@ -980,6 +987,7 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
             const int nqc = (int)((L.max_k + 63) / 64);
             const int ipc = (nqc + (int)((L.max_nrem + 63) / 64)) * NCB;
             const unsigned nb = (unsigned)(L.ncell * ipc);
+            Span sp(H, s, PASS_DOWN, l);
             if (nb < SPLIT_BELOW)
                 k_down_multi_split<<<nb, 64 * SPLIT_WAVES, 0, s>>>(ipc, nqc, RP, L.piv_ptr, L.tt_off, L.ipos,
                                                                    L.rem_ptr, L.rem_pos, L.crem_off, L.crem_t,
@@ -991,6 +999,7 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
         }
     }
     const Level &F = H->lev[kap];
+    Span sp(H, s, PASS_P2P, kap);   // the near field and the combine
 #define PP(T, K, A, B, PRM) k_p2p_mfma<T, K, NCB><<<(int)F.ncell, NT, 0, s>>>(F.ncell, F.first, F.count, F.nb_ptr, F.nb, H->nbpre, H->nbsum, H->pts64, n, H->dim, A, B, far, W.far, R, PRM)
     if (mixed) {
         if (kind == NNCA_K_INV_R) PP(float, NNCA_K_INV_R, W.xhi, W.xlo, prm32);

@@ -297,6 +297,29 @@ void probe_rates(double *out, int32_t count, hipStream_t s);
 void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, double hparam,
                 const double *X, double *Y, int64_t nrhs, int64_t ldx, int64_t ldy, hipStream_t s);
 
+// event pair around one launch when the handle is profiling
+struct Span {
+    nnca_h2 *H;
+    hipStream_t s;
+    bool on;
+    nnca_h2::ProfRec r;
+    Span(nnca_h2 *H_, hipStream_t s_, int pass, int level) : H(H_), s(s_), on(((H_->prof_mask >> pass) & 1) != 0)
+    {
+        if (!on) return;
+        r.pass = pass;
+        r.level = level;
+        HIPCHECK(hipEventCreate(&r.a));
+        HIPCHECK(hipEventCreate(&r.b));
+        HIPCHECK(hipEventRecord(r.a, s));
+    }
+    ~Span() noexcept(false)
+    {
+        if (!on) return;
+        HIPCHECK(hipEventRecord(r.b, s));
+        H->prof.push_back(r);
+    }
+};
+
 inline int grid_for(int64_t work, int block)
 {
     int64_t g = (work + block - 1) / block;
