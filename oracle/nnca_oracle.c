@@ -18,7 +18,10 @@
  *     the nested bases of Sec. 2.3.1);
  *   - the H2 matrix-vector product of Sec. 4 (upward, transverse, downward
  *     passes and the near field);
- *   - the dense direct sum, the plain definition A_ij = K(p_i, p_j).
+ *   - the dense direct sum, the plain definition A_ij = K(p_i, p_j);
+ *   - the general case P != Q (Sec. 2.1, 2.3): one tree over both sets, the
+ *     incoming and the outgoing ACA of every cell, the rectangular product
+ *     and its transpose, and the rectangular direct sum.
  *
  * Everything is FP64, sequential inside a cell, with OpenMP only over the
  * independent cells of one tree level.  Floating-point expressions are written
