@@ -260,8 +260,16 @@ nnca_status nnca_direct(const double *points, int64_t n, int32_t dim, int64_t ld
  *                        arguments replay it (other arguments re-capture);
  *   NNCA_BATCH_AUTOTUNE  the first call for a column-block width and
  *                        precision times split factors 1, 2, 4, ..., 64 of
- *                        every level's transverse-pass launch on the live
- *                        data and keeps the fastest (many-column path).
+ *                        every level's transverse-pass launch and, on the
+ *                        FP32 levels, two tile shapes (sources per LDS tile)
+ *                        on the live data and keeps the fastest (many-column
+ *                        path).  If the environment variable NNCA_TUNE_CACHE
+ *                        names a file, choices are read from it first and
+ *                        new ones appended to it (one text line per level
+ *                        shape: device architecture, pass, form, column-block
+ *                        width and log2 buckets of the level's cell count,
+ *                        sources per cell and rank), so later processes skip
+ *                        the timing.
  * Errors: INVALID_ARG (NULL, count < 1, unknown flags, mismatched handles),
  * NOT_SUPPORTED (a problem without a far field, more than 2^30 rows),
  * OUT_OF_MEMORY, HIP.                                                     */

@@ -17,6 +17,11 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <string>
+
 #include "nnca_internal.h"
 #include "kernel_values.h"
 
@@ -339,8 +344,9 @@ __global__ void k_to_f32(int64_t cnt, const double *a, float *b)
 // weight operand), or, with fewer than four units, a phase of the 4-source
 // steps of one unit.  With one column block the kernel fits six waves per
 // SIMD in 80 registers (the matrix products then accumulate in ordinary
-// vector registers).
-template <int KIND, int NCB>
+// vector registers).  TSEL = 1 halves the sources per LDS tile (a tile
+// shape the autotuner may pick per level).
+template <int KIND, int NCB, int TSEL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 2))) void k_m2l_mfma(int64_t nc, int P, const int32_t *k, const int32_t *piv_ptr,
                                                  const int32_t *il_ptr, const int32_t *il, const int32_t *ilpre,
                                                  const int32_t *ilsum, const float *pc, int64_t npiv,
@@ -349,7 +355,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
 {
     constexpr int RP = NCB * 16;
     constexpr int TB = NCB <= 2 ? 2 : 1;             // target blocks per wavefront
-    constexpr int TS = NCB == 1 ? 256 : 128;         // sources per LDS tile
+    constexpr int TS = (NCB == 1 ? 256 : 128) >> TSEL;   // sources per LDS tile
     static_assert(TS % 64 == 0 && TS <= NT, "the tile pads to a multiple of 64 sources, one per thread");
     constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
     constexpr int RED = NT * NCB * 4 * TB;           // doubles of the phase reduction
@@ -824,7 +830,7 @@ int parts_for(const Level &L)
 
 // transverse pass of one level for a block of NCB * 16 columns, split P ways
 template <int NCB>
-void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
+void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s, int tsel = 0)
 {
     constexpr int RP = NCB * 16;
     auto &W = H->multi;
@@ -835,12 +841,15 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s)
     double *part = P > 1 ? W.part : nullptr;
     const int g = (int)(L.ncell * P);
     if (mixed && l > kap - H->fp32_levels) {
-#define MF(K) k_m2l_mfma<K, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w32[l], W.R, W.u[l], part, prm32)
-        if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R);
-        else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R);
-        else if (kind == NNCA_K_LOG_REG) MF(NNCA_K_LOG_REG);
-        else if (kind == NNCA_K_INV_REG) MF(NNCA_K_INV_REG);
-        else MF(NNCA_K_GAUSS);
+#define MF(K, TSL) k_m2l_mfma<K, NCB, TSL><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc32, L.npiv, L.coord, L.hcell, (float)L.h, H->dim, W.w32[l], W.R, W.u[l], part, prm32)
+#define MFK(TSL) \
+        if (kind == NNCA_K_INV_R) MF(NNCA_K_INV_R, TSL); \
+        else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R, TSL); \
+        else if (kind == NNCA_K_LOG_REG) MF(NNCA_K_LOG_REG, TSL); \
+        else if (kind == NNCA_K_INV_REG) MF(NNCA_K_INV_REG, TSL); \
+        else MF(NNCA_K_GAUSS, TSL);
+        if (tsel) { MFK(1) } else { MFK(0) }
+#undef MFK
 #undef MF
     } else {
 #define VM(K, M) k_m2l_mfma64<K, M, NCB><<<g, NT, 0, s>>>(L.ncell, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, L.pc64, L.npiv, H->dim, W.w[l], W.R, W.u[l], part, prm64)
@@ -873,49 +882,119 @@ void check_part(nnca_h2 *H, int RP, const std::vector<int32_t> *tab)
     auto &W = H->multi;
     for (int l = H->lmin; l <= H->kappa; l++) {
         const Level &L = H->lev[l];
-        const int P = tab ? (*tab)[l] : parts_for(L);
+        const int P = tab ? (*tab)[l] / 2 : parts_for(L);
         if (P > 1 && (int64_t)P * L.npiv * RP > W.part_cap) fail(NNCA_ERR_INTERNAL, "split workspace not sized");
     }
 }
 
 // Autotuner of the transverse pass: for every level, time the launch (and the
 // ordered sum of the partial vectors) for split factors P = 1, 2, 4, ..., 64
-// on the multipole vectors already in place, and keep the fastest.  Factors
-// that leave a part without a full source tile, put more than 2^18
-// workgroups in flight or need more partial vectors than the workspace holds
-// are not tried.
+// and, on the FP32 levels of the mixed form, both tile shapes (the sources
+// per LDS tile of k_m2l_mfma: TSEL 0 or 1), on the multipole vectors already
+// in place, and keep the fastest.  Factors that leave a part without a full
+// source tile, put more than 2^18 workgroups in flight or need more partial
+// vectors than the workspace holds are not tried.  A level's choice is coded
+// as 2 P + TSEL.
+//
+// With NNCA_TUNE_CACHE naming a file, choices are looked up there first and
+// new ones appended to it, one line per level shape:
+//   <arch> m2l <f32|f64> ncb=<NCB> cells=<b> srcs=<b> rank=<b> <2 P + TSEL>
+// where f32 / f64 is the form of the level's launch and each <b> is the
+// ceiling of log2 of the level's cell count, largest source count per cell
+// and largest rank.
+namespace {
+
+std::string tune_key(const Level &L, bool f32form, int ncb)
+{
+    auto bucket = [](int64_t v) {
+        int b = 0;
+        while (((int64_t)1 << b) < v) b++;
+        return b;
+    };
+    hipDeviceProp_t prop;
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    return arch + " m2l " + (f32form ? "f32" : "f64") + " ncb=" + std::to_string(ncb) +
+           " cells=" + std::to_string(bucket(L.ncell)) + " srcs=" + std::to_string(bucket(L.max_ilsum)) +
+           " rank=" + std::to_string(bucket(L.max_k));
+}
+
+std::map<std::string, int32_t> read_tune_cache(const char *path)
+{
+    std::map<std::string, int32_t> m;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return m;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string ln(line);
+        while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+        const size_t sp = ln.rfind(' ');
+        if (sp == std::string::npos) continue;
+        char *end = nullptr;
+        const long v = std::strtol(ln.c_str() + sp + 1, &end, 10);
+        if (end == ln.c_str() + sp + 1 || v < 2 || v > 129) continue;   // 2 P + TSEL, P in 1..64
+        m[ln.substr(0, sp)] = (int32_t)v;
+    }
+    std::fclose(f);
+    return m;
+}
+
+}  // namespace
+
 template <int NCB>
 std::vector<int32_t> tune_m2l_multi(nnca_h2 *H, bool mixed, hipStream_t s)
 {
     constexpr int RP = NCB * 16;
-    std::vector<int32_t> best(H->kappa + 1, 1);
+    std::vector<int32_t> best(H->kappa + 1, 2);
+    const char *cache_path = std::getenv("NNCA_TUNE_CACHE");
+    std::map<std::string, int32_t> cache;
+    if (cache_path && *cache_path) cache = read_tune_cache(cache_path);
+    std::vector<std::string> fresh;
     hipEvent_t a, b;
     HIPCHECK(hipEventCreate(&a));
     HIPCHECK(hipEventCreate(&b));
     try {
         for (int l = H->lmin; l <= H->kappa; l++) {
             const Level &L = H->lev[l];
+            const bool f32form = mixed && l > H->kappa - H->fp32_levels;
+            const std::string key = tune_key(L, f32form, NCB);
+            auto hit = cache.find(key);
+            if (hit != cache.end()) {
+                const int P = hit->second / 2;
+                if (P == 1 || ((int64_t)P * L.npiv * RP <= H->multi.part_cap && (int64_t)P * L.ncell <= (1 << 18))) {
+                    best[l] = hit->second;
+                    continue;
+                }
+            }
             std::vector<int32_t> cand;
             for (int P = 1; P <= 64; P *= 2) {
                 if (P > 1 && (int64_t)P * 128 > L.max_ilsum) break;
                 if ((int64_t)P * L.ncell > (1 << 18)) break;
                 if (P > 1 && (int64_t)P * L.npiv * RP > H->multi.part_cap) break;
-                cand.push_back(P);
+                cand.push_back(2 * P);
+                if (f32form) cand.push_back(2 * P + 1);
             }
             float tbest = 0.f;
-            for (int32_t P : cand) {
-                m2l_level_multi<NCB>(H, l, P, mixed, s);   // warm
+            for (int32_t code : cand) {
+                const int P = code / 2, tsel = code % 2;
+                m2l_level_multi<NCB>(H, l, P, mixed, s, tsel);   // warm
                 HIPCHECK(hipEventRecord(a, s));
-                for (int rep = 0; rep < 3; rep++) m2l_level_multi<NCB>(H, l, P, mixed, s);
+                for (int rep = 0; rep < 3; rep++) m2l_level_multi<NCB>(H, l, P, mixed, s, tsel);
                 HIPCHECK(hipEventRecord(b, s));
                 HIPCHECK(hipEventSynchronize(b));
                 float ms = 0.f;
                 HIPCHECK(hipEventElapsedTime(&ms, a, b));
-                if (P == cand[0] || ms < tbest) {
+                if (code == cand[0] || ms < tbest) {
                     tbest = ms;
-                    best[l] = P;
+                    best[l] = code;
                 }
             }
+            cache[key] = best[l];
+            fresh.push_back(key + " " + std::to_string(best[l]));
         }
     } catch (...) {
         (void)hipEventDestroy(a);
@@ -924,6 +1003,14 @@ std::vector<int32_t> tune_m2l_multi(nnca_h2 *H, bool mixed, hipStream_t s)
     }
     HIPCHECK(hipEventDestroy(a));
     HIPCHECK(hipEventDestroy(b));
+    if (cache_path && *cache_path && !fresh.empty()) {
+        // appended, one line per new level shape; an unwritable file only
+        // means the next process tunes again
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            for (const std::string &ln : fresh) std::fprintf(f, "%s\n", ln.c_str());
+            std::fclose(f);
+        }
+    }
     return best;
 }
 
@@ -978,7 +1065,8 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
         check_part(H, RP, tab);
         for (int l = lmin; l <= kap; l++) {
             Span sp(H, s, PASS_M2L, l);   // the launch and, for split levels, the ordered sum of its parts
-            m2l_level_multi<NCB>(H, l, tab ? (*tab)[l] : parts_for(H->lev[l]), mixed, s);
+            if (tab) m2l_level_multi<NCB>(H, l, (*tab)[l] / 2, mixed, s, (*tab)[l] % 2);
+            else m2l_level_multi<NCB>(H, l, parts_for(H->lev[l]), mixed, s);
         }
         far = W.far;
         for (int l = lmin; l <= kap; l++) {

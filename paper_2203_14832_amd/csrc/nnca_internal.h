@@ -198,8 +198,9 @@ struct nnca_h2 {
         std::vector<float *> w32;     // per level: FP32 copy of w for the FP32 transverse pass
         int R = 0;                    // columns of the block in flight
     } multi;
-    // transverse-pass split factors per level picked by timing (autotune on),
-    // keyed by column-block width and precision
+    // transverse-pass choices per level picked by timing (autotune on): 2 P +
+    // TSEL (split factor, tile shape), keyed by column-block width and
+    // precision
     bool autotune = false;
     std::map<int, std::vector<int32_t>> m2l_tuned;
     int64_t m2l_inter = 0, p2p_inter = 0, transfer_entries = 0;

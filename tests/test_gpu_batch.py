@@ -182,3 +182,38 @@ def test_profile_pass_mask(problems):
     ps, lv, ms = h.profile_read()
     h.profile(False)
     assert {0, 1, 2, 3, 4}.issubset(set(ps.tolist()))
+
+
+def test_autotune_cache_file(problems, tmp_path, monkeypatch):
+    # the first autotuned batch times every level's candidates (split factor,
+    # and the tile shape on the FP32 levels) and appends one line per level
+    # shape to NNCA_TUNE_CACHE; a second batch over the same problems finds
+    # every shape there, appends nothing and gives the same product bit for bit
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("NNCA_TUNE_CACHE", str(path))
+    X = torch.tensor(_stack(problems, 8), device="cuda")
+    B1 = nnca.H2Batch([h for _, _, h in problems], graph=False, autotune=True)
+    Y1 = {prec: B1.matvec(X, prec).cpu().numpy() for prec in ("mixed", "fp64")}
+    B1.close()
+    lines = path.read_text().splitlines()
+    assert lines, "no tuning lines written"
+    for ln in lines:
+        f = ln.split()
+        assert f[1] == "m2l" and f[2] in ("f32", "f64") and f[3].startswith("ncb=")
+        code = int(f[-1])
+        assert 2 <= code <= 129 and (code % 2 == 0 or f[2] == "f32")
+    assert any(ln.split()[2] == "f32" for ln in lines) and any(ln.split()[2] == "f64" for ln in lines)
+    before = path.read_text()
+    B2 = nnca.H2Batch([h for _, _, h in problems], graph=False, autotune=True)
+    Y2 = {prec: B2.matvec(X, prec).cpu().numpy() for prec in ("mixed", "fp64")}
+    B2.close()
+    assert path.read_text() == before
+    for prec in Y1:
+        np.testing.assert_array_equal(Y2[prec], Y1[prec])
+    # against the separate products, as for the default choices
+    sep64 = [h.matvec(torch.tensor(x[:, :8]), "fp64").cpu().numpy() for _, x, h in problems]
+    B3 = nnca.H2Batch([h for _, _, h in problems], graph=False, autotune=False)
+    for b, (y64, ymx) in enumerate(zip(_split(B3, Y1["fp64"]), _split(B3, Y1["mixed"]))):
+        assert rel(y64, sep64[b]) <= 1e-13, b
+        assert rel(ymx, sep64[b]) <= 1e-6, b
+    B3.close()
