@@ -486,6 +486,408 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (t == 0) k_out[cell] = s_over ? -1 : k;
 }
 
+// ----------------------------------------------------------------------------
+// The same ACA spread over many workgroups per cell, for levels whose cells
+// are few and long (the coarse levels: hundreds of cells with 10^4-10^5
+// candidate columns, where one workgroup per cell leaves the chip idle).
+// The cells of a chunk advance in lockstep; each step is five launches:
+//   row    (column segments x cells)  1-2: the residual of row i_k on a
+//          segment of columns, and the segment's argmax over unused columns;
+//   pivot  (cells)  the argmax over the segments; a zero row is marked used
+//          and the smallest unused row taken instead (the step is redone);
+//          else 4: u_k, |u_k|^2, the next row, and u_k . u_l for l < k;
+//   scale  (column segments x cells)  3: v_k = R / R(j_k), zero at used columns;
+//   cross  (groups x cells)  |v_k|^2 and v_l . v_k for l < k;
+//   finish (cells)  5-7: the norm update and the stopping rule.
+// Every column's residual is formed by one thread, every dot product by one
+// workgroup in the fixed shape, and every argmax keeps the larger value and
+// then the smaller index, exactly as in k_aca: the pivots are the same bit
+// for bit.
+
+struct AcaState {
+    int32_t i, k, stop, over, jk, next, retry, pad;
+    double nrm2, piv, ukk, vkk;
+};
+
+constexpr int MSEG = 1024;   // columns per row / scale workgroup (four per thread)
+constexpr int MRW = MSEG / NT;
+
+__global__ __launch_bounds__(NT) void k_acm_init(const AcaCell *cells, int32_t cell0, AcaState *st, uint8_t *flags,
+                                                 int32_t *k_out, int32_t *ipos_cap, int32_t *jid_cap)
+{
+    const AcaCell C = cells[blockIdx.x];
+    const int t = threadIdx.x;
+    const int32_t cell = cell0 + blockIdx.x;
+    AcaState *S = st + blockIdx.x;
+    if (C.whole) {
+        for (int32_t q = t; q < C.m; q += NT) {
+            ipos_cap[C.cap_off + q] = q;
+            jid_cap[C.cap_off + q] = -1;
+        }
+        if (t == 0) {
+            k_out[cell] = C.m;
+            S->stop = 1;
+        }
+        return;
+    }
+    if (C.kcap == 0) {
+        if (t == 0) {
+            k_out[cell] = 0;
+            S->stop = 1;
+        }
+        return;
+    }
+    uint8_t *rf = flags + C.f_off;
+    uint8_t *cf = rf + C.m;
+    for (int32_t r = t; r < C.m; r += NT) rf[r] = 0;
+    for (int32_t j = t; j < C.n; j += NT) cf[j] = 0;
+    if (t == 0) {
+        S->i = 0;
+        S->k = 0;
+        S->stop = 0;
+        S->over = 0;
+        S->jk = INT32_MAX;
+        S->next = INT32_MAX;
+        S->retry = 0;
+        S->nrm2 = 0.0;
+    }
+}
+
+// 1-2 on columns [blockIdx.x MSEG, (blockIdx.x + 1) MSEG) of cell blockIdx.y
+__global__ __launch_bounds__(NT) void k_acm_row(const AcaCell *cells, const AcaState *st, const double *P,
+                                                int64_t np, int d, const int32_t *tsrc, const double *sc,
+                                                int64_t ntot, const double *U, double *V, const uint8_t *flags,
+                                                int kind, double hh, double *segv, int32_t *segi, int32_t nsegmax)
+{
+    const AcaCell C = cells[blockIdx.y];
+    const AcaState S = st[blockIdx.y];
+    const int32_t j0 = blockIdx.x * MSEG;
+    if (C.whole || S.stop || j0 >= C.n) return;   // uniform for the workgroup
+    __shared__ double coef[COEF];
+    __shared__ double sv[NT];
+    __shared__ int32_t si[NT];
+    const int t = threadIdx.x;
+    const int32_t m = C.m, n = C.n, k = S.k, i = S.i;
+    const double *Uc = U + C.u_off;
+    double *Vc = V + C.v_off;
+    const uint8_t *cf = flags + C.f_off + m;
+    const double *sx = sc + C.s_off, *sy = sc + ntot + C.s_off, *sz = sc + 2 * ntot + C.s_off;
+    const int32_t pid = tsrc ? tsrc[C.tt_off + i] : C.tt_off + i;
+    const double ax = P[pid], ay = P[np + pid], az = d == 3 ? P[2 * np + pid] : 0.0;
+    for (int32_t l = t; l < k && l < COEF; l += NT) coef[l] = Uc[(int64_t)l * m + i];
+    __syncthreads();
+    const int32_t j1 = n - j0 < MSEG ? n : j0 + MSEG;
+    const int32_t jb = j0 + t;
+    double r[MRW];
+#pragma unroll
+    for (int c = 0; c < MRW; c++) {
+        const int32_t j = jb + c * NT;
+        r[c] = j < j1 ? kval(kind, hh, d, ax, ay, az, sx[j], sy[j], sz[j]) : 0.0;
+    }
+    if (jb + (MRW - 1) * NT < j1) {
+        int32_t l = 0;
+        for (; l + LA - 1 < k; l += LA) {   // LA rows in flight, updates in ascending l
+            double ul[LA], a[LA][MRW];
+#pragma unroll
+            for (int q = 0; q < LA; q++) {
+                ul[q] = l + q < COEF ? coef[l + q] : Uc[(int64_t)(l + q) * m + i];
+                const double *Vl = Vc + (int64_t)(l + q) * n + jb;
+#pragma unroll
+                for (int c = 0; c < MRW; c++) a[q][c] = Vl[c * NT];
+            }
+#pragma unroll
+            for (int q = 0; q < LA; q++)
+#pragma unroll
+                for (int c = 0; c < MRW; c++) r[c] = r[c] - ul[q] * a[q][c];
+        }
+        for (; l < k; l++) {
+            const double ul = l < COEF ? coef[l] : Uc[(int64_t)l * m + i];
+            const double *Vl = Vc + (int64_t)l * n + jb;
+#pragma unroll
+            for (int c = 0; c < MRW; c++) r[c] = r[c] - ul * Vl[c * NT];
+        }
+    } else {
+        for (int32_t l = 0; l < k; l++) {
+            const double ul = l < COEF ? coef[l] : Uc[(int64_t)l * m + i];
+            const double *Vl = Vc + (int64_t)l * n;
+#pragma unroll
+            for (int c = 0; c < MRW; c++) {
+                const int32_t j = jb + c * NT;
+                if (j < j1) r[c] = r[c] - ul * Vl[j];
+            }
+        }
+    }
+    double best = 0.0;
+    int32_t bj = INT32_MAX;
+    double *Rk = Vc + (int64_t)k * n;
+#pragma unroll
+    for (int c = 0; c < MRW; c++) {
+        const int32_t j = jb + c * NT;
+        if (j < j1) {
+            Rk[j] = r[c];
+            if (!cf[j]) {
+                const double a = fabs(r[c]);
+                if (a > best) { best = a; bj = j; }
+            }
+        }
+    }
+    sv[t] = best;
+    si[t] = bj;
+    __syncthreads();
+    tree_argmax(sv, si, t);
+    if (t == 0) {
+        segv[(int64_t)blockIdx.y * nsegmax + blockIdx.x] = sv[0];
+        segi[(int64_t)blockIdx.y * nsegmax + blockIdx.x] = si[0];
+    }
+}
+
+// the pivot of the step, then 4 (u_k) and the u side of the cross terms
+__global__ __launch_bounds__(NT) void k_acm_pivot(const AcaCell *cells, int32_t cell0, AcaState *st, const double *P,
+                                                  int64_t np, int d, const int32_t *tsrc, const double *sc,
+                                                  int64_t ntot, double *U, const double *V, uint8_t *flags, int kind,
+                                                  double hh, const double *segv, const int32_t *segi,
+                                                  int32_t nsegmax, double *uu, int32_t kcapmax, int32_t *k_out)
+{
+    const AcaCell C = cells[blockIdx.x];
+    AcaState *S = st + blockIdx.x;
+    if (C.whole || S->stop) return;   // uniform
+    __shared__ double sv[NT];
+    __shared__ int32_t si[NT];
+    __shared__ double su2[NT];
+    __shared__ double red[DOTB][NT];
+    __shared__ double coef[COEF];
+    const int t = threadIdx.x;
+    const int32_t m = C.m, n = C.n, k = S->k, i = S->i;
+    double *Uc = U + C.u_off;
+    const double *Vc = V + C.v_off;
+    uint8_t *rf = flags + C.f_off;
+    const int32_t nseg = (n + MSEG - 1) / MSEG;
+    double bv = 0.0;
+    int32_t bi = INT32_MAX;
+    for (int32_t q = t; q < nseg; q += NT) {
+        const double v = segv[(int64_t)blockIdx.x * nsegmax + q];
+        const int32_t ix = segi[(int64_t)blockIdx.x * nsegmax + q];
+        if (v > bv || (v == bv && ix < bi)) { bv = v; bi = ix; }
+    }
+    sv[t] = bv;
+    si[t] = bi;
+    __syncthreads();
+    tree_argmax(sv, si, t);
+    const int32_t jk = si[0];
+    __syncthreads();
+    if (jk == INT32_MAX) {
+        // zero residual row: mark it and continue with the smallest unused row
+        if (t == 0) rf[i] = 1;
+        __syncthreads();
+        int32_t cand = INT32_MAX;
+        for (int32_t r = t; r < m; r += NT)
+            if (!rf[r] && r < cand) cand = r;
+        sv[t] = 0.0;
+        si[t] = cand;
+        __syncthreads();
+        tree_argmax(sv, si, t);
+        if (t == 0) {
+            if (si[0] == INT32_MAX) {
+                S->stop = 1;
+                k_out[cell0 + blockIdx.x] = S->over ? -1 : k;
+            } else {
+                S->i = si[0];
+                S->retry = 1;
+            }
+        }
+        return;
+    }
+    const double *Rk = Vc + (int64_t)k * n;
+    const double piv = Rk[jk];
+    for (int32_t l = t; l < k && l < COEF; l += NT) coef[l] = Vc[(int64_t)l * n + jk];
+    __syncthreads();
+    const double bx = sc[C.s_off + jk], by = sc[ntot + C.s_off + jk], bz = sc[2 * ntot + C.s_off + jk];
+    double *uk = Uc + (int64_t)k * m;
+    double pu = 0.0;
+    double ub = -1.0;
+    int32_t bu = INT32_MAX;
+    for (int32_t r = t; r < m; r += NT) {
+        double u = 0.0;
+        if (!rf[r]) {
+            const int32_t rid = tsrc ? tsrc[C.tt_off + r] : C.tt_off + r;
+            u = kval(kind, hh, d, P[rid], P[np + rid], d == 3 ? P[2 * np + rid] : 0.0, bx, by, bz);
+            int32_t l = 0;
+            for (; l + LU - 1 < k; l += LU) {
+                double vl[LU], a[LU];
+#pragma unroll
+                for (int q = 0; q < LU; q++) {
+                    vl[q] = l + q < COEF ? coef[l + q] : Vc[(int64_t)(l + q) * n + jk];
+                    a[q] = Uc[(int64_t)(l + q) * m + r];
+                }
+#pragma unroll
+                for (int q = 0; q < LU; q++) u = u - vl[q] * a[q];
+            }
+            for (; l < k; l++) {
+                const double vl = l < COEF ? coef[l] : Vc[(int64_t)l * n + jk];
+                u = u - vl * Uc[(int64_t)l * m + r];
+            }
+        }
+        uk[r] = u;
+        pu = pu + u * u;
+        if (!rf[r] && r != i) {
+            const double a = fabs(u);
+            if (a > ub) { ub = a; bu = r; }
+        }
+    }
+    su2[t] = pu;
+    sv[t] = ub;
+    si[t] = bu;
+    __syncthreads();
+    for (int st2 = NT / 2; st2 > 0; st2 >>= 1) {
+        if (t < st2) {
+            su2[t] = su2[t] + su2[t + st2];
+            const double a = sv[t], b = sv[t + st2];
+            const int32_t ia = si[t], ib = si[t + st2];
+            if (b > a || (b == a && ib < ia)) { sv[t] = b; si[t] = ib; }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        S->jk = jk;
+        S->piv = piv;
+        S->ukk = su2[0];
+        S->next = si[0];
+    }
+    // u_k . u_l for l < k, DOTB at a time
+    double *uuc = uu + (int64_t)blockIdx.x * kcapmax;
+    for (int32_t lb = 0; lb < k; lb += DOTB) {
+        const int nbat = k - lb < DOTB ? k - lb : DOTB;
+        double au[DOTB];
+#pragma unroll
+        for (int q = 0; q < DOTB; q++) au[q] = 0.0;
+        for (int32_t r = t; r < m; r += NT) {
+            const double x = uk[r];
+#pragma unroll
+            for (int q = 0; q < DOTB; q++)
+                if (q < nbat) au[q] = au[q] + x * Uc[(int64_t)(lb + q) * m + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < DOTB; q++) red[q][t] = au[q];
+        __syncthreads();
+        for (int st2 = NT / 2; st2 > 0; st2 >>= 1) {
+            if (t < st2)
+                for (int q = 0; q < nbat; q++) red[q][t] = red[q][t] + red[q][t + st2];
+            __syncthreads();
+        }
+        if (t < nbat) uuc[lb + t] = red[t][0];
+    }
+}
+
+// 3: v_k on a segment of columns
+__global__ __launch_bounds__(NT) void k_acm_scale(const AcaCell *cells, const AcaState *st, double *V,
+                                                  const uint8_t *flags)
+{
+    const AcaCell C = cells[blockIdx.y];
+    const AcaState S = st[blockIdx.y];
+    const int32_t j0 = blockIdx.x * MSEG;
+    if (C.whole || S.stop || S.retry || j0 >= C.n) return;
+    const int32_t n = C.n;
+    const uint8_t *cf = flags + C.f_off + C.m;
+    double *Rk = V + C.v_off + (int64_t)S.k * n;
+    const double piv = S.piv;
+    const int32_t j1 = n - j0 < MSEG ? n : j0 + MSEG;
+    for (int32_t j = j0 + threadIdx.x; j < j1; j += NT) Rk[j] = cf[j] ? 0.0 : Rk[j] / piv;
+}
+
+// group 0: |v_k|^2; group g > 0: v_l . v_k for l in [(g - 1) DOTB, g DOTB) below k
+__global__ __launch_bounds__(NT) void k_acm_cross(const AcaCell *cells, AcaState *st, const double *V, double *vv,
+                                                  int32_t kcapmax)
+{
+    const AcaCell C = cells[blockIdx.y];
+    AcaState *S = st + blockIdx.y;
+    const int32_t k = S->k;
+    const int32_t lb = ((int32_t)blockIdx.x - 1) * DOTB;
+    if (C.whole || S->stop || S->retry || (blockIdx.x > 0 && lb >= k)) return;
+    __shared__ double red[DOTB][NT];
+    const int t = threadIdx.x;
+    const int32_t n = C.n;
+    const double *Vc = V + C.v_off;
+    const double *vk = Vc + (int64_t)k * n;
+    if (blockIdx.x == 0) {
+        double pv = 0.0;
+        for (int32_t j = t; j < n; j += NT) {
+            const double v = vk[j];
+            pv = pv + v * v;
+        }
+        red[0][t] = pv;
+        __syncthreads();
+        for (int st2 = NT / 2; st2 > 0; st2 >>= 1) {
+            if (t < st2) red[0][t] = red[0][t] + red[0][t + st2];
+            __syncthreads();
+        }
+        if (t == 0) S->vkk = red[0][0];
+        return;
+    }
+    const int nbat = k - lb < DOTB ? k - lb : DOTB;
+    double av[DOTB];
+#pragma unroll
+    for (int q = 0; q < DOTB; q++) av[q] = 0.0;
+    for (int32_t j = t; j < n; j += NT) {
+        const double x = vk[j];
+#pragma unroll
+        for (int q = 0; q < DOTB; q++)
+            if (q < nbat) av[q] = av[q] + Vc[(int64_t)(lb + q) * n + j] * x;
+    }
+#pragma unroll
+    for (int q = 0; q < DOTB; q++) red[q][t] = av[q];
+    __syncthreads();
+    for (int st2 = NT / 2; st2 > 0; st2 >>= 1) {
+        if (t < st2)
+            for (int q = 0; q < nbat; q++) red[q][t] = red[q][t] + red[q][t + st2];
+        __syncthreads();
+    }
+    if (t < nbat) vv[(int64_t)blockIdx.y * kcapmax + lb + t] = red[t][0];
+}
+
+// 5-7 (one thread per cell)
+__global__ void k_acm_finish(int32_t cn, const AcaCell *cells, int32_t cell0, AcaState *st, const int32_t *sid,
+                             uint8_t *flags, const double *uu, const double *vv, int32_t kcapmax, double tol,
+                             int32_t *k_out, int32_t *ipos_cap, int32_t *jid_cap)
+{
+    const int32_t cb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cb >= cn) return;
+    const AcaCell C = cells[cb];
+    AcaState *S = st + cb;
+    if (C.whole || S->stop) return;
+    if (S->retry) {
+        S->retry = 0;
+        return;
+    }
+    const int32_t k = S->k, i = S->i, jk = S->jk;
+    const double *uuc = uu + (int64_t)cb * kcapmax, *vvc = vv + (int64_t)cb * kcapmax;
+    double s = 0.0;
+    for (int32_t l = 0; l < k; l++) s = s + uuc[l] * vvc[l];
+    const double ukk = S->ukk, vkk = S->vkk;
+    double nrm2 = (S->nrm2 + 2.0 * s) + ukk * vkk;
+    if (nrm2 < 0.0) nrm2 = 0.0;
+    S->nrm2 = nrm2;
+    ipos_cap[C.cap_off + k] = i;
+    jid_cap[C.cap_off + k] = sid[C.s_off + jk];
+    uint8_t *rf = flags + C.f_off;
+    rf[i] = 1;
+    rf[C.m + jk] = 1;
+    const int32_t kn = k + 1, next = S->next;
+    const bool conv = sqrt(ukk) * sqrt(vkk) <= tol * sqrt(nrm2);
+    const int stop = conv || kn >= C.kcap || next == INT32_MAX;
+    if (!conv && next != INT32_MAX && kn >= C.kcap && C.kcap < C.kfull) S->over = 1;
+    S->k = kn;
+    S->i = next;
+    S->stop = stop;
+    if (stop) k_out[cell0 + cb] = S->over ? -1 : kn;
+}
+
+__global__ void k_acm_active(int32_t cn, const AcaState *st, int32_t *cnt)
+{
+    const int32_t cb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cb < cn && !st[cb].stop) atomicAdd(cnt, 1);
+}
+
 // Transfer operator C_B = U L^{-1}, L = U(I, :) (Remark in Sec. 2.3.2).  The
 // pivot rows of C_B are the identity and are not stored; every other row x
 // solves x L = U(r, :) from the last column down:
@@ -595,6 +997,71 @@ struct Half {
     const double *pts;   // 3 x n, this half's tree order
     int64_t n;
 };
+
+// Levels with fewer cells than this run the ACA spread over many workgroups
+// per cell (k_acm_*): there one workgroup per cell would leave most of the
+// chip idle while it waits on its panel loads.
+constexpr int64_t ACA_SPREAD_BELOW = 8192;
+
+// The steps of the spread ACA for the cells [c0, c1) of a chunk, in lockstep
+// until every cell has stopped.
+static void aca_spread(nnca_h2 *H, const AcaCell *dcells, const std::vector<AcaCell> &hc, int64_t c0, int64_t c1,
+                       const Half &own, const int32_t *tsrc, const int32_t *sid, const double *sc,
+                       int64_t ntot, double *U, double *V, uint8_t *fl, int32_t *k_out, int32_t *ipos_cap,
+                       int32_t *jid_cap)
+{
+    hipStream_t s = H->stream;
+    const int32_t cn = (int32_t)(c1 - c0);
+    int32_t nsegmax = 1, kcapmax = 1, mmax = 1;
+    for (int64_t c = c0; c < c1; c++) {
+        if (hc[c].whole) continue;
+        nsegmax = std::max(nsegmax, (hc[c].n + MSEG - 1) / MSEG);
+        kcapmax = std::max(kcapmax, hc[c].kcap);
+        mmax = std::max(mmax, hc[c].m);
+    }
+    AcaState *st = dalloc<AcaState>(cn);
+    double *segv = dalloc<double>((size_t)cn * nsegmax);
+    int32_t *segi = dalloc<int32_t>((size_t)cn * nsegmax);
+    double *uu = dalloc<double>((size_t)cn * kcapmax);
+    double *vv = dalloc<double>((size_t)cn * kcapmax);
+    int32_t *cnt = dalloc<int32_t>(1);
+    const double hh = aca_param(H->kind, H->hparam);
+    try {
+        k_acm_init<<<cn, NT, 0, s>>>(dcells, (int32_t)c0, st, fl, k_out, ipos_cap, jid_cap);
+        HIPCHECK(hipGetLastError());
+        // every step advances k or uses up a row of the cell: at most m + kcap steps
+        const int64_t max_steps = (int64_t)mmax + kcapmax + 2;
+        for (int64_t step = 0;; step++) {
+            k_acm_row<<<dim3(nsegmax, cn), NT, 0, s>>>(dcells, st, own.pts, own.n, H->dim, tsrc, sc, ntot, U, V, fl,
+                                                      H->kind, hh, segv, segi, nsegmax);
+            k_acm_pivot<<<cn, NT, 0, s>>>(dcells, (int32_t)c0, st, own.pts, own.n, H->dim, tsrc, sc, ntot, U, V, fl,
+                                          H->kind, hh, segv, segi, nsegmax, uu, kcapmax, k_out);
+            k_acm_scale<<<dim3(nsegmax, cn), NT, 0, s>>>(dcells, st, V, fl);
+            const int64_t kbound = std::min<int64_t>(step, kcapmax);   // k <= step
+            const unsigned ngrp = (unsigned)(1 + (kbound + DOTB - 1) / DOTB);
+            k_acm_cross<<<dim3(ngrp, cn), NT, 0, s>>>(dcells, st, V, vv, kcapmax);
+            k_acm_finish<<<grid_for(cn, 64), 64, 0, s>>>(cn, dcells, (int32_t)c0, st, sid, fl, uu, vv, kcapmax,
+                                                         H->tol, k_out, ipos_cap, jid_cap);
+            HIPCHECK(hipGetLastError());
+            if (step % 8 == 7 || step >= max_steps) {
+                int32_t h = 0;
+                HIPCHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+                k_acm_active<<<grid_for(cn, 256), 256, 0, s>>>(cn, st, cnt);
+                HIPCHECK(hipGetLastError());
+                HIPCHECK(hipMemcpyAsync(&h, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipStreamSynchronize(s));
+                if (h == 0) break;
+                if (step >= max_steps) fail(NNCA_ERR_INTERNAL, "spread ACA did not stop");
+            }
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        dfree(st); dfree(segv); dfree(segi); dfree(uu); dfree(vv); dfree(cnt);
+        throw;
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(st); dfree(segv); dfree(segi); dfree(uu); dfree(vv); dfree(cnt);
+}
 
 // step 1 of Sec. 2.3.2 for one half: m_B and the start of t~
 static void level_sizes(nnca_h2 *H, std::vector<Level> &lv, int l)
@@ -711,8 +1178,11 @@ static void build_level(nnca_h2 *H, int l, const Half &own, const Half &far)
         k_gather_cand<<<(int)cn, 256, 0, s>>>(dcells, (int32_t)c0, L.il_ptr, L.il, Lf.m, Lf.tt_off, ftsrc, far.pts,
                                               far.n, H->dim, sid, sc, so);
         HIPCHECK(hipGetLastError());
-        k_aca<<<(int)cn, NT, 0, s>>>(dcells, (int32_t)c0, own.pts, own.n, H->dim, tsrc, sid, sc, so, U, V, fl,
-                                     H->kind, aca_param(H->kind, H->hparam), H->tol, L.k, ipos_cap, jid_cap);
+        if (nc < ACA_SPREAD_BELOW)
+            aca_spread(H, dcells, hc, c0, c1, own, tsrc, sid, sc, so, U, V, fl, L.k, ipos_cap, jid_cap);
+        else
+            k_aca<<<(int)cn, NT, 0, s>>>(dcells, (int32_t)c0, own.pts, own.n, H->dim, tsrc, sid, sc, so, U, V, fl,
+                                         H->kind, aca_param(H->kind, H->hparam), H->tol, L.k, ipos_cap, jid_cap);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(hk.data() + c0, L.k + c0, sizeof(int32_t) * cn, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
