@@ -159,6 +159,7 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = H.info()
+    bst = H.build_stats()
     inter = info["m2l_interactions"] + info["p2p_interactions"]
     print(f"[bench] built N={n} kappa={info['kappa']} in {build_s:.2f}s, "
           f"M2L {info['m2l_interactions']:.3e} + P2P {info['p2p_interactions']:.3e} interactions",
@@ -275,6 +276,14 @@ def main():
         "speedup_vs_fp64_plain_pass": fp64_plain_ms / ms_nosym,
         "speedup_mixed_vs_fp64_plain_pass": fp64_plain_ms / ms_step,
         "err_mixed_vs_fp64": err_mixed, "build_seconds": build_s, "pass_ms_per_step": breakdown,
+        # the build's pivot traversal against HBM: its algorithmic panel reads
+        # (step k of a cell's ACA reads the k previous panel rows twice) over
+        # its time
+        "build_roofline": {"bound": "hbm", "kernel": "k_aca / k_acm_* (pivot traversal, FP64)",
+                           "achieved": bst["aca_panel_bytes"] / bst["aca_seconds"] / 1e9, "peak": 8000.0,
+                           "unit": "GB/s", "frac": bst["aca_panel_bytes"] / bst["aca_seconds"] / 8e12,
+                           "aca_seconds": bst["aca_seconds"], "panel_bytes": bst["aca_panel_bytes"],
+                           "build_seconds_library": bst["build_seconds"]},
         "interactions_per_step": inter, "ms_per_step_without_events": ms_plain,
     }
     # attainable rates measured on this device (copy, FMA, rsq, and the

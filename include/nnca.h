@@ -318,6 +318,16 @@ typedef struct {
 /* Structure and statistics of a handle (blocking). */
 nnca_status nnca_query(nnca_handle h, nnca_info *info);
 
+/* Timing of the build (host pointer out, the first `count` of, at most 3):
+ *   out[0]  seconds of the whole build (nnca_build / nnca_build_general);
+ *   out[1]  seconds of its pivot traversal (the ACAs of Sec. 2.3.2 and the
+ *           transfer operators);
+ *   out[2]  the traversal's algorithmic panel reads in bytes: step k of a
+ *           cell's ACA reads the k previous rows of its n-column panel twice
+ *           (row residual, norm update), sum over ACA cells of k (k - 1) n 8.
+ * Errors: INVALID_ARG (NULL handle or out, count < 1).                    */
+nnca_status nnca_query_build(nnca_handle h, double *out, int32_t count);
+
 /* Parity exports (blocking; all output buffers are host memory sized by the
  * caller from nnca_query).
  *   order[n]: original index of each tree-order position.

@@ -1243,6 +1243,10 @@ static void build_level(nnca_h2 *H, int l, const Half &own, const Half &far)
         L.max_nrem = std::max(L.max_nrem, nr);
     }
     L.h_k = hk;
+    // algorithmic panel traffic: step k of a cell reads its k V rows of n
+    // entries twice (row residual, cross terms)
+    for (int64_t c = 0; c < nc; c++)
+        if (!hc[c].whole) H->aca_panel_bytes += (double)hk[c] * (double)(hk[c] - 1) * (double)hc[c].n * 8.0;
     L.max_k = kmx;
     L.npiv = pp[nc];
     L.ncrem = cpp[nc];

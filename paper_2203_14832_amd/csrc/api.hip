@@ -317,7 +317,13 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
                 HIPCHECK(hipStreamSynchronize(H->stream));
                 dfree(pin);
             }
-            build_pivots(H);
+            {
+                HIPCHECK(hipStreamSynchronize(H->stream));
+                const auto ta = std::chrono::steady_clock::now();
+                build_pivots(H);
+                HIPCHECK(hipStreamSynchronize(H->stream));
+                H->aca_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ta).count();
+            }
             prepare_apply(H);
             HIPCHECK(hipEventCreateWithFlags(&H->ev_done, hipEventDisableTiming));
             HIPCHECK(hipStreamSynchronize(H->stream));
@@ -363,7 +369,13 @@ nnca_status nnca_build_general(const double *targets, int64_t np, int64_t ldp, c
             }
             HIPCHECK(hipStreamSynchronize(H->stream));
             dfree(Z);
-            build_pivots(H);
+            {
+                HIPCHECK(hipStreamSynchronize(H->stream));
+                const auto ta = std::chrono::steady_clock::now();
+                build_pivots(H);
+                HIPCHECK(hipStreamSynchronize(H->stream));
+                H->aca_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ta).count();
+            }
             prepare_general(H);
             HIPCHECK(hipEventCreateWithFlags(&H->ev_done, hipEventDisableTiming));
             HIPCHECK(hipStreamSynchronize(H->stream));
@@ -554,6 +566,15 @@ nnca_status nnca_query(nnca_handle h, nnca_info *info)
         info->build_seconds = h->build_seconds;
         info->mixed_fp32_levels = h->fp32_levels;
         info->mixed_near_symmetric = h->p2p_sym ? 1 : 0;
+    });
+}
+
+nnca_status nnca_query_build(nnca_handle h, double *out, int32_t count)
+{
+    return guarded([&] {
+        if (!h || !out || count < 1) fail(NNCA_ERR_INVALID_ARG, "NULL argument or count < 1");
+        const double v[3] = {h->build_seconds, h->aca_seconds, h->aca_panel_bytes};
+        for (int32_t q = 0; q < count && q < 3; q++) out[q] = v[q];
     });
 }
 

@@ -141,6 +141,8 @@ struct nnca_h2 {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_leafk = nullptr;           // after the leaf level's transverse kernel
     double build_seconds = 0.0;
+    double aca_seconds = 0.0;     // the pivot traversal (ACA and transfer operators) of the build
+    double aca_panel_bytes = 0.0; // its algorithmic panel reads: sum over ACA cells of k (k - 1) n 8 bytes
 
     // General case P != Q (Sec. 2.1, 2.3): n is |P| (the rows), nq = |Q| (the
     // columns).  lev holds the incoming half of every cell (targets: first /

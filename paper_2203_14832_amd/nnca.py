@@ -137,6 +137,7 @@ def lib():
             "nnca_gmres": [P, f64, f64, P, P, f64, i32, i32, i32, P, P, P],
             "nnca_build_general": [P, i64, i64, P, i64, i64, i32, i32, i32, f64, f64, i32, P, P, P],
             "nnca_query_shape": [P, P, P, P],
+            "nnca_query_build": [P, P, i32],
             "nnca_export_half": [P, i32, i32, P, P, P],
             "nnca_export_half_operator": [P, i32, i32, i64, P, i64, P, P],
         }
@@ -326,6 +327,13 @@ class H2Matrix:
         _check(lib().nnca_profile_read(self._h, C.byref(cnt), _np_ptr(ps), _np_ptr(lv), _np_ptr(ms), cap))
         k = min(cnt.value, cap)
         return ps[:k].copy(), lv[:k].copy(), ms[:k].copy()
+
+    def build_stats(self) -> dict:
+        """Build seconds, pivot-traversal seconds and its algorithmic panel
+        bytes (``nnca_query_build``)."""
+        out = np.zeros(3)
+        _check(lib().nnca_query_build(self._h, _np_ptr(out), 3))
+        return dict(build_seconds=float(out[0]), aca_seconds=float(out[1]), aca_panel_bytes=float(out[2]))
 
     def info(self) -> dict:
         inf = Info()

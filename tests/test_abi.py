@@ -87,6 +87,7 @@ def test_general_build_invalid_arguments(lib):
     assert bg(P, 10, 10, Q, 12, 12, kind=3, hh=0.0) == 1
     assert not h.value
     assert lib.nnca_query_shape(None, None, None, None) == 1
+    assert lib.nnca_query_build(None, None, 3) == 1
     assert lib.nnca_export_half(None, 0, 0, None, None, None) == 1
     assert lib.nnca_export_half_operator(None, 0, 0, 0, None, 0, None, None) == 1
 
