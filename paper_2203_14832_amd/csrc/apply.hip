@@ -1059,10 +1059,14 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
     launch_m2l_pair<MODE, C>(kind, H, L, L, pc, pc, prm, s, after);
 }
 
-// split factor of the symmetric pass: as for the plain pass, on the owned sources
+// split factor of the symmetric pass, on the owned sources: enough
+// workgroups for about 16384 per level (four per cell at level kappa-1 of
+// the 2^20 cube, whose 4096 cells vary in work: 0.80 against 0.89-0.91 ms
+// unsplit; the leaf level's 32768 cells run unsplit, a split of two made it
+// slower, 0.94 against 0.86 ms)
 static int sym_parts(const nnca::Level &L)
 {
-    const int64_t want = 4096;
+    const int64_t want = 16384;
     if (L.ncell >= want) return 1;
     int64_t P = (want + L.ncell - 1) / L.ncell;
     int64_t maxp = (L.max_own + 1023) / 1024;
