@@ -1007,10 +1007,13 @@ __global__ void k_m2l_gather(int64_t npiv, const int32_t *piv_cell, const int32_
 // Sources per LDS tile: long inner loops also for cells with few targets.
 constexpr int M2L_TILE = 4 * NT;
 
-// Split factor: enough workgroups to fill the chip on levels with few cells.
+// Split factor: enough workgroups to fill the chip on levels with few cells
+// and to even out cells of unequal work, about 16384 per level (the plain
+// pass at 2^20 points: mixed 3.97 against 4.21 ms per matvec with 4096, FP64
+// 17.7 against 18.4 ms; the general product likewise)
 static int m2l_parts(const nnca::Level &L)
 {
-    const int64_t want = 4096;
+    const int64_t want = 16384;
     if (L.ncell >= want) return 1;
     int64_t P = (want + L.ncell - 1) / L.ncell;
     int64_t maxp = (L.max_ilsum + 1023) / 1024;   // keep at least ~1k sources per part
