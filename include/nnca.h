@@ -63,7 +63,9 @@ typedef enum {
     NNCA_K_INV_R = 2,   /* 1/r                                            */
     NNCA_K_GAUSS = 3,   /* exp(-r^2 / h^2), h = length_scale > 0          */
     NNCA_K_LOG_REG = 4, /* regularised log r, a = length_scale, 2D only   */
-    NNCA_K_INV_REG = 5  /* regularised 1/r, a = length_scale              */
+    NNCA_K_INV_REG = 5, /* regularised 1/r, a = length_scale              */
+    NNCA_K_EXP_R = 6    /* exp(-r / h), h = length_scale > 0 (the "Matern"
+                           kernel of Exp. 6); 1 at r = 0                  */
 } nnca_kernel_kind;
 
 /* Arithmetic of a matvec.
@@ -146,7 +148,8 @@ nnca_status nnca_build(const double *points, int64_t n, int32_t dim, int64_t ld,
  * rows to nq.  Both precisions and dtypes are supported; the transverse pass
  * and the near field evaluate every ordered pair of cells (there is no
  * symmetric form).  nnca_matvec_noalloc, nnca_matvec_backward,
- * nnca_batch_create and nnca_gmres return NOT_SUPPORTED for it.
+ * nnca_batch_create, nnca_gmres and nnca_svm_train return NOT_SUPPORTED for
+ * it.
  * Other arguments and errors as nnca_build; INVALID_ARG also for np or nq
  * < 1 or np + nq > 2^30.                                                  */
 nnca_status nnca_build_general(const double *targets, int64_t np, int64_t ldp, const double *sources,
@@ -398,6 +401,49 @@ nnca_status nnca_profile_read(nnca_handle h, int64_t *count, int32_t *pass, int3
 nnca_status nnca_gmres(nnca_handle h, double alpha, double beta, const double *F, double *X, double tol,
                        int32_t max_iter, int32_t restart, int32_t precision, int32_t *iters, double *relres,
                        void *stream);
+
+/* Kernel SVM training of Exp. 6 (Sec. 5) on a handle of nnca_build over the
+ * N training points: gradient ascent on the penalised dual
+ *   L(a) = sum a_i - 1/2 sum_ij K(x_i, x_j) y_i y_j a_i a_j - beta/2 (sum_j a_j y_j)^2,
+ * whose gradient is 1 - y .* (K~ v) - beta sum(v) y with v = y .* a and K~ the
+ * H2 operator of the handle (one nnca_matvec per step).  Each step is
+ *   a <- min(max(a + eta grad, 0), lambda)
+ * (the box 0 <= a <= lambda of the dual enforced by projection).
+ * y: device, N labels in the original point order (+1 / -1; other values
+ * are taken as given).  alpha: device, N entries, the initial iterate on
+ * entry (usually zeros), the last iterate on return; must not overlap y.
+ * lambda > 0 (the box bound), beta >= 0 (the penalty of the equality
+ * constraint sum a_i y_i = 0).  eta > 0 is the step; eta <= 0 picks
+ * 1 / (||K~||_2 + beta N) with ||K~||_2 from 30 power steps on K~ started
+ * at the normalised all-ones vector (a step no longer than 1 / Lipschitz
+ * constant of the gradient, so each step does not decrease L).  The loop
+ * stops after max_iter steps or at the first step with
+ * ||a_new - a||_2 <= tol ||a_new||_2 (||a_new|| read as 1 when it is 0).
+ * Host outputs (may be NULL): *iters = steps taken, *eta_used = the step,
+ * *bias = the mean of y_i - (K~ v)_i over the free support vectors
+ * (0 < a_i < lambda) of the final iterate, 0 if there are none.  The
+ * precision (an nnca_precision) is that of every matvec.  Reductions have
+ * a fixed shape, so the iterates repeat bit for bit run to run.  Blocks
+ * until done; allocates device scratch of 2N + 1026 doubles.
+ * Errors: INVALID_ARG (NULL handle or vectors, overlap, lambda not > 0,
+ * beta < 0, non-finite eta, tol < 0, max_iter < 0, bad precision);
+ * NOT_SUPPORTED (a handle of nnca_build_general); NUMERICAL (power steps
+ * with ||K~ u|| = 0); OUT_OF_MEMORY; HIP.                                 */
+nnca_status nnca_svm_train(nnca_handle h, const double *y, double *alpha, double lambda, double beta, double eta,
+                           double tol, int32_t max_iter, int32_t precision, int32_t *iters, double *bias,
+                           double *eta_used, void *stream);
+
+/* The SVM decision function of Exp. 6, f(x) = sum_i a_i y_i K(x_i, x) + bias,
+ * at the rows of the handle: on a handle of nnca_build_general(targets =
+ * the new points, sources = the training points) y and alpha have nq
+ * entries and f has np; on a handle of nnca_build f is taken at the
+ * training points (n entries each).  Device vectors in the original point
+ * order; f must not overlap y or alpha.  The label is sgn f.  Blocks until
+ * done; allocates nq doubles of scratch.
+ * Errors: INVALID_ARG (NULL handle or vectors, overlap, non-finite bias,
+ * bad precision); OUT_OF_MEMORY; HIP.                                     */
+nnca_status nnca_svm_decision(nnca_handle h, const double *y, const double *alpha, double bias, double *f,
+                              int32_t precision, void *stream);
 
 /* Attainable rates on the current device, for the rooflines of the apply
  * passes (blocking; allocates and frees 512 MiB of workspace):

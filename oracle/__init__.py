@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nnca_oracle.c")
 _LIB = os.path.join(_HERE, "libnnca_oracle.so")
 
-KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "log_reg": 4, "inv_reg": 5, "poly2": 99}
+KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "log_reg": 4, "inv_reg": 5, "exp_r": 6, "poly2": 99}
 
 
 def build(force: bool = True) -> str:
@@ -464,3 +464,68 @@ def gmres(apply, f, tol: float = 1e-10, max_iter: int = 500, restart: int = 50, 
         x = x + V[:j].T @ y
         if done or it >= max_iter:
             return x, it, np.linalg.norm(f - apply(x)) / fn
+
+
+def svm_objective(K, y, alpha, beta: float) -> float:
+    """The penalised SVM dual L(alpha) of Exp. 6 (Sec. 5) from a dense kernel
+    matrix: the sum of alpha, minus half the quadratic form of K with the
+    signed weights y * alpha, minus half of beta times the squared constraint
+    residual sum(alpha * y)."""
+    v = np.asarray(y, dtype=np.float64) * np.asarray(alpha, dtype=np.float64)
+    return float(np.sum(alpha) - 0.5 * (v @ (K @ v)) - 0.5 * beta * np.sum(v) ** 2)
+
+
+def svm_step_size(apply, n: int, beta: float, steps: int = 30) -> float:
+    """The gradient-ascent step 1 / (||K||_2 + beta n): ||K||_2 by `steps`
+    power-method steps on the symmetric positive definite K, started at the
+    normalised all-ones vector (beta n bounds the penalty's Hessian beta y
+    y^T for labels of modulus 1)."""
+    u = np.full(n, 1.0 / np.sqrt(n))
+    lam = 0.0
+    for _ in range(steps):
+        w = apply(u)
+        lam = float(np.linalg.norm(w))
+        if not lam > 0.0:
+            raise ValueError("the kernel matrix has no positive norm")
+        u = w / lam
+    return 1.0 / (lam + beta * n)
+
+
+def svm_train(apply, y, lam: float = 1.0, beta: float = 1.0, eta: float = 0.0, tol: float = 1e-8,
+              max_iter: int = 1000, alpha0=None):
+    """Kernel SVM training of Exp. 6 (Sec. 5): gradient ascent on the
+    penalised dual, alpha <- alpha + eta dL/dalpha with the gradient in the
+    paper's vector form 1 - y .* (K v) - beta sum(v) y, v = y .* alpha, each
+    step followed by the projection onto the box 0 <= alpha <= lam.  K v is
+    `apply(v)`.  eta <= 0 takes svm_step_size.  Stops after max_iter steps or
+    at the first step with ||alpha_new - alpha|| <= tol ||alpha_new|| (||.||
+    read as 1 when alpha_new = 0).  Returns (alpha, bias, steps, eta); the
+    bias is the mean of y_i - (K v)_i over the free support vectors 0 <
+    alpha_i < lam of the final iterate (0 when there are none)."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    if not eta > 0.0:
+        eta = svm_step_size(apply, n, beta)
+    a = np.zeros(n) if alpha0 is None else np.array(alpha0, dtype=np.float64)
+    it = 0
+    while it < max_iter:
+        v = y * a
+        g = 1.0 - y * apply(v) - beta * np.sum(v) * y
+        an = np.clip(a + eta * g, 0.0, lam)
+        dn = np.linalg.norm(an - a)
+        nn = np.linalg.norm(an)
+        a = an
+        it += 1
+        if dn <= tol * (nn if nn > 0.0 else 1.0):
+            break
+    kv = apply(y * a)
+    free = (a > 0.0) & (a < lam)
+    b = float(np.mean(y[free] - kv[free])) if free.any() else 0.0
+    return a, b, it, eta
+
+
+def svm_decision(apply, y, alpha, bias: float):
+    """The SVM decision function of Exp. 6, f(x) = sum_i alpha_i y_i K(x_i, x)
+    + b, at the points where `apply` evaluates the kernel sums over the
+    training points; the label is sgn f."""
+    return apply(np.asarray(y, dtype=np.float64) * np.asarray(alpha, dtype=np.float64)) + bias

@@ -118,7 +118,7 @@ static double dist2(const double *a, const double *b, int d)
 
 /* The kernel K(x, y) used inside the method (build and apply).
  * 1/r and log r are set to zero at r = 0 ("zero on the diagonal");
- * the Gaussian exp(-r^2/h^2) is 1 there.  ORC_K_POLY2 = (1 + x.y)^2 is a
+ * the Gaussian exp(-r^2/h^2) and exp(-r/h) are 1 there.  ORC_K_POLY2 = (1 + x.y)^2 is a
  * test kernel of known rank used only to pin the ACA.                       */
 static double kern(int kind, double hparam, const double *a, const double *b, int d)
 {
@@ -134,6 +134,10 @@ static double kern(int kind, double hparam, const double *a, const double *b, in
     case ORC_K_GAUSS: {
         double d2 = dist2(a, b, d);
         return orc_exp(-(d2 / (hparam * hparam)));
+    }
+    case ORC_K_EXP_R: {     /* Exp. 6 ("Matern"): exp(-r/h), 1 at r = 0; hparam = h */
+        double d2 = dist2(a, b, d);
+        return orc_exp(-(sqrt(d2) / hparam));
     }
     case ORC_K_INV_REG: {   /* Exp. 1-4: r/a for r < a, a/r for r >= a; hparam = a */
         double d2 = dist2(a, b, d);
@@ -166,6 +170,7 @@ static double kern_ref(int kind, double hparam, const double *a, const double *b
     case ORC_K_INV_R: return d2 == 0.0 ? 0.0 : 1.0 / sqrt(d2);
     case ORC_K_LOG_R: return d2 == 0.0 ? 0.0 : log(sqrt(d2));
     case ORC_K_GAUSS: return exp(-d2 / (hparam * hparam));
+    case ORC_K_EXP_R: return exp(-sqrt(d2) / hparam);
     case ORC_K_INV_REG: {
         double r = sqrt(d2), a0 = hparam;
         if (r == 0.0) return 0.0;

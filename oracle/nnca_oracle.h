@@ -8,7 +8,7 @@
 #define NNCA_ORACLE_H
 #include <stdint.h>
 
-enum { ORC_K_LOG_R = 1, ORC_K_INV_R = 2, ORC_K_GAUSS = 3, ORC_K_LOG_REG = 4, ORC_K_INV_REG = 5, ORC_K_POLY2 = 99 };
+enum { ORC_K_LOG_R = 1, ORC_K_INV_R = 2, ORC_K_GAUSS = 3, ORC_K_LOG_REG = 4, ORC_K_INV_REG = 5, ORC_K_EXP_R = 6, ORC_K_POLY2 = 99 };
 
 typedef struct orc_tree orc_tree;
 typedef struct orc_h2 orc_h2;

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnnca.so")
-SOURCES = ["api.hip", "tree.hip", "aca.hip", "apply.hip", "apply_multi.hip", "grad.hip", "batch.hip", "noalloc.hip", "probe.hip", "gmres.hip"]
+SOURCES = ["api.hip", "tree.hip", "aca.hip", "apply.hip", "apply_multi.hip", "grad.hip", "batch.hip", "noalloc.hip", "probe.hip", "gmres.hip", "svm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("NNCA_ARCH", "gfx950")
 

@@ -116,6 +116,7 @@ __device__ inline double kval(int kind, double hh, int d, double ax, double ay, 
         const double la = dlog(hh);
         return s >= hh * hh ? (0.5 * dlog(s)) / la : (sqrt(s) * (0.5 * dlog(s) - 1.0)) / (hh * (la - 1.0));
     }
+    if (kind == NNCA_K_EXP_R) return dexp(-(sqrt(s) / hh));   // hh = h
     return dexp(-(s / hh));
 }
 

@@ -133,13 +133,13 @@ void nnca::destroy_handle(nnca_h2 *H)
 
 static bool uses_length_scale(int32_t kind)
 {
-    return kind == NNCA_K_GAUSS || kind == NNCA_K_LOG_REG || kind == NNCA_K_INV_REG;
+    return kind == NNCA_K_GAUSS || kind == NNCA_K_LOG_REG || kind == NNCA_K_INV_REG || kind == NNCA_K_EXP_R;
 }
 
 static void check_kernel(int32_t kind, int32_t dim, double hparam)
 {
     if (kind != NNCA_K_LOG_R && kind != NNCA_K_INV_R && kind != NNCA_K_GAUSS && kind != NNCA_K_LOG_REG &&
-        kind != NNCA_K_INV_REG)
+        kind != NNCA_K_INV_REG && kind != NNCA_K_EXP_R)
         fail(NNCA_ERR_INVALID_ARG, "unknown kernel kind");
     if ((kind == NNCA_K_LOG_R || kind == NNCA_K_LOG_REG) && dim != 2)
         fail(NNCA_ERR_NOT_SUPPORTED, "log kernels are provided in 2D only");
@@ -713,6 +713,54 @@ nnca_status nnca_gmres(nnca_handle h, double alpha, double beta, const double *F
         const hipStream_t s = (hipStream_t)stream;
         order_call_begin(h, s);
         run_gmres(h, alpha, beta, F, X, tol, max_iter, restart, precision, iters, relres, s);
+        order_call_end(h, s);
+    });
+}
+
+static void no_overlap(const double *a, int64_t na, const double *b, int64_t nb, const char *what)
+{
+    const char *ab = (const char *)a, *ae = ab + sizeof(double) * na;
+    const char *bb = (const char *)b, *be = bb + sizeof(double) * nb;
+    if (ab < be && bb < ae) fail(NNCA_ERR_INVALID_ARG, what);
+}
+
+nnca_status nnca_svm_train(nnca_handle h, const double *y, double *alpha, double lambda, double beta, double eta,
+                           double tol, int32_t max_iter, int32_t precision, int32_t *iters, double *bias,
+                           double *eta_used, void *stream)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        require_square(h, "nnca_svm_train");
+        if (!y || !alpha) fail(NNCA_ERR_INVALID_ARG, "y or alpha is NULL");
+        no_overlap(y, h->n, alpha, h->n, "y and alpha overlap");
+        if (!(lambda > 0.0) || !std::isfinite(lambda)) fail(NNCA_ERR_INVALID_ARG, "lambda must be finite and > 0");
+        if (!(beta >= 0.0) || !std::isfinite(beta)) fail(NNCA_ERR_INVALID_ARG, "beta must be finite and >= 0");
+        if (!std::isfinite(eta) || !(tol >= 0.0)) fail(NNCA_ERR_INVALID_ARG, "eta must be finite and tol >= 0");
+        if (max_iter < 0) fail(NNCA_ERR_INVALID_ARG, "max_iter < 0");
+        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+        AllocScope as(h->alloc);
+        const hipStream_t s = (hipStream_t)stream;
+        order_call_begin(h, s);
+        run_svm_train(h, y, alpha, lambda, beta, eta, tol, max_iter, precision, iters, bias, eta_used, s);
+        order_call_end(h, s);
+    });
+}
+
+nnca_status nnca_svm_decision(nnca_handle h, const double *y, const double *alpha, double bias, double *f,
+                              int32_t precision, void *stream)
+{
+    return guarded([&] {
+        if (!h) fail(NNCA_ERR_INVALID_ARG, "handle is NULL");
+        if (!y || !alpha || !f) fail(NNCA_ERR_INVALID_ARG, "y, alpha or f is NULL");
+        const int64_t nq = h->general ? h->nq : h->n, np = h->n;
+        no_overlap(f, np, y, nq, "f and y overlap");
+        no_overlap(f, np, alpha, nq, "f and alpha overlap");
+        if (!std::isfinite(bias)) fail(NNCA_ERR_INVALID_ARG, "bias must be finite");
+        if (precision != NNCA_PREC_FP64 && precision != NNCA_PREC_MIXED) fail(NNCA_ERR_INVALID_ARG, "bad precision");
+        AllocScope as(h->alloc);
+        const hipStream_t s = (hipStream_t)stream;
+        order_call_begin(h, s);
+        run_svm_decision(h, y, alpha, bias, f, precision, s);
         order_call_end(h, s);
     });
 }

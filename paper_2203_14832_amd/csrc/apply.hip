@@ -1043,6 +1043,7 @@ static void launch_m2l_pair(int kind, nnca_h2 *H, const nnca::Level &L, const nn
     else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }
     else if (kind == NNCA_K_LOG_REG) { M2L_CASE(NNCA_K_LOG_REG) }
     else if (kind == NNCA_K_INV_REG) { M2L_CASE(NNCA_K_INV_REG) }
+    else if (kind == NNCA_K_EXP_R) { M2L_CASE(NNCA_K_EXP_R) }
     else if (kind == K_GAUSS_DH) { M2L_CASE(K_GAUSS_DH) }
     else { M2L_CASE(NNCA_K_GAUSS) }
 #undef M2L_CASE
@@ -1114,6 +1115,7 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
         else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
         else if (kind == NNCA_K_LOG_REG) SYM_CASE(NNCA_K_LOG_REG);
         else if (kind == NNCA_K_INV_REG) SYM_CASE(NNCA_K_INV_REG);
+        else if (kind == NNCA_K_EXP_R) SYM_CASE(NNCA_K_EXP_R);
         else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
         else SYM_CASE(NNCA_K_GAUSS);
 #undef SYM_CASE
@@ -1368,6 +1370,7 @@ void launch_p2p(int kind, nnca_h2 *H, const T *xw, const T *xw2, const double *f
     else if (kind == NNCA_K_LOG_R) P2P_CASE(NNCA_K_LOG_R);
     else if (kind == NNCA_K_LOG_REG) P2P_CASE(NNCA_K_LOG_REG);
     else if (kind == NNCA_K_INV_REG) P2P_CASE(NNCA_K_INV_REG);
+    else if (kind == NNCA_K_EXP_R) P2P_CASE(NNCA_K_EXP_R);
     else if (kind == K_GAUSS_DH) P2P_CASE(K_GAUSS_DH);
     else P2P_CASE(NNCA_K_GAUSS);
 #undef P2P_CASE
@@ -1388,6 +1391,7 @@ static void launch_p2p_sym(int kind, nnca_h2 *H, const float *xhi, const float *
     else if (kind == NNCA_K_LOG_R) PS_CASE(NNCA_K_LOG_R);
     else if (kind == NNCA_K_LOG_REG) PS_CASE(NNCA_K_LOG_REG);
     else if (kind == NNCA_K_INV_REG) PS_CASE(NNCA_K_INV_REG);
+    else if (kind == NNCA_K_EXP_R) PS_CASE(NNCA_K_EXP_R);
     else if (kind == K_GAUSS_DH) PS_CASE(K_GAUSS_DH);
     else PS_CASE(NNCA_K_GAUSS);
 #undef PS_CASE
@@ -1858,6 +1862,7 @@ void run_direct(const double *pts, int64_t n, int dim, int64_t ld, int kind, dou
         else if (kind == NNCA_K_LOG_R) k_direct<NNCA_K_LOG_R><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         else if (kind == NNCA_K_LOG_REG) k_direct<NNCA_K_LOG_REG><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         else if (kind == NNCA_K_INV_REG) k_direct<NNCA_K_INV_REG><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
+        else if (kind == NNCA_K_EXP_R) k_direct<NNCA_K_EXP_R><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         else k_direct<NNCA_K_GAUSS><<<g, NT, 0, s>>>(pts, n, dim, ld, x, y, prm);
         HIPCHECK(hipGetLastError());
     }
@@ -1990,6 +1995,7 @@ void one_column_general(nnca_h2 *H, bool adj, const T *xhi, const T *xlo, void *
     else if (kind == NNCA_K_LOG_R) P2PG_CASE(NNCA_K_LOG_R);
     else if (kind == NNCA_K_LOG_REG) P2PG_CASE(NNCA_K_LOG_REG);
     else if (kind == NNCA_K_INV_REG) P2PG_CASE(NNCA_K_INV_REG);
+    else if (kind == NNCA_K_EXP_R) P2PG_CASE(NNCA_K_EXP_R);
     else P2PG_CASE(NNCA_K_GAUSS);
 #undef P2PG_CASE
     HIPCHECK(hipGetLastError());

@@ -847,6 +847,7 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s, int ts
         else if (kind == NNCA_K_LOG_R) MF(NNCA_K_LOG_R, TSL); \
         else if (kind == NNCA_K_LOG_REG) MF(NNCA_K_LOG_REG, TSL); \
         else if (kind == NNCA_K_INV_REG) MF(NNCA_K_INV_REG, TSL); \
+        else if (kind == NNCA_K_EXP_R) MF(NNCA_K_EXP_R, TSL); \
         else MF(NNCA_K_GAUSS, TSL);
         if (tsel) { MFK(1) } else { MFK(0) }
 #undef MFK
@@ -858,12 +859,14 @@ void m2l_level_multi(nnca_h2 *H, int l, int P, bool mixed, hipStream_t s, int ts
             else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 1);
             else if (kind == NNCA_K_LOG_REG) VM(NNCA_K_LOG_REG, 1);
             else if (kind == NNCA_K_INV_REG) VM(NNCA_K_INV_REG, 1);
+            else if (kind == NNCA_K_EXP_R) VM(NNCA_K_EXP_R, 1);
             else VM(NNCA_K_GAUSS, 1);
         } else {
             if (kind == NNCA_K_INV_R) VM(NNCA_K_INV_R, 2);
             else if (kind == NNCA_K_LOG_R) VM(NNCA_K_LOG_R, 2);
             else if (kind == NNCA_K_LOG_REG) VM(NNCA_K_LOG_REG, 2);
             else if (kind == NNCA_K_INV_REG) VM(NNCA_K_INV_REG, 2);
+            else if (kind == NNCA_K_EXP_R) VM(NNCA_K_EXP_R, 2);
             else VM(NNCA_K_GAUSS, 2);
         }
 #undef VM
@@ -1094,12 +1097,14 @@ void multi_block(nnca_h2 *H, const TI *X, TO *Y, int R, int64_t ldx, int64_t ldy
         else if (kind == NNCA_K_LOG_R) PP(float, NNCA_K_LOG_R, W.xhi, W.xlo, prm32);
         else if (kind == NNCA_K_LOG_REG) PP(float, NNCA_K_LOG_REG, W.xhi, W.xlo, prm32);
         else if (kind == NNCA_K_INV_REG) PP(float, NNCA_K_INV_REG, W.xhi, W.xlo, prm32);
+        else if (kind == NNCA_K_EXP_R) PP(float, NNCA_K_EXP_R, W.xhi, W.xlo, prm32);
         else PP(float, NNCA_K_GAUSS, W.xhi, W.xlo, prm32);
     } else {
         if (kind == NNCA_K_INV_R) PP(double, NNCA_K_INV_R, W.xs, (const double *)nullptr, prm64);
         else if (kind == NNCA_K_LOG_R) PP(double, NNCA_K_LOG_R, W.xs, (const double *)nullptr, prm64);
         else if (kind == NNCA_K_LOG_REG) PP(double, NNCA_K_LOG_REG, W.xs, (const double *)nullptr, prm64);
         else if (kind == NNCA_K_INV_REG) PP(double, NNCA_K_INV_REG, W.xs, (const double *)nullptr, prm64);
+        else if (kind == NNCA_K_EXP_R) PP(double, NNCA_K_EXP_R, W.xs, (const double *)nullptr, prm64);
         else PP(double, NNCA_K_GAUSS, W.xs, (const double *)nullptr, prm64);
     }
 #undef PP

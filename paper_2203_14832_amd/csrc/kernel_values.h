@@ -1,6 +1,6 @@
 // Kernel values K(r) of the apply passes, shared by the single- and
 // multi-column kernels.  1/r and log r vanish at r = 0 in the near field; the
-// Gaussian is 1 there.
+// Gaussian and exp(-r/h) are 1 there.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -15,11 +15,13 @@ namespace nnca {
 constexpr int K_GAUSS_DH = 103;
 
 // The parameter `prm` of the apply kernels, from the kernel's length scale:
-// the Gaussian 1/h^2 (FP64) or log2(e)/h^2 (FP32), the regularised 1/r its
-// a, the regularised log r 1/log(a^2); unused by the others.
+// the Gaussian 1/h^2 (FP64) or log2(e)/h^2 (FP32), exp(-r/h) 1/h (FP64) or
+// log2(e)/h (FP32), the regularised 1/r its a, the regularised log r
+// 1/log(a^2); unused by the others.
 inline double kernel_prm64(int kind, double hp)
 {
     if (kind == NNCA_K_GAUSS || kind == K_GAUSS_DH) return 1.0 / (hp * hp);
+    if (kind == NNCA_K_EXP_R) return 1.0 / hp;
     if (kind == NNCA_K_INV_REG) return hp;
     if (kind == NNCA_K_LOG_REG) return 1.0 / std::log(hp * hp);
     return 0.0;
@@ -27,6 +29,7 @@ inline double kernel_prm64(int kind, double hp)
 inline float kernel_prm32(int kind, double hp)
 {
     if (kind == NNCA_K_GAUSS || kind == K_GAUSS_DH) return (float)(1.4426950408889634 / (hp * hp));
+    if (kind == NNCA_K_EXP_R) return (float)(1.4426950408889634 / hp);
     return (float)kernel_prm64(kind, hp);
 }
 
@@ -45,6 +48,7 @@ __device__ inline float kv32(float d2, float prm)
         const float r = sqrtf(d2), a = expf(0.5f * t);
         return (r * (0.5f * l - 1.0f)) / (a * (0.5f * t - 1.0f));
     }
+    if (KIND == NNCA_K_EXP_R) return __builtin_amdgcn_exp2f(-sqrtf(d2) * prm);   // prm = log2(e) / h
     if (KIND == K_GAUSS_DH) {
         float t = d2 * prm;   // log2(e) r^2 / h^2
         return (t * 0.693147180559945309f) * __builtin_amdgcn_exp2f(-t);
@@ -63,6 +67,7 @@ __device__ inline double kv64(double d2, double prm)
         const double r = sqrt(d2), a = exp(0.5 * t);
         return (r * (0.5 * l - 1.0)) / (a * (0.5 * t - 1.0));
     }
+    if (KIND == NNCA_K_EXP_R) return exp(-sqrt(d2) * prm);   // prm = 1 / h
     if (KIND == K_GAUSS_DH) {
         double t = d2 * prm;  // r^2 / h^2
         return t * exp(-t);
@@ -75,12 +80,12 @@ __device__ inline T kv(T d2, T prm)
     if constexpr (sizeof(T) == 4) return kv32<KIND>(d2, prm);
     else return kv64<KIND>(d2, prm);
 }
-// near field: 1/r and log r vanish at r = 0, the Gaussian is 1 there
+// near field: 1/r and log r vanish at r = 0, the Gaussian and exp(-r/h) are 1 there
 template <int KIND, typename T>
 __device__ inline T kv_self(T d2, T prm)
 {
     T v = kv<KIND, T>(d2, prm);
-    if (KIND == NNCA_K_GAUSS) return v;
+    if (KIND == NNCA_K_GAUSS || KIND == NNCA_K_EXP_R) return v;
     return d2 > T(0) ? v : T(0);
 }
 

@@ -293,6 +293,14 @@ enum { PASS_GATHER = 0, PASS_UP = 1, PASS_M2L = 2, PASS_DOWN = 3, PASS_P2P = 4, 
 // gmres.hip: restarted GMRES(restart) for (alpha I + beta A~) x = f
 void run_gmres(nnca_h2 *H, double alpha, double beta, const double *F, double *X, double tol, int32_t max_iter,
                int32_t restart, int precision, int32_t *iters, double *relres, hipStream_t s);
+// svm.hip: projected gradient ascent on the penalised SVM dual (eta <= 0:
+// 1 / (|K~|_2 + beta n) by the power method), then the bias; the decision
+// function f = K~ (y .* alpha) + bias
+void run_svm_train(nnca_h2 *H, const double *y, double *alpha, double lambda, double beta, double eta, double tol,
+                   int32_t max_iter, int precision, int32_t *iters, double *bias, double *eta_used,
+                   hipStream_t s);
+void run_svm_decision(nnca_h2 *H, const double *y, const double *alpha, double bias, double *f, int precision,
+                      hipStream_t s);
 // probe.hip: out[0..count) of {HBM copy bytes/s, FP32 FMA lane-ops/s,
 // v_rsq_f32 lane-ops/s, pairs/s of the symmetric pass's inner loop with r^2
 // on the vector ALUs, the same with r^2 on the matrix cores}

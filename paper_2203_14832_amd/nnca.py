@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnnca.so")
 
-KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "log_reg": 4, "inv_reg": 5}
+KINDS = {"log_r": 1, "inv_r": 2, "gauss": 3, "log_reg": 4, "inv_reg": 5, "exp_r": 6}
 PRECISION = {"fp64": 0, "mixed": 1}
 DTYPE_F32, DTYPE_F64 = 0, 1
 MAX_LEVELS = 64
@@ -140,6 +140,8 @@ def lib():
             "nnca_query_build": [P, P, i32],
             "nnca_export_half": [P, i32, i32, P, P, P],
             "nnca_export_half_operator": [P, i32, i32, i64, P, i64, P, P],
+            "nnca_svm_train": [P, P, P, f64, f64, f64, f64, i32, i32, P, P, P, P],
+            "nnca_svm_decision": [P, P, P, f64, P, i32, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -264,6 +266,44 @@ class H2Matrix:
                                     C.c_void_p(X.data_ptr()), float(tol), int(max_iter), int(restart),
                                     PRECISION[precision], C.byref(it), C.byref(rr), _stream(torch)))
         return X, it.value, rr.value
+
+    def shape(self):
+        """(rows, columns, general) of the operator (``nnca_query_shape``)."""
+        r, c, g = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().nnca_query_shape(self._h, C.byref(r), C.byref(c), C.byref(g)))
+        return r.value, c.value, bool(g.value)
+
+    def svm_train(self, y, lam: float = 1.0, beta: float = 1.0, eta: float = 0.0, tol: float = 1e-8,
+                  max_iter: int = 1000, precision: str = "fp64", alpha0=None):
+        """Kernel SVM dual by projected gradient ascent (``nnca_svm_train``):
+        labels y (+1 / -1) in the original point order; eta <= 0 picks
+        1 / (||K~|| + beta n).  Returns (alpha, bias, steps, eta)."""
+        torch = self.torch
+        yd = torch.as_tensor(y, dtype=torch.float64, device=self.device).reshape(self.n).contiguous()
+        a = (torch.zeros_like(yd) if alpha0 is None
+             else torch.as_tensor(alpha0, dtype=torch.float64, device=self.device).reshape(self.n).clone())
+        it = C.c_int32()
+        b = C.c_double()
+        e = C.c_double()
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_svm_train(self._h, C.c_void_p(yd.data_ptr()), C.c_void_p(a.data_ptr()), float(lam),
+                                        float(beta), float(eta), float(tol), int(max_iter), PRECISION[precision],
+                                        C.byref(it), C.byref(b), C.byref(e), _stream(torch)))
+        return a, b.value, it.value, e.value
+
+    def svm_decision(self, y, alpha, bias: float, precision: str = "fp64"):
+        """f = K~ (y .* alpha) + bias at the rows of the operator
+        (``nnca_svm_decision``); y and alpha have one entry per column."""
+        torch = self.torch
+        rows, cols, _ = self.shape()
+        yd = torch.as_tensor(y, dtype=torch.float64, device=self.device).reshape(cols).contiguous()
+        ad = torch.as_tensor(alpha, dtype=torch.float64, device=self.device).reshape(cols).contiguous()
+        f = torch.empty(rows, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().nnca_svm_decision(self._h, C.c_void_p(yd.data_ptr()), C.c_void_p(ad.data_ptr()),
+                                           float(bias), C.c_void_p(f.data_ptr()), PRECISION[precision],
+                                           _stream(torch)))
+        return f
 
     def set_symmetric(self, enable: bool = True):
         """Use (default) or not the symmetric evaluation (transverse pass and
@@ -431,11 +471,6 @@ class H2General(H2Matrix):
         self._soa = (ps, qs)
         self._destroy = lib().nnca_destroy
         _live.add(self)
-
-    def shape(self):
-        r, c, g = C.c_int64(), C.c_int64(), C.c_int32()
-        _check(lib().nnca_query_shape(self._h, C.byref(r), C.byref(c), C.byref(g)))
-        return r.value, c.value, bool(g.value)
 
     def _apply(self, X, precision: str, adjoint: bool, out=None, fn=None):
         torch = self.torch

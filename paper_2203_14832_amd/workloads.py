@@ -112,3 +112,37 @@ def batch_problem(b: int, n: int, nrhs: int = 8, seed: int = 1004):
     pts = rng.uniform(-1.0, 1.0, size=(n, 3))
     x = rng.standard_normal(size=(n, nrhs))
     return pts, x
+
+
+def svm_dataset(m: int, dim: int = 2, rule: str = "disk", seed: int = 1006, train_frac: float = 0.85):
+    """The synthetic two-class data of the kernel SVM (Exp. 6): m points
+    uniform in [-1.4,1.4]^2 (dim 2) or [-1,1]^dim (otherwise), labels +1 / -1
+    in nearly equal numbers, split per class into train_frac training points
+    and the rest for testing (so both parts stay balanced).  Label rules:
+      disk  +1 where |x| is below the sample median of |x| (any dim);
+      wave  +1 where x_2 > 0.6 sin(1.5 x_1) (2D; balanced by the point
+            symmetry x -> -x of the box, which swaps the classes).
+    Returns (train points, train labels, test points, test labels), FP64."""
+    rng = np.random.default_rng(seed)
+    half = 1.4 if dim == 2 else 1.0
+    x = rng.uniform(-half, half, size=(m, dim))
+    if rule == "disk":
+        r = np.linalg.norm(x, axis=1)
+        y = np.where(r < np.median(r), 1.0, -1.0)
+    elif rule == "wave":
+        if dim != 2:
+            raise ValueError("the wave rule is 2D")
+        y = np.where(x[:, 1] > 0.6 * np.sin(1.5 * x[:, 0]), 1.0, -1.0)
+    else:
+        raise ValueError(rule)
+    tr = []
+    te = []
+    for c in (1.0, -1.0):
+        idx = np.flatnonzero(y == c)
+        idx = idx[rng.permutation(idx.size)]
+        k = int(round(train_frac * idx.size))
+        tr.append(idx[:k])
+        te.append(idx[k:])
+    tr = np.sort(np.concatenate(tr))
+    te = np.sort(np.concatenate(te))
+    return x[tr], y[tr], x[te], y[te]

@@ -52,6 +52,7 @@ def test_invalid_arguments(lib):
     assert _build(lib, P, 10, 3, 10, tol=float("nan"))[0] == 1
     assert _build(lib, P, 10, 3, 10, kind=7)[0] == 1
     assert _build(lib, P, 10, 3, 10, kind=3, h=0.0)[0] == 1
+    assert _build(lib, P, 10, 3, 10, kind=6, h=-1.0)[0] == 1   # exp(-r/h) needs h > 0
     assert _build(lib, P, 10, 3, 10, kind=1)[0] == 4   # log only in 2D
     assert b"dim" in lib.nnca_last_error() or lib.nnca_last_error()
     assert lib.nnca_matvec(None, None, None, 1, 1, 1, 1, 0, None) == 1
@@ -63,6 +64,8 @@ def test_invalid_arguments(lib):
     assert lib.nnca_destroy(None) == 0
     assert lib.nnca_direct(None, 10, 3, 10, 2, 1.0, None, None, 1, 10, 10, None) == 1
     assert lib.nnca_matvec_backward(None, None, None, 1, 1, 1, 0, None, 1, None, None) == 1
+    assert lib.nnca_svm_train(None, None, None, 1.0, 1.0, 0.0, 1e-8, 10, 0, None, None, None, None) == 1
+    assert lib.nnca_svm_decision(None, None, None, 0.0, None, 0, None) == 1
 
 
 def test_general_build_invalid_arguments(lib):

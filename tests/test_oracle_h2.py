@@ -24,7 +24,7 @@ def build(orc, p, kind, tol, leaf, eta2=None, h=1.0, policy=1):
     return T, orc.H2(T, kind, tol, h=h, policy=policy)
 
 
-@pytest.mark.parametrize("kind,d", [("inv_r", 3), ("log_r", 2), ("gauss", 3)])
+@pytest.mark.parametrize("kind,d", [("inv_r", 3), ("log_r", 2), ("gauss", 3), ("exp_r", 2)])
 def test_single_leaf_is_dense(orc, kind, d):
     rng = np.random.default_rng(0)
     p, x = rng.uniform(-1, 1, (300, d)), rng.standard_normal(300)
@@ -33,7 +33,8 @@ def test_single_leaf_is_dense(orc, kind, d):
     assert rel(H.matvec(x), orc.direct(p, x, kind, 0.5)) <= 1e-14
 
 
-@pytest.mark.parametrize("kind,d,n", [("inv_r", 3, 3000), ("log_r", 2, 2000), ("gauss", 3, 2500)])
+@pytest.mark.parametrize("kind,d,n", [("inv_r", 3, 3000), ("log_r", 2, 2000), ("gauss", 3, 2500),
+                                      ("exp_r", 2, 2000)])
 def test_zero_tolerance_is_dense(orc, kind, d, n):
     rng = np.random.default_rng(1)
     p, x = rng.uniform(-1, 1, (n, d)), rng.standard_normal(n)
@@ -50,7 +51,7 @@ def test_c1_workload_against_direct_sum(orc):
     assert rel(y, orc.direct(p, x[:, 0], "log_r")) <= 1e-6
 
 
-@pytest.mark.parametrize("kind,d,n,leaf", [("log_r", 2, 4096, 32), ("inv_r", 3, 8192, 32)])
+@pytest.mark.parametrize("kind,d,n,leaf", [("log_r", 2, 4096, 32), ("inv_r", 3, 8192, 32), ("exp_r", 2, 4096, 32)])
 def test_error_falls_with_tolerance(orc, kind, d, n, leaf):
     rng = np.random.default_rng(2)
     p, x = rng.uniform(-1, 1, (n, d)), rng.standard_normal(n)

@@ -34,15 +34,16 @@ def test_exp_matches_libm(orc):
     assert orc.exp(0.0) == 1.0
 
 
-@pytest.mark.parametrize("kind,d", [("inv_r", 3), ("inv_r", 2), ("log_r", 2), ("gauss", 3)])
+@pytest.mark.parametrize("kind,d", [("inv_r", 3), ("inv_r", 2), ("log_r", 2), ("gauss", 3), ("exp_r", 2),
+                                    ("exp_r", 4)])
 def test_kernel_diagonal_and_symmetry(orc, kind, d):
     rng = np.random.default_rng(2)
     a, b = rng.uniform(-1, 1, d), rng.uniform(-1, 1, d)
     assert orc.kernel_eval(kind, a, b, 0.5) == orc.kernel_eval(kind, b, a, 0.5)
     diag = orc.kernel_eval(kind, a, a, 0.5)
-    assert diag == (1.0 if kind == "gauss" else 0.0)
+    assert diag == (1.0 if kind in ("gauss", "exp_r") else 0.0)
     r = np.linalg.norm(a - b)
-    ref = {"inv_r": 1 / r, "log_r": np.log(r), "gauss": np.exp(-r * r / 0.25)}[kind]
+    ref = {"inv_r": 1 / r, "log_r": np.log(r), "gauss": np.exp(-r * r / 0.25), "exp_r": np.exp(-r / 0.5)}[kind]
     assert abs(orc.kernel_eval(kind, a, b, 0.5) - ref) <= 1e-15 * max(1.0, abs(ref))
 
 
@@ -54,16 +55,18 @@ def _dense(kind, p, h=1.0):
             K = np.where(r > 0, 1.0 / np.where(r > 0, r, 1), 0.0)
         elif kind == "log_r":
             K = np.where(r > 0, np.log(np.where(r > 0, r, 1)), 0.0)
+        elif kind == "exp_r":
+            K = np.exp(-r / h)
         else:
             K = np.exp(-r * r / (h * h))
     return K
 
 
-@pytest.mark.parametrize("kind,d", [("inv_r", 3), ("log_r", 2), ("gauss", 3)])
+@pytest.mark.parametrize("kind,d", [("inv_r", 3), ("log_r", 2), ("gauss", 3), ("exp_r", 2)])
 def test_direct_equals_dense_product(orc, kind, d):
     rng = np.random.default_rng(3)
     p = rng.uniform(-1, 1, (700, d))
-    p[5] = p[17]  # a duplicate point: K = 0 (1/r, log) or 1 (Gaussian) there
+    p[5] = p[17]  # a duplicate point: K = 0 (1/r, log) or 1 (Gaussian, exp(-r/h)) there
     x = rng.standard_normal((700, 2))
     y = orc.direct(p, x, kind, 0.5)
     yd = _dense(kind, p, 0.5) @ x
