@@ -119,7 +119,7 @@ def main():
                          "mixed matvecs of the workload, no timing")
     ap.add_argument("--rates", action="store_true",
                     help="print the device's attainable rates (copy, FMA, rsq, the symmetric pass's inner loop)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie", "exp", "general"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ie", "exp", "general", "svm"],
                     help="c2: the metric (N=2^20 cube, 1 RHS); c3: 64 RHS on the sphere, block vs column loop; "
                          "c4: Gaussian forward + backward (x and length scale); c5: uneven batch of 32 problems")
     args = ap.parse_args()
@@ -151,6 +151,8 @@ def main():
         return bench_experiments(args)
     if args.config == "general":
         return bench_general(args)
+    if args.config == "svm":
+        return bench_svm(args)
     dev = torch.device("cuda:0")
     p, x = workload("c2", n=args.n)
     n = p.shape[0]
@@ -412,6 +414,71 @@ def bench_general(args):
         torch.cuda.empty_cache()
     print(json.dumps({"config": "general", "workload": "3D 1/r, tol 1e-6, leaf 64, 2^20 uniform sources; targets "
                                                        "2^20 uniform in the same cube, or 2^19 in a shifted cube",
+                      "rows": rows}), flush=True)
+
+
+def bench_svm(args):
+    """Exp. 6 in 2D: kernel SVM trained by projected gradient ascent with
+    the H2 matvec (FSVM).  The two datasets (M points uniform in
+    [-1.4,1.4]^2, 85 % for training): exp(-r) with the
+    disk labels and exp(-r^2) with the wave labels; lambda = 1, beta = 1,
+    the step 1 / (||K~|| + beta n), tol 1e-8 for the ACA, training until the
+    relative step is below 1e-4.  Per dataset: assembly (build) seconds,
+    training steps and seconds, seconds per step with the H2 product and
+    with the GPU direct sum in its place (NSVM), and the per-class and
+    overall accuracy on the held-out points.  Then seconds per step at M =
+    2^16, 2^18, 2^20 (100 steps at tol 0)."""
+    import torch
+    from paper_2203_14832_amd import nnca
+    from paper_2203_14832_amd.workloads import svm_dataset
+    dev = torch.device("cuda:0")
+    rows = []
+    for kind, rule in (("exp_r", "disk"), ("gauss", "wave")):
+        for m in (5625, 1 << 16, 1 << 18, 1 << 20):
+            P, y, Q, yq = svm_dataset(m, 2, rule)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G = nnca.H2Matrix(P, kind, 1e-8, 64, device=dev)
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - t0
+            row = {"kernel": kind, "labels": rule, "M": m, "train": [int((y > 0).sum()), int((y < 0).sum())],
+                   "test": [int((yq > 0).sum()), int((yq < 0).sum())], "assembly_s": ta}
+            if m == 5625:
+                t0 = time.perf_counter()
+                a, b, it, eta = G.svm_train(y, 1.0, 1.0, tol=1e-4, max_iter=50000)
+                torch.cuda.synchronize()
+                tt = time.perf_counter() - t0
+                GG = nnca.H2General(Q, P, kind, 1e-8, 64, device=dev)
+                f = GG.svm_decision(y, a, b).cpu().numpy()
+                GG.close()
+                acc = [float(np.mean(np.sign(f[yq == c]) == c)) for c in (1.0, -1.0)]
+                row.update({"steps": it, "train_s": tt, "s_per_step": tt / max(it, 1), "eta": eta, "bias": b,
+                            "accuracy_per_class": acc, "accuracy": float(np.mean(np.sign(f) == yq))})
+                # NSVM: the same step with the GPU direct sum for K v
+                v = torch.tensor(y, device=dev)
+                nnca.direct(P, v, kind, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(20):
+                    nnca.direct(P, v, kind, device=dev)
+                torch.cuda.synchronize()
+                row["direct_matvec_s"] = (time.perf_counter() - t0) / 20
+            else:
+                G.svm_train(y, 1.0, 1.0, tol=0.0, max_iter=3)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, it, _ = G.svm_train(y, 1.0, 1.0, tol=0.0, max_iter=100)
+                torch.cuda.synchronize()
+                tt = time.perf_counter() - t0
+                row.update({"steps": it, "train_s": tt, "s_per_step": tt / it})
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            G.close()
+            del G
+            torch.cuda.empty_cache()
+    print(json.dumps({"config": "svm", "workload": "kernel SVM by projected gradient ascent (Exp. 6, 2D): "
+                                                   "exp(-r) disk / exp(-r^2) wave labels, [-1.4,1.4]^2, 85/15 "
+                                                   "split, lambda 1, beta 1, ACA tol 1e-8, leaf 64",
                       "rows": rows}), flush=True)
 
 
