@@ -1071,13 +1071,14 @@ static void launch_m2l_mode(int kind, nnca_h2 *H, const nnca::Level &L, const C 
 }
 
 // split factor of the symmetric pass, on the owned sources: enough
-// workgroups for about 16384 per level (four per cell at level kappa-1 of
-// the 2^20 cube, whose 4096 cells vary in work: 0.80 against 0.89-0.91 ms
-// unsplit; the leaf level's 32768 cells run unsplit, a split of two made it
-// slower, 0.94 against 0.86 ms)
+// workgroups for about 8192 per level (two per cell at level kappa-1 of the
+// 2^20 cube, whose 4096 cells vary in work; with the XCD-aware, largest-
+// first launch order 0.73 ms per launch against 0.745 for four parts, 0.77
+// for eight; in cell order four parts had been best, 0.80 against 0.89-0.91
+// ms unsplit; the leaf level's 32768 cells run unsplit)
 static int sym_parts(const nnca::Level &L)
 {
-    const int64_t want = 16384;
+    const int64_t want = 8192;
     if (L.ncell >= want) return 1;
     int64_t P = (want + L.ncell - 1) / L.ncell;
     int64_t maxp = (L.max_own + 1023) / 1024;
