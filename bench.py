@@ -41,7 +41,7 @@ PEAK_PAIRS = VALU_LANE_SLOTS / SLOTS_PER_PAIR
 # runs of `bench.py --probe` (profiles/h2_matvec_c2_hbm_bytes.md), scaled by
 # the counters' reading of a 256 MiB copy: fetch + write MiB at kappa and
 # kappa-1.  Valid for one version of k_m2l_sym; None once the kernel changes.
-M2L_SYM_HBM_MIB = ((277.0, 339.9), (94.1, 117.0))
+M2L_SYM_HBM_MIB = ((387.7, 343.8), (30.9, 120.3))
 # Dense FP32 matrix-core peak of MI355X (the many-column transverse pass and
 # near field multiply FP32 kernel tiles by weight tiles on the matrix cores)
 FP32_MFMA_PEAK = 157.3e12
