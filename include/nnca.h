@@ -423,8 +423,10 @@ nnca_status nnca_gmres(nnca_handle h, double alpha, double beta, const double *F
  * *bias = the mean of y_i - (K~ v)_i over the free support vectors
  * (0 < a_i < lambda) of the final iterate, 0 if there are none.  The
  * precision (an nnca_precision) is that of every matvec.  Reductions have
- * a fixed shape, so the iterates repeat bit for bit run to run.  Blocks
- * until done; allocates device scratch of 2N + 1026 doubles.
+ * a fixed shape, so the iterates repeat bit for bit run to run.  The
+ * stopping rule is evaluated on the device and read by the host every 16
+ * steps (steps launched after it has fired change nothing).  Blocks until
+ * done; allocates device scratch of 2N + 2050 doubles.
  * Errors: INVALID_ARG (NULL handle or vectors, overlap, lambda not > 0,
  * beta < 0, non-finite eta, tol < 0, max_iter < 0, bad precision);
  * NOT_SUPPORTED (a handle of nnca_build_general); NUMERICAL (power steps

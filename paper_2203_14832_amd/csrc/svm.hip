@@ -18,6 +18,7 @@ namespace {
 
 constexpr int SV_NT = 256;
 constexpr int SV_BLK = 512;   // partial sums per reduction
+static_assert(SV_BLK == 2 * SV_NT, "k_sv_step folds the partials two per thread");
 
 // elementwise kernels: grid-stride loops (the grid is capped by grid_for)
 __global__ void k_sv_mul(int64_t n, const double *a, const double *b, double *c)
@@ -44,18 +45,30 @@ __global__ __launch_bounds__(SV_NT) void k_sv_sum(int64_t n, const double *v, do
     if (t == 0) part[b] = red[0];
 }
 
-// a_new = clip(a + eta (1 - y Kv - beta s y), 0, lambda) with s = sum v
-// (*sv, device); per block, the sums of (a_new - a)^2 and a_new^2
-__global__ __launch_bounds__(SV_NT) void k_sv_step(int64_t n, const double *y, const double *kv, const double *sv,
-                                                   double eta, double beta, double lambda, double *a,
-                                                   double *part)
+// One step, for every block: s = sum v from the previous step's SV_BLK
+// partials (svin, the same fixed-shape fold in every block), then
+// a_new = clip(a + eta (1 - y Kv - beta s y), 0, lambda), v_new = y a_new, and
+// per block the sums of (a_new - a)^2, a_new^2 (part, part + SV_BLK) and
+// v_new (svout).  Nothing is written once the stopping rule has fired
+// (*state: [0] done flag, [1] steps taken).
+__global__ __launch_bounds__(SV_NT) void k_sv_step(int64_t n, const double *y, const double *kv, const double *svin,
+                                                   double eta, double beta, double lambda, double *a, double *v,
+                                                   double *part, double *svout, const int32_t *state)
 {
-    __shared__ double rd[SV_NT], ra[SV_NT];
+    __shared__ double rd[SV_NT], ra[SV_NT], rv[SV_NT];
+    if (state[0]) return;   // uniform for the grid
     const int b = blockIdx.x, t = threadIdx.x;
+    rd[t] = svin[t] + svin[t + SV_NT];   // SV_BLK = 2 SV_NT partials
+    __syncthreads();
+    for (int h = SV_NT / 2; h > 0; h >>= 1) {
+        if (t < h) rd[t] += rd[t + h];
+        __syncthreads();
+    }
+    const double s = rd[0];
+    __syncthreads();
     const int64_t per = (n + SV_BLK - 1) / SV_BLK;
     const int64_t i0 = (int64_t)b * per, i1 = i0 + per < n ? i0 + per : n;
-    const double s = *sv;
-    double d2 = 0.0, a2 = 0.0;
+    double d2 = 0.0, a2 = 0.0, vs = 0.0;
     for (int64_t i = i0 + t; i < i1; i += SV_NT) {
         const double g = (1.0 - y[i] * kv[i]) - beta * s * y[i];
         double an = a[i] + eta * g;
@@ -64,21 +77,42 @@ __global__ __launch_bounds__(SV_NT) void k_sv_step(int64_t n, const double *y, c
         d2 += dd * dd;
         a2 += an * an;
         a[i] = an;
+        const double vn = y[i] * an;
+        v[i] = vn;
+        vs += vn;
     }
     rd[t] = d2;
     ra[t] = a2;
+    rv[t] = vs;
     __syncthreads();
     for (int h = SV_NT / 2; h > 0; h >>= 1) {
         if (t < h) {
             rd[t] += rd[t + h];
             ra[t] += ra[t + h];
+            rv[t] += rv[t + h];
         }
         __syncthreads();
     }
     if (t == 0) {
         part[b] = rd[0];
         part[SV_BLK + b] = ra[0];
+        svout[b] = rv[0];
     }
+}
+
+// the stopping rule after a step: ||a_new - a|| <= tol ||a_new|| (||a_new||
+// read as 1 when it is 0); counts the step and sets the done flag
+__global__ void k_sv_check(const double *part, double tol, int32_t *state)
+{
+    if (threadIdx.x != 0 || state[0]) return;
+    double d2 = 0.0, a2 = 0.0;
+    for (int b = 0; b < SV_BLK; b++) {
+        d2 += part[b];
+        a2 += part[SV_BLK + b];
+    }
+    const double dn = sqrt(d2), an = sqrt(a2);
+    state[1] += 1;
+    if (dn <= tol * (an > 0.0 ? an : 1.0)) state[0] = 1;
 }
 
 // the bias terms: per block the sum of y_i - (K v)_i over the free support
@@ -148,12 +182,15 @@ void run_svm_train(nnca_h2 *H, const double *y, double *alpha, double lambda, do
 {
     const int64_t n = H->n;
     double *v = dalloc<double>(n), *kv = dalloc<double>(n);
-    double *part = dalloc<double>(2 * SV_BLK), *red = dalloc<double>(2);
+    double *part = dalloc<double>(4 * SV_BLK), *red = dalloc<double>(2);
+    double *svp[2] = {part + 2 * SV_BLK, part + 3 * SV_BLK};   // sum-v partials, by step parity
+    int32_t *state = dalloc<int32_t>(2);
     auto release = [&] {
         dfree(v);
         dfree(kv);
         dfree(part);
         dfree(red);
+        dfree(state);
     };
     try {
         const int g = grid_for(n, 256);
@@ -187,25 +224,30 @@ void run_svm_train(nnca_h2 *H, const double *y, double *alpha, double lambda, do
             eta = 1.0 / (lam + beta * (double)n);
         }
         if (eta_used) *eta_used = eta;
-        int32_t it = 0;
-        for (; it < max_iter; it++) {
-            k_sv_mul<<<g, 256, 0, s>>>(n, y, alpha, v);
-            HIPCHECK(hipGetLastError());
+        // v = y a and its block partials; state = {done, steps}
+        k_sv_mul<<<g, 256, 0, s>>>(n, y, alpha, v);
+        HIPCHECK(hipGetLastError());
+        k_sv_sum<<<SV_BLK, SV_NT, 0, s>>>(n, v, svp[0]);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemsetAsync(state, 0, 2 * sizeof(int32_t), s));
+        int32_t hs[2] = {0, 0};
+        // the host reads the state every SV_POLL steps: steps launched after
+        // the rule has fired change nothing (the step kernel returns at once)
+        constexpr int SV_POLL = 16;
+        for (int32_t it = 0; it < max_iter; it++) {
             run_matvec(H, v, kv, 1, n, n, NNCA_F64, precision, s);
-            k_sv_sum<<<SV_BLK, SV_NT, 0, s>>>(n, v, part);
+            k_sv_step<<<SV_BLK, SV_NT, 0, s>>>(n, y, kv, svp[it & 1], eta, beta, lambda, alpha, v, part,
+                                               svp[(it + 1) & 1], state);
             HIPCHECK(hipGetLastError());
-            k_sv_fold<<<1, 64, 0, s>>>(1, part, red);   // red[0] = sum v, read on the device
+            k_sv_check<<<1, 64, 0, s>>>(part, tol, state);
             HIPCHECK(hipGetLastError());
-            k_sv_step<<<SV_BLK, SV_NT, 0, s>>>(n, y, kv, red, eta, beta, lambda, alpha, part);
-            HIPCHECK(hipGetLastError());
-            fold(2);
-            const double dn = std::sqrt(hr[0]), an = std::sqrt(hr[1]);
-            if (dn <= tol * (an > 0.0 ? an : 1.0)) {
-                it++;
-                break;
+            if ((it + 1) % SV_POLL == 0 || it + 1 == max_iter) {
+                HIPCHECK(hipMemcpyAsync(hs, state, sizeof(hs), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipStreamSynchronize(s));
+                if (hs[0]) break;
             }
         }
-        if (iters) *iters = it;
+        if (iters) *iters = hs[1];
         if (bias) {
             k_sv_mul<<<g, 256, 0, s>>>(n, y, alpha, v);
             HIPCHECK(hipGetLastError());
