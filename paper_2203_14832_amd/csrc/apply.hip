@@ -1118,22 +1118,29 @@ static void launch_m2l_sym(int kind, nnca_h2 *H, const nnca::Level &L, int level
         if (H->m2l_part_cap < (int64_t)P * L.npiv) fail(NNCA_ERR_INTERNAL, "split workspace not sized");
         part = H->m2l_part;
     }
-    SymArgs A{L.k, L.piv_ptr, L.own_ptr, L.own_il, L.own_pre, L.own_sum, L.own_slot, L.pc32, L.pc64, L.npiv, nc,
-              L.coord, L.hcell, (float)L.h, H->dim, P, L.w64, L.u64, part, L.col32, L.col64, prm, L.sym_order,
-              L.sym_slots};
-    const int g = (int)(8 * L.sym_slots * P);
     {
         Span sp(H, s, PASS_M2L, level);
-#define SYM_CASE(K) sym_launch<K, MODE>(L.max_k, g, A, s)
-        if (kind == NNCA_K_INV_R) SYM_CASE(NNCA_K_INV_R);
-        else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
-        else if (kind == NNCA_K_LOG_REG) SYM_CASE(NNCA_K_LOG_REG);
-        else if (kind == NNCA_K_INV_REG) SYM_CASE(NNCA_K_INV_REG);
-        else if (kind == NNCA_K_EXP_R) SYM_CASE(NNCA_K_EXP_R);
-        else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
-        else SYM_CASE(NNCA_K_GAUSS);
+        // the cells of rank <= 80 (all cells when the level is not split),
+        // then those above
+        for (int cls = 0; cls < 2; cls++) {
+            const int64_t slots = cls == 0 ? L.sym_slots : L.sym_slots_hi;
+            if (slots == 0) continue;
+            const int32_t mk = cls == 0 && L.sym_slots_hi > 0 ? 80 : L.max_k;
+            SymArgs A{L.k, L.piv_ptr, L.own_ptr, L.own_il, L.own_pre, L.own_sum, L.own_slot, L.pc32, L.pc64, L.npiv,
+                      nc, L.coord, L.hcell, (float)L.h, H->dim, P, L.w64, L.u64, part, L.col32, L.col64, prm,
+                      L.sym_order + (cls == 0 ? 0 : 8 * L.sym_slots), slots};
+            const int g = (int)(8 * slots * P);
+#define SYM_CASE(K) sym_launch<K, MODE>(mk, g, A, s)
+            if (kind == NNCA_K_INV_R) SYM_CASE(NNCA_K_INV_R);
+            else if (kind == NNCA_K_LOG_R) SYM_CASE(NNCA_K_LOG_R);
+            else if (kind == NNCA_K_LOG_REG) SYM_CASE(NNCA_K_LOG_REG);
+            else if (kind == NNCA_K_INV_REG) SYM_CASE(NNCA_K_INV_REG);
+            else if (kind == NNCA_K_EXP_R) SYM_CASE(NNCA_K_EXP_R);
+            else if (kind == K_GAUSS_DH) SYM_CASE(K_GAUSS_DH);
+            else SYM_CASE(NNCA_K_GAUSS);
 #undef SYM_CASE
-        HIPCHECK(hipGetLastError());
+            HIPCHECK(hipGetLastError());
+        }
     }
     if (after) HIPCHECK(hipEventRecord(after, s));
     Span sp(H, s, PASS_M2L_COMBINE, level);
@@ -1648,28 +1655,56 @@ void prepare_symmetric(nnca_h2 *H, Level &L, bool)
     // 0.87 and 0.80 in plain cell order; 0.81 and 0.75 with the largest-
     // first order over the whole level; 0.83 and 0.75 with the runs in tree
     // order.
-    std::vector<int64_t> wk(nc);
-    int64_t wtot = 0;
-    for (int64_t c = 0; c < nc; c++) { wk[c] = (int64_t)kh[c] * osum[c]; wtot += wk[c]; }
-    std::vector<std::vector<int32_t>> ch(8);
-    {
-        int64_t cum = 0;
+    //
+    // Rank classes.  A launch's shape set follows the largest rank it
+    // holds, and the sets for ranks above 80 take more registers per lane
+    // (fewer waves per SIMD).  Where cells of rank above 80 are at most a
+    // quarter of the level, they get a launch of their own and the others
+    // run with the set for ranks <= 80: level 7 of the 80^3 Chebyshev grid
+    // (343 000 cells, mean rank 1.5, largest 88) 7.3 -> about 1.6 ms in the
+    // FP32 form; splitting level kappa-1 of the 2^20 cube (most of its 4096
+    // cells above 80) made it slower, 0.76 against 0.73 ms.  Cells of rank 0
+    // own no pairs and get no slot.
+    int64_t nhi = 0;
+    for (int64_t c = 0; c < nc; c++) nhi += kh[c] > 80;
+    const bool split = L.max_k > 80 && nhi > 0 && 4 * nhi <= nc;
+    std::vector<int32_t> ord;
+    auto runs = [&](int cls) -> int64_t {
+        std::vector<int64_t> wk(nc, 0);
+        int64_t wtot = 0, cnt = 0;
         for (int64_t c = 0; c < nc; c++) {
-            int x = wtot > 0 ? (int)((cum * 8) / (wtot + 1)) : (int)((c * 8) / nc);
+            const bool in = kh[c] > 0 && (!split || (cls == 0 ? kh[c] <= 80 : kh[c] > 80));
+            if (!in) continue;
+            wk[c] = (int64_t)kh[c] * osum[c];
+            wtot += wk[c];
+            cnt++;
+        }
+        if (cnt == 0) return 0;
+        std::vector<std::vector<int32_t>> ch(8);
+        int64_t cum = 0, seen = 0;
+        for (int64_t c = 0; c < nc; c++) {
+            const bool in = kh[c] > 0 && (!split || (cls == 0 ? kh[c] <= 80 : kh[c] > 80));
+            if (!in) continue;
+            int x = wtot > 0 ? (int)((cum * 8) / (wtot + 1)) : (int)((seen * 8) / cnt);
             if (x > 7) x = 7;
             ch[x].push_back((int32_t)c);
             cum += wk[c];
+            seen++;
         }
-    }
-    size_t ms = 1;
-    for (auto &v : ch) {
-        std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return wk[a] > wk[b]; });
-        ms = std::max(ms, v.size());
-    }
-    std::vector<int32_t> ord(8 * ms, -1);
-    for (int x = 0; x < 8; x++)
-        for (size_t i = 0; i < ch[x].size(); i++) ord[x * ms + i] = ch[x][i];
-    L.sym_slots = (int64_t)ms;
+        size_t ms = 1;
+        for (auto &v : ch) {
+            std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return wk[a] > wk[b]; });
+            ms = std::max(ms, v.size());
+        }
+        const size_t base = ord.size();
+        ord.resize(base + 8 * ms, -1);
+        for (int x = 0; x < 8; x++)
+            for (size_t i = 0; i < ch[x].size(); i++) ord[base + x * ms + i] = ch[x][i];
+        return (int64_t)ms;
+    };
+    L.sym_slots = runs(0);
+    L.sym_slots_hi = split ? runs(1) : 0;
+    if (ord.empty()) ord.push_back(-1);
     L.sym_order = up(ord);
     L.col64 = dalloc<double>(col);
     L.col32 = reinterpret_cast<float *>(L.col64);

@@ -104,8 +104,8 @@ struct Level {
     int32_t *own_ptr = nullptr, *own_il = nullptr, *own_pre = nullptr, *own_sum = nullptr;
     int32_t *own_slot = nullptr;     // per owned entry: colbuf offset of its first source minus own_pre
     int32_t *non_ptr = nullptr, *non_slot = nullptr;   // per cell: slots of the pairs it does not own
-    int32_t *sym_order = nullptr;    // launch order: 8 runs (one per XCD) of sym_slots cells, -1 = empty
-    int64_t sym_slots = 0;
+    int32_t *sym_order = nullptr;    // launch order: 8 runs (one per XCD) of sym_slots cells, -1 = empty,
+    int64_t sym_slots = 0, sym_slots_hi = 0;   // then 8 runs of sym_slots_hi cells of rank > 80 (if split)
     float *col32 = nullptr;          // column slots, FP32 (FP32 form) or
     double *col64 = nullptr;         //   FP64 (FP64-refined form)
     int64_t ncol = 0;
