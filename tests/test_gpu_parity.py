@@ -73,7 +73,16 @@ CASES = {
     # the kernel SVM's training points of Exp. 6 (2D, [-1.4,1.4]^2) with the
     # paper's "Matern" kernel exp(-r)
     "svm2d_expr": (lambda: svm_dataset(24000, 2, "disk")[0], "exp_r", 1e-8, 64, 1.0, None),
+    # a uniform cube with a dense Gaussian cluster: at levels 3-5 a few cells
+    # (under a quarter) have ranks above 80, so the symmetric pass launches
+    # them apart from the rest (rank classes) in all three arithmetic forms
+    "cluster_split": (lambda: _cluster(), "inv_r", 1e-7, 64, 1.0, None),
 }
+
+
+def _cluster():
+    rng = np.random.default_rng(31)
+    return np.vstack([rng.uniform(-1, 1, (30000, 3)), 0.3 + 0.12 * rng.standard_normal((20000, 3))])
 
 
 def close_elementwise(Y, Yo, tol):
@@ -228,6 +237,20 @@ def test_matvec_parity(built, name):
     Ya = G.rmatvec(Xt, "fp64").cpu().numpy()
     lhs, rhs = X[:, 0] @ Ya[:, 1], Y64[:, 0] @ X[:, 1]
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(X[:, 0]) * np.linalg.norm(Y64[:, 1])
+
+
+def test_rank_class_split_reached(built):
+    # the library splits a level's symmetric launch when its largest rank is
+    # above 80 and at most a quarter of its cells are: this case must have
+    # such levels on both sides of the FP32 / FP64-refined boundary
+    p, G, T, O, kind, h = built("cluster_split")
+    kap = G.info()["kappa"]
+    split = []
+    for l in range(O.lmin, kap + 1):
+        k = np.diff(np.asarray(G.pivots(l)[0]))
+        if k.max() > 80 and 4 * (k > 80).sum() <= k.size:
+            split.append(l)
+    assert kap in (6,) and 5 in split and 4 in split, split
 
 
 def test_symmetric_near_field(built):
