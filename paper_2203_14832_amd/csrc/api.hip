@@ -119,7 +119,7 @@ void nnca::destroy_handle(nnca_h2 *H)
             void *ps[] = {L.first, L.count, L.m, L.tt_off, L.k, L.piv_ptr, L.piv_id, L.ipos, L.jid, L.rem_ptr,
                           L.rem_pos, L.crem_off, L.crem64, L.crem_t, L.piv_cell, L.rem_cell, L.pc64, L.pc32,
                           L.ilpre, L.ilsum, L.w64, L.u64, L.hcell, L.own_ptr, L.own_il, L.own_pre, L.own_sum,
-                          L.own_slot, L.non_ptr, L.non_slot, L.sym_order, L.col64};   // col32 aliases col64
+                          L.own_slot, L.non_ptr, L.non_slot, L.sym_order, L.m2l_order, L.col64};   // col32 aliases col64
             for (void *p : ps) dfree(p);
         }
     void *ps[] = {H->pts64,    H->order,    H->keys,     H->nbpre,    H->nbsum,     H->xs64,

@@ -247,7 +247,8 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
                                             const typename M2LTypes<MODE>::C *pcs, int64_t npivs,
                                             const int32_t *piv_ptr_s,
                                             const int32_t *coord, const float *hc, float h0, int d,
-                                            const double *w, double *u, double *part_out, double prm64)
+                                            const double *w, double *u, double *part_out, double prm64,
+                                            const int32_t *corder, int64_t slots)
 {
     using T = typename M2LTypes<MODE>::C;
     using T4 = typename M2LTypes<MODE>::V;
@@ -261,8 +262,17 @@ __global__ __launch_bounds__(NT) void k_m2l(int64_t nc, int P, const int32_t *k,
     __shared__ int32_t est[ET + 1], ebase[ET];
     __shared__ float esh[3][ET];
     const int t = threadIdx.x;
-    const int64_t c = blockIdx.x / P;
-    const int pp = blockIdx.x % P;
+    int64_t c;
+    int pp;
+    if (corder) {   // slot q / P of XCD x's run, part q % P
+        const int64_t q = blockIdx.x >> 3;
+        c = corder[(blockIdx.x & 7) * slots + q / P];
+        pp = (int)(q % P);
+        if (c < 0) return;   // padding slot (uniform exit)
+    } else {
+        c = blockIdx.x / P;
+        pp = blockIdx.x % P;
+    }
     const int32_t kk = k[c], po = piv_ptr[c], S = ilsum[c];
     const int32_t sb = (int32_t)(((int64_t)S * pp) / P), se = (int32_t)(((int64_t)S * (pp + 1)) / P);
     const int32_t e0 = il_ptr[c], e1 = il_ptr[c + 1];
@@ -1048,8 +1058,8 @@ static void launch_m2l_pair(int kind, nnca_h2 *H, const nnca::Level &L, const nn
         if (H->m2l_part_cap < (int64_t)P * L.npiv) fail(NNCA_ERR_INTERNAL, "split workspace not sized");
         part = H->m2l_part;
     }
-    const int g = (int)(nc * P);
-#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, pcs, S.npiv, S.piv_ptr, L.coord, L.hcell, (float)L.h, H->dim, S.w64, L.u64, part, prm
+    const int g = L.m2l_order ? (int)(8 * L.m2l_slots * P) : (int)(nc * P);
+#define M2L_ARGS nc, P, L.k, L.piv_ptr, L.il_ptr, L.il, L.ilpre, L.ilsum, pc, L.npiv, pcs, S.npiv, S.piv_ptr, L.coord, L.hcell, (float)L.h, H->dim, S.w64, L.u64, part, prm, L.m2l_order, L.m2l_slots
 #define M2L_CASE(K) k_m2l<K, MODE, M2L_TILE><<<g, NT, 0, s>>>(M2L_ARGS);
     if (kind == NNCA_K_INV_R) { M2L_CASE(NNCA_K_INV_R) }
     else if (kind == NNCA_K_LOG_R) { M2L_CASE(NNCA_K_LOG_R) }
@@ -1590,6 +1600,70 @@ void column_passes(nnca_h2 *H, int precision, int kind, bool do_up, bool do_p2p,
 // The column slots are one FP64 buffer: the FP64 and FP64-refined forms use
 // it as FP64 slots, the FP32 form (levels of the mixed matvec that run in
 // FP32) as FP32 slots.
+// Launch order of a level's cells.  Workgroups are dispatched to the eight
+// XCDs round robin (workgroup b to XCD b mod 8), each with its own L2: XCD x
+// gets the x-th of eight runs of the cells in tree (Morton) order holding
+// equal work, so the sources it reads come from one compact region (about an
+// eighth of the level's pivot data); inside a run the cells go largest work
+// first, so the last wave of the launch holds the shortest workgroups.
+// Cells without work follow, dealt to the runs round robin (in a general
+// product the target cells outside the source set's region are many and
+// contiguous in tree order: in one run they would lengthen the grid by their
+// count of empty slots; 8.9 against 7.3 ms for the transposed product of
+// 2^19 shifted targets and 2^20 sources).  Runs are padded to equal length
+// with empty slots (-1) and appended to `ord`; returns the run length (0 when
+// no cell has in[c] set).
+static int64_t xcd_runs(const std::vector<int64_t> &wk, const std::vector<char> &in, std::vector<int32_t> &ord)
+{
+    const int64_t nc = (int64_t)wk.size();
+    int64_t wtot = 0, cnt = 0;
+    for (int64_t c = 0; c < nc; c++)
+        if (in[c] && wk[c] > 0) {
+            wtot += wk[c];
+            cnt++;
+        }
+    std::vector<std::vector<int32_t>> ch(8);
+    int64_t cum = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        if (!in[c] || wk[c] == 0) continue;
+        int x = (int)((cum * 8) / wtot);
+        if (x > 7) x = 7;
+        ch[x].push_back((int32_t)c);
+        cum += wk[c];
+    }
+    for (auto &v : ch) std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return wk[a] > wk[b]; });
+    // cells without work (rows to clear only) go last, dealt round robin,
+    // so that they do not lengthen one run (and the grid) by themselves
+    int64_t z = 0;
+    for (int64_t c = 0; c < nc; c++)
+        if (in[c] && wk[c] == 0) ch[(z++) % 8].push_back((int32_t)c);
+    if (cnt + z == 0) return 0;
+    size_t ms = 1;
+    for (auto &v : ch) ms = std::max(ms, v.size());
+    const size_t base = ord.size();
+    ord.resize(base + 8 * ms, -1);
+    for (int x = 0; x < 8; x++)
+        for (size_t i = 0; i < ch[x].size(); i++) ord[base + x * ms + i] = ch[x][i];
+    return (int64_t)ms;
+}
+
+// the plain transverse pass's order: work = rank x sources of the list
+static void plain_order(Level &L, const std::vector<int32_t> &ils)
+{
+    const int64_t nc = L.ncell;
+    std::vector<int64_t> wk(nc);
+    std::vector<char> in(nc);
+    for (int64_t c = 0; c < nc; c++) {
+        wk[c] = (int64_t)L.h_k[c] * ils[c];
+        in[c] = 1;   // every cell keeps its slot (its rows are written even without sources)
+    }
+    std::vector<int32_t> ord;
+    L.m2l_slots = xcd_runs(wk, in, ord);
+    if (ord.empty()) ord.push_back(-1);
+    L.m2l_order = dalloc<int32_t>(ord.size());
+    HIPCHECK(hipMemcpy(L.m2l_order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice));
+}
+
 void prepare_symmetric(nnca_h2 *H, Level &L, bool)
 {
     if (L.sym || L.ncell < 1 || L.max_k > SYM_MAXK) return;
@@ -1644,17 +1718,10 @@ void prepare_symmetric(nnca_h2 *H, Level &L, bool)
     L.own_slot = up(oslot);
     L.non_ptr = up(nptr);
     L.non_slot = up(nslot);
-    // launch order.  Workgroups are dispatched to the eight XCDs round
-    // robin (workgroup b to XCD b mod 8), each with its own L2: XCD x gets
-    // the x-th of eight runs of cells in tree (Morton) order holding equal
-    // owned work (rank x owned sources), so the sources it reads come from
-    // one compact region (about an eighth of a level's pivot data).  Inside
-    // a run the cells go largest work first, so the last wave of the launch
-    // holds the shortest workgroups.  Runs are padded to equal length with
-    // empty slots (-1).  c2 per launch: leaf 0.79 ms, level kappa-1 0.74 ms;
-    // 0.87 and 0.80 in plain cell order; 0.81 and 0.75 with the largest-
-    // first order over the whole level; 0.83 and 0.75 with the runs in tree
-    // order.
+    // launch order (xcd_runs).  c2 per launch: leaf 0.79 ms, level kappa-1
+    // 0.74 ms; 0.87 and 0.80 in plain cell order; 0.81 and 0.75 with the
+    // largest-first order over the whole level; 0.83 and 0.75 with the runs
+    // in tree order.
     //
     // Rank classes.  A launch's shape set follows the largest rank it
     // holds, and the sets for ranks above 80 take more registers per lane
@@ -1668,42 +1735,16 @@ void prepare_symmetric(nnca_h2 *H, Level &L, bool)
     int64_t nhi = 0;
     for (int64_t c = 0; c < nc; c++) nhi += kh[c] > 80;
     const bool split = L.max_k > 80 && nhi > 0 && 4 * nhi <= nc;
+    std::vector<int64_t> wk(nc);
+    std::vector<char> in0(nc), in1(nc);
+    for (int64_t c = 0; c < nc; c++) {
+        wk[c] = (int64_t)kh[c] * osum[c];
+        in0[c] = kh[c] > 0 && (!split || kh[c] <= 80);
+        in1[c] = kh[c] > 80 && split;
+    }
     std::vector<int32_t> ord;
-    auto runs = [&](int cls) -> int64_t {
-        std::vector<int64_t> wk(nc, 0);
-        int64_t wtot = 0, cnt = 0;
-        for (int64_t c = 0; c < nc; c++) {
-            const bool in = kh[c] > 0 && (!split || (cls == 0 ? kh[c] <= 80 : kh[c] > 80));
-            if (!in) continue;
-            wk[c] = (int64_t)kh[c] * osum[c];
-            wtot += wk[c];
-            cnt++;
-        }
-        if (cnt == 0) return 0;
-        std::vector<std::vector<int32_t>> ch(8);
-        int64_t cum = 0, seen = 0;
-        for (int64_t c = 0; c < nc; c++) {
-            const bool in = kh[c] > 0 && (!split || (cls == 0 ? kh[c] <= 80 : kh[c] > 80));
-            if (!in) continue;
-            int x = wtot > 0 ? (int)((cum * 8) / (wtot + 1)) : (int)((seen * 8) / cnt);
-            if (x > 7) x = 7;
-            ch[x].push_back((int32_t)c);
-            cum += wk[c];
-            seen++;
-        }
-        size_t ms = 1;
-        for (auto &v : ch) {
-            std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return wk[a] > wk[b]; });
-            ms = std::max(ms, v.size());
-        }
-        const size_t base = ord.size();
-        ord.resize(base + 8 * ms, -1);
-        for (int x = 0; x < 8; x++)
-            for (size_t i = 0; i < ch[x].size(); i++) ord[base + x * ms + i] = ch[x][i];
-        return (int64_t)ms;
-    };
-    L.sym_slots = runs(0);
-    L.sym_slots_hi = split ? runs(1) : 0;
+    L.sym_slots = xcd_runs(wk, in0, ord);
+    L.sym_slots_hi = split ? xcd_runs(wk, in1, ord) : 0;
     if (ord.empty()) ord.push_back(-1);
     L.sym_order = up(ord);
     L.col64 = dalloc<double>(col);
@@ -1825,6 +1866,7 @@ void prepare_apply(nnca_h2 *H)
             L.m2l_inter += (int64_t)L.h_k[c] * ils[c];
             L.max_ilsum = std::max(L.max_ilsum, ils[c]);
         }
+        plain_order(L, ils);
         m2l += L.m2l_inter;
         trans += L.ncrem;
     }
@@ -2010,6 +2052,7 @@ void prepare_half(nnca_h2 *H, std::vector<Level> &lv, const std::vector<Level> &
             L.m2l_inter += (int64_t)L.h_k[c] * ils[c];
             L.max_ilsum = std::max(L.max_ilsum, ils[c]);
         }
+        plain_order(L, ils);
         m2l += L.m2l_inter;
         trans += L.ncrem;
     }

@@ -106,6 +106,8 @@ struct Level {
     int32_t *non_ptr = nullptr, *non_slot = nullptr;   // per cell: slots of the pairs it does not own
     int32_t *sym_order = nullptr;    // launch order: 8 runs (one per XCD) of sym_slots cells, -1 = empty,
     int64_t sym_slots = 0, sym_slots_hi = 0;   // then 8 runs of sym_slots_hi cells of rank > 80 (if split)
+    int32_t *m2l_order = nullptr;    // launch order of the plain transverse pass: 8 runs of m2l_slots cells
+    int64_t m2l_slots = 0;
     float *col32 = nullptr;          // column slots, FP32 (FP32 form) or
     double *col64 = nullptr;         //   FP64 (FP64-refined form)
     int64_t ncol = 0;
