@@ -8,7 +8,6 @@
 // found from the sorted keys: points i and i+nu share a cell exactly down to
 // the level given by the common prefix of their keys.
 #include <cstring>
-#include <rocprim/rocprim.hpp>
 
 #include "nnca_internal.h"
 
@@ -294,21 +293,216 @@ __global__ void k_lists(int which, int l, int d, int64_t nc, const int32_t *coor
     }
 }
 
+// Prefix sums.  The values are integers, so the sums are exact in any
+// order.  Blocks of SC_NT threads scan tiles of SC_TILE elements (SC_IPT
+// consecutive elements per thread), one block scans the tile totals, and the
+// totals' prefixes are added to the tiles.
+constexpr int SC_NT = 256, SC_IPT = 8, SC_TILE = SC_NT * SC_IPT;
+
+// exclusive scan of one value per thread over the block; *total = the sum
+template <typename T>
+__device__ T block_excl_scan(T v, T *sh, T &total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < SC_NT; o <<= 1) {
+        const T x = t >= o ? sh[t - o] : T(0);
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    total = sh[SC_NT - 1];
+    const T r = sh[t] - v;
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SC_NT) void k_scan_tiles(const T *in, T *out, int64_t n, T *tile_sum, int inclusive)
+{
+    __shared__ T sh[SC_NT];
+    const int t = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * SC_TILE + (int64_t)t * SC_IPT;
+    T v[SC_IPT], sum = T(0);
+#pragma unroll
+    for (int i = 0; i < SC_IPT; i++) {
+        v[i] = b0 + i < n ? in[b0 + i] : T(0);
+        sum += v[i];
+    }
+    T tot;
+    T run = block_excl_scan(sum, sh, tot);
+#pragma unroll
+    for (int i = 0; i < SC_IPT; i++) {
+        if (b0 + i < n) out[b0 + i] = inclusive ? run + v[i] : run;
+        run += v[i];
+    }
+    if (t == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// exclusive scan of the nt tile totals, in place, by one block
+template <typename T>
+__global__ __launch_bounds__(SC_NT) void k_scan_sums(T *sum, int64_t nt)
+{
+    __shared__ T sh[SC_NT];
+    T carry = T(0);
+    for (int64_t c0 = 0; c0 < nt; c0 += SC_NT) {
+        const int64_t g = c0 + threadIdx.x;
+        const T v = g < nt ? sum[g] : T(0);
+        T tot;
+        const T pre = block_excl_scan(v, sh, tot);
+        if (g < nt) sum[g] = carry + pre;
+        carry += tot;
+    }
+}
+
+template <typename T>
+__global__ void k_scan_add(T *out, int64_t n, const T *tile_off)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g < n) out[g] += tile_off[g / SC_TILE];
+}
+
 template <typename T>
 void scan(const T *in, T *out, int64_t n, bool inclusive, hipStream_t s)
 {
-    size_t bytes = 0;
-    if (inclusive)
-        HIPCHECK(rocprim::inclusive_scan(nullptr, bytes, in, out, (size_t)n, rocprim::plus<T>(), s));
-    else
-        HIPCHECK(rocprim::exclusive_scan(nullptr, bytes, in, out, T(0), (size_t)n, rocprim::plus<T>(), s));
-    void *tmp = dalloc<char>(bytes + 16);
-    if (inclusive)
-        HIPCHECK(rocprim::inclusive_scan(tmp, bytes, in, out, (size_t)n, rocprim::plus<T>(), s));
-    else
-        HIPCHECK(rocprim::exclusive_scan(tmp, bytes, in, out, T(0), (size_t)n, rocprim::plus<T>(), s));
-    HIPCHECK(hipStreamSynchronize(s));
-    dfree(tmp);
+    if (n <= 0) return;
+    const int64_t nt = (n + SC_TILE - 1) / SC_TILE;
+    if (nt > INT32_MAX) fail(NNCA_ERR_NOT_SUPPORTED, "scan too long");
+    T *tsum = dalloc<T>(nt);
+    try {
+        k_scan_tiles<T><<<(unsigned)nt, SC_NT, 0, s>>>(in, out, n, tsum, inclusive ? 1 : 0);
+        HIPCHECK(hipGetLastError());
+        if (nt > 1) {
+            k_scan_sums<T><<<1, SC_NT, 0, s>>>(tsum, nt);
+            HIPCHECK(hipGetLastError());
+            k_scan_add<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n, tsum);
+            HIPCHECK(hipGetLastError());
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        dfree(tsum);
+        throw;
+    }
+    dfree(tsum);
+}
+
+// Stable LSD radix sort of (64-bit key, 32-bit value) pairs on key bits
+// [0, bits), eight bits per pass.  Per pass: each block counts the digits of
+// its tile of RS_TILE pairs; an exclusive scan of the counts laid out digit
+// by digit, block by block, gives every (digit, block) its first output
+// position; each block then writes its tile in index order, 256 pairs at a
+// time, a pair's place among equal digits of its wavefront from the lanes
+// below it (ballots on the eight digit bits), after those of the
+// wavefronts below and of the earlier chunks.  Equal keys keep their input
+// order, so input in index order sorts by (key, index).
+constexpr int RS_NT = 256, RS_IPT = 16, RS_TILE = RS_NT * RS_IPT, RS_WAVES = RS_NT / 64;
+
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t *key, int64_t n, int shift, int32_t *hist,
+                                                   int64_t nb)
+{
+    __shared__ int32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t tb = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = 0; i < RS_IPT; i++) {
+        const int64_t g = tb + (int64_t)i * RS_NT + t;
+        if (g < n) atomicAdd(&h[(int)((key[g] >> shift) & 255u)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)t * nb + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout,
+                                                      int32_t *vout, int64_t n, int shift, const int32_t *off,
+                                                      int64_t nb)
+{
+    __shared__ int32_t base[256];
+    __shared__ int32_t wcnt[RS_WAVES][256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    base[t] = off[(int64_t)t * nb + blockIdx.x];
+    for (int q = 0; q < RS_WAVES; q++) wcnt[q][t] = 0;
+    __syncthreads();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t tb = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = 0; i < RS_IPT; i++) {
+        const int64_t g = tb + (int64_t)i * RS_NT + t;
+        const bool ok = g < n;
+        const uint64_t k = ok ? kin[g] : 0ull;
+        const int32_t v = ok ? vin[g] : 0;
+        const int dg = (int)((k >> shift) & 255u);
+        uint64_t m = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = ((dg >> b) & 1) != 0;
+            const uint64_t bb = __ballot(ok && bit);
+            m &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(m & below);
+        if (ok && rank == 0) wcnt[w][dg] = __popcll(m);
+        __syncthreads();
+        if (ok) {
+            int32_t pos = base[dg] + rank;
+            for (int q = 0; q < w; q++) pos += wcnt[q][dg];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        int32_t c = 0;
+        for (int q = 0; q < RS_WAVES; q++) {
+            c += wcnt[q][t];
+            wcnt[q][t] = 0;
+        }
+        base[t] += c;
+        __syncthreads();
+    }
+}
+
+// sorts (k_in, v_in) into (k_out, v_out); k_in and v_in are overwritten
+void radix_sort_pairs(uint64_t *k_in, int32_t *v_in, uint64_t *k_out, int32_t *v_out, int64_t n, int bits,
+                      hipStream_t s)
+{
+    if (n <= 0) return;
+    if (n > INT32_MAX) fail(NNCA_ERR_NOT_SUPPORTED, "sort too long");
+    const int passes = (bits + 7) / 8;
+    if (passes == 0) {
+        HIPCHECK(hipMemcpyAsync(k_out, k_in, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHECK(hipMemcpyAsync(v_out, v_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        return;
+    }
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    int32_t *hist = dalloc<int32_t>(256 * nb);
+    uint64_t *kt = passes > 1 ? dalloc<uint64_t>(n) : nullptr;
+    int32_t *vt = passes > 1 ? dalloc<int32_t>(n) : nullptr;
+    auto release = [&] {
+        dfree(hist);
+        dfree(kt);
+        dfree(vt);
+    };
+    try {
+        uint64_t *ks = k_in;
+        int32_t *vs = v_in;
+        for (int p = 0; p < passes; p++) {
+            uint64_t *kd = p == passes - 1 ? k_out : (ks == k_in ? kt : k_in);
+            int32_t *vd = p == passes - 1 ? v_out : (vs == v_in ? vt : v_in);
+            k_rs_hist<<<(unsigned)nb, RS_NT, 0, s>>>(ks, n, 8 * p, hist, nb);
+            HIPCHECK(hipGetLastError());
+            scan<int32_t>(hist, hist, 256 * nb, false, s);
+            k_rs_scatter<<<(unsigned)nb, RS_NT, 0, s>>>(ks, vs, kd, vd, n, 8 * p, hist, nb);
+            HIPCHECK(hipGetLastError());
+            ks = kd;
+            vs = vd;
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        release();
+        throw;
+    }
+    release();
 }
 
 }  // namespace
@@ -414,12 +608,7 @@ void build_tree(nnca_h2 *H, const double *pin, int64_t ld, int64_t split)
     H->order = dalloc<int32_t>(n);
     k_keys<<<grid_for(n, 256), 256, 0, s>>>(pin, n, d, ld, H->lo[0], H->lo[1], H->lo[2], H->L, H->kmax, k_in, i_in);
     HIPCHECK(hipGetLastError());
-    size_t bytes = 0;
-    HIPCHECK(rocprim::radix_sort_pairs(nullptr, bytes, k_in, H->keys, i_in, H->order, (size_t)n, 0, d * H->kmax, s));
-    void *tmp = dalloc<char>(bytes + 16);
-    HIPCHECK(rocprim::radix_sort_pairs(tmp, bytes, k_in, H->keys, i_in, H->order, (size_t)n, 0, d * H->kmax, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    dfree(tmp);
+    radix_sort_pairs(k_in, i_in, H->keys, H->order, n, d * H->kmax, s);
     dfree(k_in);
     dfree(i_in);
 
