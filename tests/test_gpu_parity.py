@@ -343,7 +343,8 @@ def test_rank_cap_retry_and_chunking(orc):
 
 
 @pytest.mark.parametrize("name,R", [("cube3d", 5), ("cube3d", 37), ("sphere", 64), ("mixture", 16), ("c1", 20),
-                                    ("literal_sqrt2", 33), ("c2_64k", 16)])
+                                    ("literal_sqrt2", 33), ("c2_64k", 16), ("svm2d_expr", 12),
+                                    ("cluster_split", 8)])
 def test_many_rhs_parity(built, name, R):
     # The block path (columns innermost, MFMA for the FP32 transverse pass)
     # against the oracle and against one column at a time.
