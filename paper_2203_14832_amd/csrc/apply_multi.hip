@@ -330,7 +330,12 @@ __device__ inline int32_t list_entry(const int32_t *pre, int32_t e0, int32_t e1,
 // transfer-pass launches with fewer items than this take the four-wavefront
 // kernels
 constexpr unsigned SPLIT_BELOW = 2048;
-constexpr int MET = 256;   // interaction-list entries staged in LDS at a time
+// interaction-list entries staged in LDS at a time.  128 with the row stride
+// RP + 4 below keeps the 64-column transverse kernel under 40 KB of LDS, so
+// four workgroups (four waves per SIMD) fit on a CU: c3 (64 columns) 4.03
+// against 4.21 ms per block matvec with 256 entries and stride RP + 16
+// (48.6 KB, three workgroups); c5 unchanged
+constexpr int MET = 128;
 
 __global__ void k_to_f32(int64_t cnt, const double *a, float *b)
 {
@@ -357,7 +362,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
     constexpr int TB = NCB <= 2 ? 2 : 1;             // target blocks per wavefront
     constexpr int TS = (NCB == 1 ? 256 : 128) >> TSEL;   // sources per LDS tile
     static_assert(TS % 64 == 0 && TS <= NT, "the tile pads to a multiple of 64 sources, one per thread");
-    constexpr int SW = (NCB & 1) ? RP : RP + 16;   // LDS row stride: the four source rows of a step in distinct banks
+    constexpr int SW = (NCB & 1) ? RP : RP + 4;   // LDS row stride (even widths padded by four)
     constexpr int RED = NT * NCB * 4 * TB;           // doubles of the phase reduction
     __shared__ float4 sx[TS];
     __shared__ int32_t sidx[TS];
