@@ -661,7 +661,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // v_mfma_f32_16x16x4f32 (partial sums folded into FP64 every 16 sources);
 // T = double uses v_mfma_f64_16x16x4f64.
 template <typename T, int KIND, int NCB>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 2))) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6 : 4))) void k_p2p_mfma(int64_t nc, const int32_t *first, const int32_t *count,
                                                  const int32_t *nb_ptr, const int32_t *nb, const int32_t *nbpre,
                                                  const int32_t *nbsum, const double *pts, int64_t n, int d,
                                                  const T *xw, const T *xw2, const double *far, double *yt, int R,
@@ -671,7 +671,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NCB == 1 ? 6
     constexpr int TS = 64;
     constexpr bool mixed = sizeof(T) == 4;
     static_assert(TS == 64 && TS <= NT, "every step index stays inside one 64-source tile");
-    constexpr int SW = (mixed && !(NCB & 1)) ? RP + 16 : RP;   // LDS row stride (bank spread)
+    // LDS row stride (bank spread); with RP + 4 the 64-column mixed form
+    // stays under 40 KB and, bounded to 128 VGPRs (four waves per EU, no
+    // spills), runs four waves per SIMD: c3 near field 0.132 against 0.113
+    // of the FP32 matrix peak (RP + 16, three waves)
+    constexpr int SW = (mixed && !(NCB & 1)) ? RP + 4 : RP;
     // the weight tiles and, after the tile loop, the phase reduction share
     // one LDS buffer
     constexpr int WBYTES = (int)sizeof(T) * TS * SW * (mixed ? 2 : 1);
